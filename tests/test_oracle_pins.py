@@ -1,0 +1,345 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+quadrature of the kernels, closed-form limits, the Gauss lemma, the jump
+relation, exact polynomial rules, harmonic reproduction and invariances.
+
+Each pin is chosen so that a plausible slip in the oracle (a dropped term, a
+sign, a transposed index, a wrong normal) fails at least one of them.
+"""
+import numpy as np
+import pytest
+import mpmath as mp
+
+import oracle
+import scenegen
+
+rng_global = np.random.default_rng(12345)
+
+
+# --------------------------------------------------------------------------
+# Gauss-Legendre rule and interpolation matrix (Sec. 4.3, 5.2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [4, 8, 16])
+def test_gauss_legendre_exact_for_polynomials(g):
+    x, w = oracle.gauss_legendre(g)
+    assert abs(w.sum() - 2.0) < 1e-14
+    for k in range(2 * g):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.sum(w * x ** k) - exact) < 1e-13
+
+
+def _lagrange_matrix(g, s):
+    """Lagrange basis of the GL roots at the segment midpoints, built from
+    products (independent of the Legendre-polynomial route)."""
+    x = np.array([float(r) for r in mp.polyroots(
+        [c for c in reversed(np.polynomial.legendre.leg2poly(np.eye(g + 1)[g]))],
+        maxsteps=200, extraprec=200)])
+    x = np.sort(x)
+    tb = -1.0 + (2.0 * np.arange(s) + 1.0) / s
+    L = np.ones((s, g))
+    for i in range(g):
+        for m in range(g):
+            if m != i:
+                L[:, i] *= (tb - x[m]) / (x[i] - x[m])
+    return L
+
+
+@pytest.mark.parametrize("g,s", [(4, 20), (8, 40), (16, 80)])
+def test_interp_matrix_is_lagrange_and_reproduces_polynomials(g, s):
+    Pi = oracle.interp_matrix(g, s)
+    assert Pi.shape == (s, g)
+    np.testing.assert_allclose(Pi, _lagrange_matrix(g, s), atol=1e-12)
+    np.testing.assert_allclose(Pi.sum(axis=1), 1.0, atol=1e-13)
+    x, _ = oracle.gauss_legendre(g)
+    tb = -1.0 + (2.0 * np.arange(s) + 1.0) / s
+    for deg in range(g):
+        coef = rng_global.normal(size=deg + 1)
+        np.testing.assert_allclose(Pi @ np.polyval(coef, x), np.polyval(coef, tb),
+                                   atol=1e-11 * max(1.0, np.abs(coef).sum()))
+
+
+# --------------------------------------------------------------------------
+# Arc length (App. B)
+# --------------------------------------------------------------------------
+def test_arc_length_of_straight_bezier_is_exact():
+    a = np.array([0.1, 0.2])
+    b = np.array([0.7, -0.4])
+    ctrl = np.array([a, a + (b - a) / 3, a + 2 * (b - a) / 3, b])
+    L = oracle.curve_length(ctrl)
+    assert abs(L - np.hypot(*(b - a))) < 1e-14
+    lam = np.linspace(0.0, 1.0, 17)
+    t = oracle.arclength_to_param(ctrl, lam * L, L)
+    np.testing.assert_allclose(t, lam, atol=1e-13)
+
+
+def _polyline_length(ctrl, n):
+    pts = oracle.bezier_point(ctrl, np.linspace(0.0, 1.0, n + 1))
+    return np.sum(np.hypot(*(pts[1:] - pts[:-1]).T))
+
+
+def test_arc_length_matches_richardson_polyline():
+    ctrl = np.array([[0.0, 0.0], [0.3, 0.9], [0.8, -0.2], [1.0, 0.5]])
+    L1 = _polyline_length(ctrl, 20000)
+    L2 = _polyline_length(ctrl, 40000)
+    rich = (4.0 * L2 - L1) / 3.0          # chord sums converge as O(1/n^2)
+    assert abs(oracle.curve_length(ctrl) - rich) < 1e-11
+    assert abs(oracle.curve_length(2.5 * ctrl) - 2.5 * oracle.curve_length(ctrl)) < 1e-13
+
+
+def test_arc_length_inverse_hits_targets():
+    ctrl = np.array([[0.0, 0.0], [0.1, 0.9], [0.9, 0.9], [1.0, 0.0]])
+    L = oracle.curve_length(ctrl)
+    T = np.linspace(0.0, L, 33)
+    t = oracle.arclength_to_param(ctrl, T, L)
+    for tk, Tk in zip(t[1:], T[1:]):
+        # independent check with mpmath quadrature of |B'|
+        sp = lambda u: mp.sqrt(sum((3 * ((1 - u) ** 2 * (ctrl[1, d] - ctrl[0, d])
+                                         + 2 * u * (1 - u) * (ctrl[2, d] - ctrl[1, d])
+                                         + u ** 2 * (ctrl[3, d] - ctrl[2, d]))) ** 2
+                                   for d in range(2)))
+        assert abs(float(mp.quad(sp, [0, tk])) - Tk) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Closed-form chord integrals vs quadrature of the kernels (App. D)
+# --------------------------------------------------------------------------
+def _quad_chord(x, p1, p2):
+    """mpmath quadrature of G and F (Eq. green_G, Eq. green_F) along the
+    chord, split at the foot point so near-chord targets resolve."""
+    mp.mp.dps = 40
+    p1m = [mp.mpf(v) for v in p1]
+    p2m = [mp.mpf(v) for v in p2]
+    xm = [mp.mpf(v) for v in x]
+    a = [p2m[0] - p1m[0], p2m[1] - p1m[1]]
+    la = mp.sqrt(a[0] ** 2 + a[1] ** 2)
+    n = [-a[1] / la, a[0] / la]
+
+    def pt(s):
+        return [p1m[0] + s * a[0] / la, p1m[1] + s * a[1] / la]
+
+    def g(s):
+        p = pt(s)
+        return -mp.log(mp.sqrt((p[0] - xm[0]) ** 2 + (p[1] - xm[1]) ** 2)) / (2 * mp.pi)
+
+    def f(s):
+        p = pt(s)
+        d0, d1 = p[0] - xm[0], p[1] - xm[1]
+        return -(d0 * n[0] + d1 * n[1]) / (2 * mp.pi * (d0 ** 2 + d1 ** 2))
+
+    foot = ((xm[0] - p1m[0]) * a[0] + (xm[1] - p1m[1]) * a[1]) / la
+    pts = [0, la]
+    if 0 < foot < la:
+        hh = abs((xm[0] - p1m[0]) * n[0] + (xm[1] - p1m[1]) * n[1])
+        pts = sorted({mp.mpf(0), la, foot,
+                      max(mp.mpf(0), foot - 50 * hh), min(la, foot + 50 * hh)})
+    G = mp.quad(g, pts, maxdegree=12)
+    F = mp.quad(f, pts, maxdegree=12)
+    mp.mp.dps = 15
+    return float(G), float(F)
+
+
+def test_chord_integrals_far_and_moderate_targets():
+    rng = np.random.default_rng(7)
+    for _ in range(12):
+        p1, p2 = rng.uniform(-1, 1, 2), rng.uniform(-1, 1, 2)
+        x = rng.uniform(-2, 2, 2)
+        G, F = oracle.chord_integrals(x[0], x[1], p1, p2)
+        Gq, Fq = _quad_chord(x, p1, p2)
+        assert abs(G - Gq) <= 1e-13 * max(1.0, abs(Gq))
+        assert abs(F - Fq) <= 1e-13 * max(1.0, abs(Fq))
+
+
+@pytest.mark.parametrize("hrel", [1e-3, 1e-6, 1e-9, 1e-12])
+@pytest.mark.parametrize("side", [1.0, -1.0])
+def test_chord_integrals_near_chord(hrel, side):
+    p1 = np.array([0.2, 0.1])
+    p2 = np.array([0.9, 0.5])
+    la = np.hypot(*(p2 - p1))
+    t = (p2 - p1) / la
+    n = np.array([-t[1], t[0]])
+    x = p1 + 0.37 * (p2 - p1) + side * hrel * la * n
+    G, F = oracle.chord_integrals(x[0], x[1], p1, p2)
+    Gq, Fq = _quad_chord(x, p1, p2)
+    assert abs(G - Gq) <= 1e-13 * max(1.0, abs(Gq))
+    assert abs(F - Fq) <= 1e-12 * max(1.0, abs(Fq))
+
+
+def test_single_layer_singular_limit_matches_appendix_d3():
+    """h -> 0 inside the chord gives (1/2pi)(s - e1 ln e1 - e2 ln e2)."""
+    p1 = np.array([0.0, 0.0])
+    p2 = np.array([0.3, 0.4])          # |a| = 0.5
+    for tstar in (0.1, 0.5, 0.77):
+        x = p1 + tstar * (p2 - p1)
+        e1, e2 = 0.5 * tstar, 0.5 * (1 - tstar)
+        ref = (0.5 - e1 * np.log(e1) - e2 * np.log(e2)) / (2 * np.pi)
+        for h in (1e-10, -1e-10, 1e-14, 0.0):
+            xx = x + h * np.array([-0.8, 0.6])
+            G, F = oracle.chord_integrals(xx[0], xx[1], p1, p2)
+            # G(h) = G(0) - |h|/2 + O(h^2 ln h): the limit is approached linearly
+            assert abs(G - (ref - 0.5 * abs(h))) < 1e-14
+        # exactly on the chord the double layer takes its principal value 0
+        # (an axis-aligned chord makes h exactly zero)
+        assert oracle.chord_integrals(0.5 * tstar, 0.0, p1, np.array([0.5, 0.0]))[1] == 0.0
+        assert abs(oracle.self_segment_G(0.5, tstar) - ref) < 1e-15
+
+
+def test_endpoint_target_is_finite():
+    G, F = oracle.chord_integrals(0.0, 0.0, np.array([0.0, 0.0]), np.array([1.0, 0.0]))
+    assert abs(G - 1.0 / (2 * np.pi)) < 1e-15      # -(1/2pi)(1*ln1 - 0 - 1)
+    assert np.isfinite(F)
+
+
+# --------------------------------------------------------------------------
+# Gauss lemma and jump relation (Sec. 5.3, App. C)
+# --------------------------------------------------------------------------
+def _polygon_double_layer(verts, pts):
+    ctrl = scenegen.polygon_ctrl(verts)
+    total = np.zeros(len(pts))
+    for c in ctrl:
+        _, F = oracle.chord_integrals(pts[:, 0], pts[:, 1], c[0], c[3])
+        total += F
+    return total
+
+
+def test_gauss_lemma_left_normal():
+    """Constant double layer of a closed polygon with the left normal: +1
+    inside a counter-clockwise curve, 0 outside, -1 inside a clockwise one."""
+    verts = np.array([[0.1, 0.1], [0.8, 0.2], [0.9, 0.7], [0.4, 0.9], [0.2, 0.6]])
+    inside = np.array([[0.5, 0.5], [0.3, 0.3], [0.7, 0.6]])
+    outside = np.array([[0.0, 0.0], [1.0, 1.0], [0.95, 0.1], [0.5, 1.2]])
+    np.testing.assert_allclose(_polygon_double_layer(verts, inside), 1.0, atol=1e-13)
+    np.testing.assert_allclose(_polygon_double_layer(verts, outside), 0.0, atol=1e-13)
+    np.testing.assert_allclose(_polygon_double_layer(verts[::-1], inside), -1.0,
+                               atol=1e-13)
+
+
+def test_jump_across_open_chord():
+    p1 = np.array([0.1, 0.3])
+    p2 = np.array([0.6, 0.5])
+    la = np.hypot(*(p2 - p1))
+    t = (p2 - p1) / la
+    n = np.array([-t[1], t[0]])
+    x = p1 + 0.4 * (p2 - p1)
+    for d in (1e-6, 1e-10, 1e-13):
+        up = oracle.chord_integrals(*(x + d * n), p1, p2)[1]
+        dn = oracle.chord_integrals(*(x - d * n), p1, p2)[1]
+        assert abs((up - dn) - 1.0) < 5.0 * d + 1e-12   # deficit is O(d / distance to ends)
+        # the single layer is continuous across the chord
+        assert abs(oracle.chord_integrals(*(x + d * n), p1, p2)[0]
+                   - oracle.chord_integrals(*(x - d * n), p1, p2)[0]) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Harmonic reproduction: the whole solve + evaluate chain (Sec. 5.2, 5.3)
+# --------------------------------------------------------------------------
+def _ring_points(c, radius, n=24):
+    a = np.linspace(0, 2 * np.pi, n, endpoint=False) + 0.1
+    return c + radius * np.stack([np.cos(a), np.sin(a)], axis=1)
+
+
+def _reproduction_errors(panels, gl, segs):
+    c = np.array([0.5, 0.5])
+    ctrl = scenegen.circle_ctrl(c[0], c[1], 0.3, n_arcs=4, ccw=True)
+    disc = oracle.discretize(ctrl, panels, gl, segs)
+    q = disc.node_xy
+    f_in = (q[:, 0] - c[0]) ** 2 - (q[:, 1] - c[1]) ** 2
+    f_out = np.log(np.hypot(q[:, 0] - c[0], q[:, 1] - c[1]))
+    # channel 0: mu = 0 (inside/outside both f_in); channel 1: two-sided data
+    # (left side = inside of the ccw curve gets f_in, right side gets f_out);
+    # channel 2: the sides swapped on a constant pair.
+    up = np.stack([f_in, f_in, np.full_like(f_in, 0.25)])
+    um = np.stack([f_in, f_out, np.full_like(f_in, 0.75)])
+    sigma, mu = oracle.solve(disc, up, um)
+    pin = np.concatenate([_ring_points(c, 0.12), _ring_points(c, 0.2), c[None]])
+    pout = np.concatenate([_ring_points(c, 0.45), _ring_points(c, 0.7)])
+    uin = oracle.evaluate(disc, sigma, mu, pin)
+    uout = oracle.evaluate(disc, sigma, mu, pout)
+    fin = (pin[:, 0] - c[0]) ** 2 - (pin[:, 1] - c[1]) ** 2
+    fo = np.log(np.hypot(pout[:, 0] - c[0], pout[:, 1] - c[1]))
+    return (np.abs(uin[:, 0] - fin).max(), np.abs(uin[:, 1] - fin).max(),
+            np.abs(uout[:, 1] - fo).max(), np.abs(uin[:, 2] - 0.25).max(),
+            np.abs(uout[:, 2] - 0.75).max())
+
+
+def test_harmonic_reproduction_converges():
+    """Interior data are reproduced; two-sided data converge at first order
+    in the segment length (the self segment's double layer is taken as its
+    principal value 0 while the node sits off its chord by the sagitta).
+    A constant on the outside is not reproducible by single + double layer
+    in 2D (the representation has no constant term at infinity), so only
+    the inside of channel 2 is checked."""
+    coarse = _reproduction_errors(2, 8, 40)     # segment length l
+    fine = _reproduction_errors(4, 16, 80)      # l / 4
+    assert fine[0] < 1e-6 and coarse[0] / fine[0] > 8.0
+    for ec, ef in zip(coarse[1:4], fine[1:4]):
+        assert 3.0 < ec / ef < 6.0
+        assert ef < 1e-3
+
+
+def test_polygon_constant_two_sided_data():
+    """Straight edges: nodes lie exactly on their chords, so the singular
+    self-segment rule is exercised; a constant on each side is reproduced."""
+    verts = np.array([[0.2, 0.2], [0.8, 0.25], [0.75, 0.8], [0.25, 0.75]])
+    ctrl = scenegen.polygon_ctrl(verts)
+    disc = oracle.discretize(ctrl, 2, 8, 40)
+    N = disc.N
+    up = np.stack([np.full(N, 0.9), np.full(N, 0.1), np.full(N, 0.5)])
+    um = np.stack([np.full(N, 0.2), np.full(N, 0.6), np.full(N, 0.5)])
+    sigma, mu = oracle.solve(disc, up, um)
+    uin = oracle.evaluate(disc, sigma, mu, np.array([[0.5, 0.5], [0.45, 0.55]]))
+    np.testing.assert_allclose(uin, [[0.9, 0.1, 0.5]] * 2, atol=2e-3)
+
+
+# --------------------------------------------------------------------------
+# Invariances of the whole pipeline
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_scene():
+    sc = scenegen.uniform_scene(n_curves=3, n_stops=2, seed=11)
+    return sc
+
+
+def _render_scene(ctrl, left, right, vp, panels=2, gl=8, segs=40):
+    disc = oracle.discretize(ctrl, panels, gl, segs)
+    sigma, mu = oracle.solve_stops(disc, left, right)
+    return oracle.render(disc, sigma, mu, vp)
+
+
+def test_translation_and_rotation_invariance(small_scene):
+    ctrl, left, right = small_scene["ctrl"], small_scene["left"], small_scene["right"]
+    vp = (0.5, 0.5, 1.0, 1.0, 12, 12)
+    base = _render_scene(ctrl, left, right, vp)
+    shift = np.array([0.37, -1.25])
+    moved = _render_scene(ctrl + shift, left, right,
+                          (0.5 + shift[0], 0.5 + shift[1], 1.0, 1.0, 12, 12))
+    np.testing.assert_allclose(moved, base, atol=1e-10)
+    # rotation by 90 degrees about the viewport centre maps pixel (r, k) to
+    # pixel (W-1-k, r) of the rotated image
+    c = np.array([0.5, 0.5])
+    rot = np.array([[0.0, -1.0], [1.0, 0.0]])
+    rctrl = (ctrl - c) @ rot.T + c
+    rimg = _render_scene(rctrl, left, right, vp)
+    np.testing.assert_allclose(np.rot90(base, 1), rimg, atol=1e-10)
+
+
+def test_channel_permutation_and_mirror(small_scene):
+    ctrl, left, right = small_scene["ctrl"], small_scene["left"], small_scene["right"]
+    vp = (0.5, 0.5, 1.0, 1.0, 10, 10)
+    base = _render_scene(ctrl, left, right, vp)
+    perm = [2, 0, 1]
+    pimg = _render_scene(ctrl, left[..., perm], right[..., perm], vp)
+    np.testing.assert_allclose(pimg, base[..., perm], atol=1e-12)
+    # mirror x -> 1 - x swaps the left and right sides of every curve
+    mctrl = ctrl.copy()
+    mctrl[..., 0] = 1.0 - mctrl[..., 0]
+    mimg = _render_scene(mctrl, right, left, vp)
+    np.testing.assert_allclose(mimg, base[:, ::-1, :], atol=1e-10)
+
+
+def test_tiny_config_lu_residual():
+    cfg = scenegen.TINY
+    sc = scenegen.uniform_scene(n_curves=cfg["n_curves"], n_stops=cfg["n_stops"],
+                                seed=cfg["seed"])
+    disc = oracle.discretize(sc["ctrl"], cfg["panels"], cfg["gl"], cfg["segs"])
+    rep = {}
+    oracle.solve_stops(disc, sc["left"], sc["right"], report=rep)
+    assert max(rep["rel_residual"]) < 1e-12
