@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark: RGB pixels/s of the FP32 FMM render (and the plain FP64 FMM
+render) of the 200-curve workload at 2048 x 2048, with max error against the
+FP64 oracle on sampled pixels, the roofline figure of the dominant kernel
+and the oracle timed on the host cores.
+
+A step is one render of the viewport (per-viewport target tree, downward
+pass and leaf evaluation; the densities are solved once before timing, as a
+scene is solved once and rendered many times).
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import scenegen  # noqa: E402
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_sigma.npz")
+METRIC = "RGB pixels/s at max err <=1e-4 vs FP64 oracle; FP32-batched vs plain FP64 FMM"
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector (packed) TFLOP/s
+PEAK_FP64 = 78.6e12
+# Algorithmic flop-equivalents per unit of work (log = 20, atan2 = 30 flops).
+FLOP_P2P = 117.0
+
+
+def flops_l2p(p):
+    return 6 * p + 12 * (p + 1)
+
+
+def flops_m2p(p):
+    return 6 * p + 12 * (p + 1) + 10 + 20
+
+
+def leaf_flops(c, p):
+    return (c["p2p_pairs"] * FLOP_P2P + c["m2p_pairs"] * flops_m2p(p)
+            + c["l2p_targets"] * flops_l2p(p))
+
+
+def sample_pixels(W, H, segs_p1, segs_p2, rng, n_near=1024, stride=64):
+    rows, cols = np.meshgrid(np.arange(stride // 2, H, stride),
+                             np.arange(stride // 2, W, stride), indexing="ij")
+    pick = rng.choice(segs_p1.shape[0], size=n_near, replace=False)
+    mid = 0.5 * (segs_p1[pick] + segs_p2[pick])
+    nc = np.clip(np.floor(mid[:, 0] * W).astype(int), 0, W - 1)
+    nr = np.clip(np.floor((1.0 - mid[:, 1]) * H).astype(int), 0, H - 1)
+    r = np.concatenate([rows.ravel(), nr])
+    c = np.concatenate([cols.ravel(), nc])
+    return r, c
+
+
+def cpu_baseline(cfg, sc, workers):
+    """Oracle on the host cores: discretisation, then the direct-sum render
+    of a bounded pixel sample (timed) with the golden oracle densities."""
+    import oracle
+    t0 = time.time()
+    disc = oracle.discretize(sc["ctrl"], cfg["panels"], cfg["gl"], cfg["segs"], workers=workers)
+    t_disc = time.time() - t0
+    up, um = oracle.boundary_values(disc, sc["left"], sc["right"])
+    mu = up - um
+    have_golden = os.path.exists(GOLDEN)
+    if have_golden:
+        sigma = np.load(GOLDEN)["sigma"]
+    else:
+        sigma = np.ones((3, disc.N))
+    vp = cfg["viewport"]
+    rng = np.random.default_rng(2024)
+    rows, cols = sample_pixels(vp[4], vp[5], disc.seg_p1, disc.seg_p2, rng)
+    xs, ys = oracle.pixel_centres(vp)
+    pts = np.stack([xs[cols], ys[rows]], axis=1)
+    t0 = time.time()
+    vals = oracle.evaluate(disc, sigma, mu, pts, workers=workers)
+    t_eval = time.time() - t0
+    return dict(rows=rows, cols=cols, vals=vals if have_golden else None,
+                value=len(pts) / t_eval, seconds=t_eval, n=len(pts), S=disc.S,
+                t_disc=t_disc, golden=have_golden)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--p32", type=int, default=16, help="expansion order, FP32 path")
+    ap.add_argument("--p64", type=int, default=20, help="expansion order, FP64 path")
+    ap.add_argument("--tile", type=int, default=8)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the render shards by viewport; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    cfg = scenegen.FMM
+    sc = scenegen.sized_scene(n_curves=cfg["n_curves"], n_stops=cfg["n_stops"],
+                              seed=cfg["seed"])
+    vp = cfg["viewport"]
+    W, H = vp[4], vp[5]
+    # The oracle runs first, before anything touches the GPU (its worker
+    # processes are forked).
+    cpu = None
+    if not args.no_cpu:
+        print("cpu baseline: oracle discretisation + sampled direct-sum render", flush=True)
+        cpu = cpu_baseline(cfg, sc, args.workers)
+        print(f"cpu baseline: {cpu['n']} px in {cpu['seconds']:.1f} s", flush=True)
+
+    import torch
+    from paper_2311_14312_amd import dcfmm
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    scene = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
+                        gl=cfg["gl"], segs=cfg["segs"], leaf_max=args.leaf)
+    t_create = time.time() - t0
+    info = scene.info()
+    print("scene", info, f"create {t_create:.2f} s", flush=True)
+    rep = scene.solve(tol=cfg["gmres_tol"], max_iter=1000, method="fmm", p=args.p64)
+    print("solve", rep, flush=True)
+
+    def timed(ev, steps, warmup, dtype):
+        out = torch.empty((H, W, 3), device="cuda", dtype=dtype)
+        for _ in range(warmup):
+            scene.render(vp, out=out, **ev)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        t = time.perf_counter()
+        start.record()
+        for _ in range(steps):
+            scene.render(vp, out=out, **ev)
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        return start.elapsed_time(stop) / steps, wall / steps, out
+
+    ev32 = dict(method="fmm", precision="f32", p=args.p32, tile_px=args.tile)
+    ev64 = dict(method="fmm", precision="f64", p=args.p64, tile_px=args.tile)
+    ms32, wall32, img32 = timed(ev32, args.steps, args.warmup, torch.float32)
+    img32 = img32.cpu().numpy()
+    ms64, wall64, img64 = timed(ev64, max(1, args.steps // 2), 1, torch.float64)
+    img64 = img64.cpu().numpy()
+    print(f"FP32 {ms32:.3f} ms/step, FP64 {ms64:.3f} ms/step", flush=True)
+
+    # Dominant kernel: per-phase HIP-event timing on the render stream.
+    scene.set_timing(True)
+    for _ in range(args.steps):
+        scene.render(vp, **ev32)
+    tm = scene.get_timing()
+    scene.set_timing(False)
+    counts = scene.render_counts(vp, **ev32)
+    leaf_ms = tm["leaf_ms"] / max(1, tm["calls"])
+    fl = leaf_flops(counts, args.p32)
+    achieved = fl / (leaf_ms * 1e-3)
+    scene.set_timing(True)
+    for _ in range(max(1, args.steps // 2)):
+        scene.render(vp, **ev64)
+    tm64 = scene.get_timing()
+    scene.set_timing(False)
+    counts64 = scene.render_counts(vp, **ev64)
+    leaf64_ms = tm64["leaf_ms"] / max(1, tm64["calls"])
+    achieved64 = leaf_flops(counts64, args.p64) / (leaf64_ms * 1e-3)
+
+    px = W * H
+    err32 = err64 = None
+    if cpu is not None and cpu["vals"] is not None:
+        err32 = float(np.abs(img32[cpu["rows"], cpu["cols"]] - cpu["vals"]).max())
+        err64 = float(np.abs(img64[cpu["rows"], cpu["cols"]] - cpu["vals"]).max())
+    line = {
+        "metric": METRIC,
+        "value": px / (ms32 * 1e-3),
+        "unit": "RGB pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "200 random cubic Beziers (lengths log-uniform 0.01-0.5), "
+                               "16 panels x 16 GL nodes (51,200 nodes), 80 segments/panel, "
+                               "3 colour stops/side; 2048x2048 render of [0,1]^2",
+                   "p_fp32": args.p32, "p_fp64": args.p64, "tile_px": args.tile,
+                   "leaf_max": args.leaf, "gmres_tol": cfg["gmres_tol"]},
+        "max_err_vs_oracle": err32,
+        "err_sample": (f"{cpu['n']} pixels (32x32 stride-64 grid + 1024 near-chord)"
+                       if cpu else None),
+        "fp64_fmm": {"value": px / (ms64 * 1e-3), "unit": "RGB pixels/s", "ms_per_step": ms64,
+                     "max_err_vs_oracle": err64,
+                     "roofline": {"bound": "alu", "achieved": achieved64 / 1e12,
+                                  "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                                  "frac": achieved64 / PEAK_FP64}},
+        "speedup_fp32_vs_fp64": ms64 / ms32,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "k_leaf<float,64>", "kernel_ms": leaf_ms,
+                     "flop_eq_per_launch": fl},
+        "phases_ms": {k: v / max(1, tm["calls"]) for k, v in tm.items() if k.endswith("_ms")},
+        "work": counts,
+        "solve": {"seconds": rep["seconds"], "iters": rep["iters"],
+                  "true_rel_residual": rep["true_rel_residual"], "p": args.p64,
+                  "scene_create_s": t_create},
+        "cpu_baseline": None if cpu is None else {
+            "value": cpu["value"], "unit": "RGB pixels/s", "cores": args.workers,
+            "kind": "oracle",
+            "sample": f"{cpu['n']} sampled pixels of the 2048x2048 viewport x {cpu['S']} "
+                      f"segments, FP64 NumPy direct sum ({cpu['seconds']:.1f} s)"},
+    }
+    print(json.dumps(line), flush=True)
+    scene.close()
+
+
+if __name__ == "__main__":
+    main()

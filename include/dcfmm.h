@@ -1,0 +1,207 @@
+/*
+ * dcfmm.h -- C ABI of the MI355X (gfx950) diffusion-curve library.
+ *
+ * The library solves and renders diffusion curves with the hybrid BEM/BIEM
+ * discretisation of Bang, Serkh, Stein and Jacobson (ACM TOG 42(6), 2023):
+ * densities live at Gauss-Legendre nodes on cubic Bezier panels (Sec. 4.3,
+ * 5.2), potentials are integrated over chord segments with closed forms
+ * (App. D) scaled to the true arc length (App. A), and both the solve
+ * (Alg. 3) and the render (Alg. 4) are accelerated by a 2D Laplace fast
+ * multipole method on a non-uniform quadtree (App. E, Alg. 8).
+ *
+ * Conventions shared by every entry point
+ *  - Curves: ctrl[c][k][xy], k = 0..3 control points, math axes (y up).
+ *  - Colours: left_rgb/right_rgb[c][stop][rgb]; stop k sits at normalised
+ *    arc length k/(n_stops-1); colour is linear in arc length between stops.
+ *    The "+" side of a curve is the side its left normal (tangent rotated
+ *    +90 degrees) points to, so u+ = left colour, u- = right colour
+ *    (Sec. 5.3, Eq. int_S_dbnd_twoside).
+ *  - Nodes are numbered curve-major, then panel, then GL node in increasing
+ *    parameter: i = (c*P + p)*g + k.  Densities are [3][N] (channel-major).
+ *  - Pixels: row r, column k of a W x H viewport with centre (cx, cy) and
+ *    size (width, height) sit at x = cx - width/2 + (k+1/2) width/W,
+ *    y = cy + height/2 - (r+1/2) height/H.  Images are [H][W][3], row 0 at
+ *    the top.  Values are not clamped.
+ *  - Ownership: the library copies every host input it is given; output
+ *    buffers are owned by the caller.  "dev" pointers are device pointers on
+ *    the current HIP device; "stream" is a hipStream_t (NULL = default).
+ *    Calls that take a stream enqueue their kernels on it and return without
+ *    waiting unless stated otherwise.
+ *  - Errors: every int-returning call returns DC_OK (0) or a negative code;
+ *    dc_last_error() returns a thread-local message for the last failure.
+ *    No exception crosses the ABI.  A scene is not thread-safe: calls on one
+ *    scene must not overlap.
+ */
+#ifndef DCFMM_H
+#define DCFMM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DC_OK 0
+#define DC_ERR_INVALID (-1)        /* bad argument, NaN or degenerate input */
+#define DC_ERR_OOM (-2)            /* device or host allocation failed */
+#define DC_ERR_NOT_CONVERGED (-3)  /* GMRES hit max_iter; report filled */
+#define DC_ERR_HIP (-4)            /* HIP runtime error; message kept */
+
+#define DC_PREC_F64 0   /* everything in FP64 */
+#define DC_PREC_F32 1   /* FP32 expansions and near field; FP64 for
+                           near-singular chord pairs */
+#define DC_METHOD_FMM 0
+#define DC_METHOD_DIRECT 1   /* brute-force sum over every chord segment */
+#define DC_OUT_F32 0
+#define DC_OUT_F64 1
+#define DC_P_MAX 40          /* largest expansion order supported */
+
+typedef struct dc_scene_s* dc_scene;
+
+/* Discretisation and quadtree of a scene.
+ * panels_per_curve P, gl_per_panel g, segs_per_panel s (the same segments
+ * are used for solution and evaluation, s = e, Sec. 9), leaf_max b (a box is
+ * split while it holds more than b GL nodes; App. E.5), max_depth (<= 40),
+ * domain = {xmin, ymin, xmax, ymax}: a rectangle the quadtree root must cover
+ * besides the curves (every rendered pixel centre must lie in the root). */
+typedef struct {
+    int panels_per_curve;
+    int gl_per_panel;
+    int segs_per_panel;
+    int leaf_max;
+    int max_depth;
+    double domain[4];
+} dc_scene_opts;
+
+/* How one evaluation of the representation is carried out.
+ * method: DC_METHOD_FMM or DC_METHOD_DIRECT; precision: DC_PREC_*;
+ * p: expansion order (coefficients 0..p, 1 <= p <= DC_P_MAX);
+ * tile_px: render target boxes hold at most tile_px x tile_px pixels
+ * (2..16); near_fp64: in DC_PREC_F32, a pixel closer to a chord than
+ * near_fp64 * (chord length) is evaluated in FP64. */
+typedef struct {
+    int method;
+    int precision;
+    int p;
+    int tile_px;
+    double near_fp64;
+} dc_eval_opts;
+
+/* GMRES (Sec. 6.5.1): relative residual tolerance ||b - Ax|| / ||b|| per
+ * channel, at most max_iter Arnoldi steps (no restart), initial guess 1. */
+typedef struct {
+    double tol;
+    int max_iter;
+    dc_eval_opts matvec;
+} dc_solve_opts;
+
+typedef struct {
+    double cx, cy, width, height;
+    int W, H;
+} dc_viewport;
+
+typedef struct {
+    int iters[3];                  /* Arnoldi steps per channel */
+    double rel_residual[3];        /* GMRES estimate at exit */
+    double true_rel_residual[3];   /* ||b - A x|| / ||b|| recomputed */
+    double seconds;                /* wall time of the solve */
+    int converged;                 /* 1 if every channel met tol */
+} dc_solve_report;
+
+typedef struct {
+    int n_curves, N, S;            /* curves, GL nodes, chord segments */
+    int n_pieces;                  /* chords clipped at quadtree leaves */
+    int n_cells, n_leaves, depth;  /* quadtree size */
+    double root[3];                /* root box x0, y0, side */
+    int solved;                    /* densities present */
+} dc_scene_info;
+
+/* Fill opts / eval with the library defaults (P=16, g=16, s=80, b=64,
+ * max_depth=40, domain [-0.45,1.45]^2; FMM, FP64, p=20, tile 8, near 1e-3). */
+void dc_default_scene_opts(dc_scene_opts* opts);
+void dc_default_eval_opts(dc_eval_opts* eval);
+
+/* Build a scene: arc-length parametrisation (App. B), panels, GL nodes,
+ * chord segments with their arc-length scale (App. A), boundary values
+ * from the colour stops, the quadtree over the nodes and the chords
+ * clipped at its leaves (Sec. 6.1, 6.2), all copied to the device.
+ * Synchronous.  DC_ERR_INVALID for NaN/Inf input, a zero-length curve,
+ * n_stops < 2 or bad options. */
+int dc_scene_create(const double* ctrl, int n_curves,
+                    const double* left_rgb, const double* right_rgb,
+                    int n_stops, const dc_scene_opts* opts, dc_scene* out);
+
+void dc_scene_destroy(dc_scene s);
+
+int dc_scene_get_info(dc_scene s, dc_scene_info* info);
+
+/* Node positions, host [N][2], in node order.  Synchronous. */
+int dc_get_nodes(dc_scene s, double* xy_host);
+
+/* Replace the boundary values with arbitrary nodal data, host [3][N] each
+ * (u+ on the left side, u- on the right).  Drops solved densities. */
+int dc_set_boundary(dc_scene s, const double* u_plus_host,
+                    const double* u_minus_host);
+
+/* Alg. 3: mu = u+ - u-, b = (u+ + u-)/2 - F_H mu, sigma = GMRES(G_H, 1, b).
+ * Densities stay resident on the device.  Synchronous (returns after the
+ * solve).  DC_ERR_NOT_CONVERGED keeps the last iterate as the densities. */
+int dc_solve_densities(dc_scene s, const dc_solve_opts* o,
+                       dc_solve_report* rep, void* stream);
+
+/* Densities sigma at the nodes, host [3][N].  Synchronous. */
+int dc_get_densities(dc_scene s, double* sigma_host);
+
+/* Install densities (e.g. from a checkpoint), host [3][N].  Synchronous. */
+int dc_set_densities(dc_scene s, const double* sigma_host);
+
+/* y = G_H x + c_mu * F_H mu at the nodes (the solve's operator, Eq.
+ * db_mat_solve), x_dev and y_dev device [3][N] FP64 in node order.
+ * c_mu is 0 or 1.  Asynchronous on stream. */
+int dc_apply_operator(dc_scene s, const double* x_dev, double* y_dev,
+                      int c_mu, const dc_eval_opts* o, void* stream);
+
+/* Alg. 4: u = FMM_G(Pi sigma) + FMM_F(Pi mu) at every pixel centre of vp,
+ * written to out_dev ([H][W][3], FP32 or FP64 per out_dtype).  Needs
+ * densities.  Every pixel centre must lie inside the quadtree root.
+ * Asynchronous on stream. */
+int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
+              int out_dtype, void* out_dev, void* stream);
+
+/* The same representation at n arbitrary points xy_dev (device [n][2]
+ * FP64), out_dev [n][3].  Uses the direct sum (method is ignored). */
+int dc_eval_points(dc_scene s, const double* xy_dev, int n,
+                   const dc_eval_opts* o, int out_dtype, void* out_dev,
+                   void* stream);
+
+/* Work actually done by one render, counted on the device (the counting
+ * run is separate from timed runs).  Synchronous. */
+typedef struct {
+    unsigned long long p2p_pairs;       /* (target, piece) closed forms */
+    unsigned long long p2p_fp64_pairs;  /* of those, evaluated in FP64 */
+    unsigned long long m2p_pairs;       /* (target, box) outgoing evaluations */
+    unsigned long long l2p_targets;     /* targets evaluated from an incoming expansion */
+    unsigned long long m2l_pairs;       /* (target box, source box) translations */
+    unsigned long long p2l_pairs;       /* (target box, piece) incoming-from-source */
+    unsigned long long l2l_boxes;       /* parent-to-child incoming translations */
+    unsigned long long leaf_boxes;      /* target leaves evaluated */
+    unsigned long long pieces;          /* clipped chord pieces of the scene */
+    unsigned long long source_cells;    /* boxes of the source quadtree */
+    int levels;                         /* levels of the target tree */
+    int p;                              /* expansion order used */
+} dc_work_counts;
+
+int dc_render_counts(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
+                     dc_work_counts* counts, void* stream);
+
+/* Per-phase timing of dc_render with HIP events on the caller's stream.
+ * While enabled every dc_render waits for its own completion.
+ * dc_get_timing fills ms[5] = {upward, downward, leaf, total (ms, summed
+ * over calls), number of calls} and resets the sums. */
+int dc_set_timing(dc_scene s, int enable);
+int dc_get_timing(dc_scene s, double* ms);
+
+const char* dc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCFMM_H */

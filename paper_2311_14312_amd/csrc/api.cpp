@@ -1,0 +1,440 @@
+// C ABI entry points (include/dcfmm.h): scene lifecycle, the GMRES solve of
+// Alg. 3 and the render of Alg. 4, dispatching to the direct-sum or FMM
+// kernels.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "scene.h"
+
+using namespace dc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        f();
+        return DC_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return DC_ERR_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return DC_ERR_INVALID;
+    }
+}
+
+void check_eval(const dc_eval_opts* o) {
+    DC_REQUIRE(o != nullptr, "null eval options");
+    DC_REQUIRE(o->method == DC_METHOD_FMM || o->method == DC_METHOD_DIRECT, "bad method");
+    DC_REQUIRE(o->precision == DC_PREC_F64 || o->precision == DC_PREC_F32, "bad precision");
+    DC_REQUIRE(o->p >= 1 && o->p <= DC_P_MAX, "expansion order p must be in 1..DC_P_MAX");
+    DC_REQUIRE(o->tile_px >= 2 && o->tile_px <= 16, "tile_px must be in 2..16");
+    DC_REQUIRE(std::isfinite(o->near_fp64) && o->near_fp64 >= 0.0, "bad near_fp64");
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+void upload_boundary(dc_scene s) {
+    const int N = s->geo.N;
+    s->d_uplus.upload(s->uplus);
+    s->d_uminus.upload(s->uminus);
+    std::vector<double> mu(3 * (size_t)N);
+    for (size_t i = 0; i < mu.size(); ++i) mu[i] = s->uplus[i] - s->uminus[i];
+    s->d_mu.upload(mu);
+    s->solved = false;
+    s->seg_w_valid = false;
+    if (s->fmm) fmm_invalidate(*s->fmm);
+}
+
+// Segment weights (kappa sigma_bar, kappa mu_bar) of the resident densities.
+void ensure_seg_weights(dc_scene s, hipStream_t st) {
+    if (s->seg_w_valid) return;
+    s->seg_w.alloc((size_t)6 * s->geo.S);
+    launch_chord_weights(s->geo.S, nullptr, s->geo.s, s->geo.g, s->geo.N, s->Pi.p,
+                         s->seg_kappa.p, s->d_sigma.p, s->d_mu.p, s->seg_w.p, nullptr, st);
+    s->seg_w_valid = true;
+}
+
+// y = G_H x + c_mu F_H mu at the nodes (x or mu may be null).
+void apply_operator(dc_scene s, const double* x, const double* mu, double* y,
+                    const dc_eval_opts& o, hipStream_t st) {
+    if (o.method == DC_METHOD_DIRECT) {
+        DevBuf<double> w;
+        w.alloc((size_t)6 * s->geo.S);
+        launch_chord_weights(s->geo.S, nullptr, s->geo.s, s->geo.g, s->geo.N, s->Pi.p,
+                             s->seg_kappa.p, x, mu, w.p, nullptr, st);
+        launch_direct_nodes(s->nodes(), s->segs(), s->seg_ell.p, s->seg_kappa.p, w.p, y, st);
+        DC_HIP(hipStreamSynchronize(st));  // w is released on return
+    } else {
+        fmm_apply_nodes(*s, x, mu, y, o, st);
+    }
+}
+
+// Alg. 3 with GMRES (Sec. 6.5.1): three channels share every matvec.
+int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStream_t st) {
+    const int N = s->geo.N;
+    const size_t n3 = 3 * (size_t)N;
+    const int m = std::max(1, std::min(o.max_iter, N));
+    DevBuf<double> b, x, w, tmp, V, dev_h, dev_small;
+    b.alloc(n3);
+    x.alloc(n3);
+    w.alloc(n3);
+    tmp.alloc(n3);
+    V.alloc((size_t)(m + 1) * n3);
+    const int kcap = m + 1;
+    dev_h.alloc((size_t)2 * 3 * kcap);
+    dev_small.alloc(3 * (size_t)kcap + 8);
+    double* h1 = dev_h.p;
+    double* h2 = dev_h.p + 3 * kcap;
+
+    // b = (u+ + u-)/2 - F_H mu
+    apply_operator(s, nullptr, s->d_mu.p, tmp.p, o.matvec, st);
+    launch_axpby((int)n3, 0.5, s->d_uplus.p, 0.5, s->d_uminus.p, b.p, st);
+    launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, b.p, st);
+    // x0 = 1, r0 = b - A x0
+    launch_fill((int)n3, 1.0, x.p, st);
+    apply_operator(s, x.p, nullptr, tmp.p, o.matvec, st);
+    launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, w.p, st);
+
+    std::vector<double> host(6 * (size_t)kcap + 8);
+    auto norms = [&](const double* vec, double out[3]) {
+        launch_block_dots(vec, 1, vec, N, dev_small.p, st);
+        DC_HIP(hipMemcpyAsync(host.data(), dev_small.p, 3 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        for (int c = 0; c < 3; ++c) out[c] = std::sqrt(std::max(host[c], 0.0));
+    };
+    double bnorm[3], beta[3];
+    norms(b.p, bnorm);
+    norms(w.p, beta);
+
+    // Hessenberg columns, Givens rotations and the rotated rhs, per channel.
+    std::vector<std::vector<double>> R(3, std::vector<double>((size_t)kcap * kcap, 0.0));
+    std::vector<std::vector<double>> cs(3, std::vector<double>(kcap)), sn(3, std::vector<double>(kcap));
+    std::vector<std::vector<double>> gv(3, std::vector<double>(kcap + 1, 0.0));
+    bool active[3];
+    double alpha[3];
+    for (int c = 0; c < 3; ++c) {
+        gv[c][0] = beta[c];
+        rep.iters[c] = 0;
+        const double bn = bnorm[c] > 0 ? bnorm[c] : 1.0;
+        rep.rel_residual[c] = beta[c] / bn;
+        active[c] = rep.rel_residual[c] > o.tol && beta[c] > 0;
+        alpha[c] = beta[c] > 0 ? 1.0 / beta[c] : 0.0;
+    }
+    DC_HIP(hipMemcpyAsync(dev_small.p, alpha, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_scale3(w.p, dev_small.p, V.p, N, st);
+
+    for (int k = 0; k < m && (active[0] || active[1] || active[2]); ++k) {
+        double* vk = V.p + (size_t)k * n3;
+        apply_operator(s, vk, nullptr, w.p, o.matvec, st);
+        // classical Gram-Schmidt, twice (CGS2), against V[0..k]
+        launch_block_dots(V.p, k + 1, w.p, N, h1, st);
+        launch_block_update(V.p, k + 1, h1, k + 1, w.p, N, st);
+        launch_block_dots(V.p, k + 1, w.p, N, h2, st);
+        launch_block_update(V.p, k + 1, h2, k + 1, w.p, N, st);
+        launch_block_dots(w.p, 1, w.p, N, dev_small.p, st);
+        DC_HIP(hipMemcpyAsync(host.data(), h1, 3 * (size_t)(k + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        DC_HIP(hipMemcpyAsync(host.data() + 3 * (size_t)kcap, h2,
+                              3 * (size_t)(k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+        DC_HIP(hipMemcpyAsync(host.data() + 6 * (size_t)kcap, dev_small.p, 3 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        for (int c = 0; c < 3; ++c) {
+            alpha[c] = 0.0;
+            if (!active[c]) continue;
+            double* col = &R[c][(size_t)k * kcap];
+            for (int j = 0; j <= k; ++j)
+                col[j] = host[(size_t)c * (k + 1) + j] + host[3 * (size_t)kcap + (size_t)c * (k + 1) + j];
+            const double hk1 = std::sqrt(std::max(host[6 * (size_t)kcap + c], 0.0));
+            for (int j = 0; j < k; ++j) {
+                const double a = cs[c][j] * col[j] + sn[c][j] * col[j + 1];
+                col[j + 1] = -sn[c][j] * col[j] + cs[c][j] * col[j + 1];
+                col[j] = a;
+            }
+            const double r = std::hypot(col[k], hk1);
+            cs[c][k] = r > 0 ? col[k] / r : 1.0;
+            sn[c][k] = r > 0 ? hk1 / r : 0.0;
+            col[k] = r;
+            gv[c][k + 1] = -sn[c][k] * gv[c][k];
+            gv[c][k] = cs[c][k] * gv[c][k];
+            rep.iters[c] = k + 1;
+            const double bn = bnorm[c] > 0 ? bnorm[c] : 1.0;
+            rep.rel_residual[c] = std::fabs(gv[c][k + 1]) / bn;
+            if (rep.rel_residual[c] <= o.tol || hk1 == 0.0) active[c] = false;
+            alpha[c] = (active[c] && hk1 > 0) ? 1.0 / hk1 : 0.0;
+        }
+        DC_HIP(hipMemcpyAsync(dev_small.p, alpha, 3 * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_scale3(w.p, dev_small.p, V.p + (size_t)(k + 1) * n3, N, st);
+    }
+    // Back substitution R y = g per channel; x += V y.
+    std::vector<double> y(3 * (size_t)kcap, 0.0);
+    for (int c = 0; c < 3; ++c) {
+        const int kk = rep.iters[c];
+        for (int i = kk - 1; i >= 0; --i) {
+            double acc = gv[c][i];
+            for (int j = i + 1; j < kk; ++j) acc -= R[c][(size_t)j * kcap + i] * y[(size_t)c * kcap + j];
+            const double d = R[c][(size_t)i * kcap + i];
+            y[(size_t)c * kcap + i] = d != 0 ? acc / d : 0.0;
+        }
+    }
+    int kmax = std::max(rep.iters[0], std::max(rep.iters[1], rep.iters[2]));
+    if (kmax > 0) {
+        DevBuf<double> dy;
+        dy.upload(y);
+        launch_combine(V.p, kmax, dy.p, kcap, x.p, N, st);
+        DC_HIP(hipStreamSynchronize(st));
+    }
+    // True residual.
+    apply_operator(s, x.p, nullptr, tmp.p, o.matvec, st);
+    launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, w.p, st);
+    double rn[3];
+    norms(w.p, rn);
+    rep.converged = 1;
+    for (int c = 0; c < 3; ++c) {
+        rep.true_rel_residual[c] = rn[c] / (bnorm[c] > 0 ? bnorm[c] : 1.0);
+        if (rep.rel_residual[c] > o.tol) rep.converged = 0;
+    }
+    s->d_sigma.alloc(n3);
+    DC_HIP(hipMemcpyAsync(s->d_sigma.p, x.p, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    DC_HIP(hipStreamSynchronize(st));
+    s->solved = true;
+    s->seg_w_valid = false;
+    if (s->fmm) fmm_invalidate(*s->fmm);
+    return rep.converged ? DC_OK : DC_ERR_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dc_default_scene_opts(dc_scene_opts* o) {
+    if (!o) return;
+    o->panels_per_curve = 16;
+    o->gl_per_panel = 16;
+    o->segs_per_panel = 80;
+    o->leaf_max = 64;
+    o->max_depth = 40;
+    o->domain[0] = -0.45;
+    o->domain[1] = -0.45;
+    o->domain[2] = 1.45;
+    o->domain[3] = 1.45;
+}
+
+void dc_default_eval_opts(dc_eval_opts* e) {
+    if (!e) return;
+    e->method = DC_METHOD_FMM;
+    e->precision = DC_PREC_F64;
+    e->p = 20;
+    e->tile_px = 8;
+    e->near_fp64 = 1e-3;
+}
+
+int dc_scene_create(const double* ctrl, int n_curves, const double* left_rgb,
+                    const double* right_rgb, int n_stops, const dc_scene_opts* opts,
+                    dc_scene* out) {
+    return guarded([&] {
+        DC_REQUIRE(ctrl && left_rgb && right_rgb && opts && out, "null argument");
+        *out = nullptr;
+        auto s = std::make_unique<dc_scene_s>();
+        s->opts = *opts;
+        discretize(ctrl, n_curves, opts->panels_per_curve, opts->gl_per_panel,
+                   opts->segs_per_panel, s->geo);
+        boundary_from_stops(s->geo, left_rgb, right_rgb, n_stops, s->uplus, s->uminus);
+        build_tree(s->geo, opts->leaf_max, opts->max_depth, opts->domain, s->tree);
+        const Geometry& G = s->geo;
+        std::vector<double> tx(G.S), ty(G.S), len(G.S);
+        for (int j = 0; j < G.S; ++j) {
+            const double ax = G.seg_x1[j] - G.seg_x0[j], ay = G.seg_y1[j] - G.seg_y0[j];
+            len[j] = std::hypot(ax, ay);
+            tx[j] = ax / len[j];
+            ty[j] = ay / len[j];
+        }
+        s->seg_x0.upload(G.seg_x0);
+        s->seg_y0.upload(G.seg_y0);
+        s->seg_tx.upload(tx);
+        s->seg_ty.upload(ty);
+        s->seg_len.upload(len);
+        s->seg_ell.upload(G.seg_ell);
+        s->seg_kappa.upload(G.seg_kappa);
+        s->node_x.upload(G.node_x);
+        s->node_y.upload(G.node_y);
+        s->node_tstar.upload(G.node_tstar);
+        s->node_self.upload(G.node_self);
+        s->Pi.upload(G.Pi);
+        upload_boundary(s.get());
+        s->fmm = fmm_create(*s);
+        *out = s.release();
+    });
+}
+
+void dc_scene_destroy(dc_scene s) { delete s; }
+
+int dc_scene_get_info(dc_scene s, dc_scene_info* info) {
+    return guarded([&] {
+        DC_REQUIRE(s && info, "null argument");
+        info->n_curves = s->geo.n_curves;
+        info->N = s->geo.N;
+        info->S = s->geo.S;
+        info->n_pieces = (int)s->tree.pseg.size();
+        info->n_cells = s->tree.n_cells;
+        info->n_leaves = s->tree.n_leaves;
+        info->depth = s->tree.depth;
+        info->root[0] = s->tree.X0;
+        info->root[1] = s->tree.Y0;
+        info->root[2] = s->tree.side;
+        info->solved = s->solved ? 1 : 0;
+    });
+}
+
+int dc_get_nodes(dc_scene s, double* xy) {
+    return guarded([&] {
+        DC_REQUIRE(s && xy, "null argument");
+        for (int i = 0; i < s->geo.N; ++i) {
+            xy[2 * (size_t)i] = s->geo.node_x[i];
+            xy[2 * (size_t)i + 1] = s->geo.node_y[i];
+        }
+    });
+}
+
+int dc_set_boundary(dc_scene s, const double* up, const double* um) {
+    return guarded([&] {
+        DC_REQUIRE(s && up && um, "null argument");
+        const size_t n3 = 3 * (size_t)s->geo.N;
+        for (size_t i = 0; i < n3; ++i)
+            DC_REQUIRE(std::isfinite(up[i]) && std::isfinite(um[i]), "non-finite boundary value");
+        s->uplus.assign(up, up + n3);
+        s->uminus.assign(um, um + n3);
+        upload_boundary(s);
+    });
+}
+
+int dc_solve_densities(dc_scene s, const dc_solve_opts* o, dc_solve_report* rep, void* stream) {
+    int rc = DC_OK;
+    int g = guarded([&] {
+        DC_REQUIRE(s && o && rep, "null argument");
+        check_eval(&o->matvec);
+        DC_REQUIRE(o->tol > 0 && o->max_iter >= 1, "bad GMRES options");
+        std::memset(rep, 0, sizeof(*rep));
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = gmres_solve(s, *o, *rep, as_stream(stream));
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc != DC_OK) g_last_error = "GMRES did not reach the tolerance";
+    });
+    return g != DC_OK ? g : rc;
+}
+
+int dc_get_densities(dc_scene s, double* sigma) {
+    return guarded([&] {
+        DC_REQUIRE(s && sigma, "null argument");
+        DC_REQUIRE(s->solved, "scene has no densities");
+        DC_HIP(hipMemcpy(sigma, s->d_sigma.p, 3 * (size_t)s->geo.N * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    });
+}
+
+int dc_set_densities(dc_scene s, const double* sigma) {
+    return guarded([&] {
+        DC_REQUIRE(s && sigma, "null argument");
+        const size_t n3 = 3 * (size_t)s->geo.N;
+        for (size_t i = 0; i < n3; ++i) DC_REQUIRE(std::isfinite(sigma[i]), "non-finite density");
+        std::vector<double> v(sigma, sigma + n3);
+        s->d_sigma.upload(v);
+        s->solved = true;
+        s->seg_w_valid = false;
+        if (s->fmm) fmm_invalidate(*s->fmm);
+    });
+}
+
+int dc_apply_operator(dc_scene s, const double* x, double* y, int c_mu, const dc_eval_opts* o,
+                      void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && x && y, "null argument");
+        check_eval(o);
+        apply_operator(s, x, c_mu ? s->d_mu.p : nullptr, y, *o, as_stream(stream));
+    });
+}
+
+int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o, int out_dtype,
+              void* out, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && vp && out, "null argument");
+        check_eval(o);
+        DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
+        DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0 &&
+                       std::isfinite(vp->cx) && std::isfinite(vp->cy) &&
+                       std::isfinite(vp->width) && std::isfinite(vp->height),
+                   "bad viewport");
+        DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
+        hipStream_t st = as_stream(stream);
+        if (o->method == DC_METHOD_DIRECT) {
+            ensure_seg_weights(s, st);
+            TargetGrid g{vp->cx, vp->cy, vp->width, vp->height, vp->W, vp->H};
+            launch_direct_targets(&g, nullptr, 0, s->segs(), s->seg_w.p, out_dtype, out, st);
+        } else {
+            fmm_render(*s, *vp, *o, out_dtype, out, st);
+        }
+    });
+}
+
+int dc_eval_points(dc_scene s, const double* xy, int n, const dc_eval_opts* o, int out_dtype,
+                   void* out, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && xy && out && n >= 0, "bad argument");
+        check_eval(o);
+        DC_REQUIRE(s->solved, "evaluation needs densities");
+        DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
+        hipStream_t st = as_stream(stream);
+        ensure_seg_weights(s, st);
+        launch_direct_targets(nullptr, xy, n, s->segs(), s->seg_w.p, out_dtype, out, st);
+    });
+}
+
+int dc_render_counts(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
+                     dc_work_counts* counts, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && vp && o && counts, "null argument");
+        check_eval(o);
+        DC_REQUIRE(o->method == DC_METHOD_FMM, "work counts are defined for the FMM path");
+        DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
+        DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0, "bad viewport");
+        std::memset(counts, 0, sizeof(*counts));
+        fmm_render_counts(*s, *vp, *o, counts, as_stream(stream));
+    });
+}
+
+int dc_set_timing(dc_scene s, int enable) {
+    return guarded([&] {
+        DC_REQUIRE(s, "null scene");
+        FmmState& f = *s->fmm;
+        if (enable)
+            for (hipEvent_t& e : f.ev)
+                if (!e) DC_HIP(hipEventCreate(&e));
+        f.timing = enable != 0;
+    });
+}
+
+int dc_get_timing(dc_scene s, double* ms) {
+    return guarded([&] {
+        DC_REQUIRE(s && ms, "null argument");
+        FmmState& f = *s->fmm;
+        for (int i = 0; i < 4; ++i) {
+            ms[i] = f.tms[i];
+            f.tms[i] = 0;
+        }
+        ms[4] = f.tcalls;
+        f.tcalls = 0;
+    });
+}
+
+const char* dc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

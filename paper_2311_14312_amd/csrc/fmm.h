@@ -1,0 +1,63 @@
+// Fast multipole evaluation of the hybrid representation (App. E, Alg. 8)
+// on the scene quadtree.  Host-side driver interface.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "dc_common.h"
+
+struct dc_scene_s;
+
+namespace dc {
+
+struct FmmState {
+    // Quadtree on the device (copied from the host tree).
+    int n_cells = 0, depth = 0, n_pieces = 0, n_target_leaves = 0;
+    double X0 = 0, Y0 = 0, side = 1;
+    std::vector<int> level_start;
+    DevBuf<int> lvl, child, parent, pbeg, pend, npc, nbeg, nend, node_perm, target_leaves;
+    DevBuf<long long> ix, iy;
+    // Pieces: start point, unit tangent, length, end point, segment.
+    DevBuf<double> px0, py0, px1, py1, ptx, pty, plen;
+    DevBuf<int> pseg;
+    // Pieces of each segment (CSR), for the self-segment correction.
+    DevBuf<int> seg_piece_beg, seg_piece_idx;
+    // Piece weights (kappa sigma_bar, kappa mu_bar) [6][n_pieces].
+    DevBuf<double> w64;
+    DevBuf<float> w32;
+    // Multipole and local coefficients of the source tree, and near sets.
+    DevBuf<double> M64, L64;
+    DevBuf<float> M32, L32;
+    DevBuf<int> nsetS;
+    // Upward pass of the resident densities (render reuses it).
+    bool up_valid = false;
+    int up_p = -1, up_prec = -1;
+    // Render scratch: local coefficients and near sets of target boxes.
+    DevBuf<double> TL64;
+    DevBuf<float> TL32;
+    DevBuf<int> Tnset;
+    // Optional device work counters (counting runs only) and phase timing.
+    unsigned long long* stats = nullptr;
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double tms[4] = {0, 0, 0, 0};
+    int tcalls = 0;
+    ~FmmState() {
+        for (hipEvent_t& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s);
+void fmm_invalidate(FmmState& f);
+// y[3][N] = G_H sigma + F_H mu at the nodes (either density may be null).
+void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, double* y,
+                     const dc_eval_opts& o, hipStream_t st);
+void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int out_dtype,
+                void* out, hipStream_t st);
+// Run one render with device work counters; fills counts (synchronous).
+void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
+                       dc_work_counts* counts, hipStream_t st);
+
+}  // namespace dc

@@ -1,0 +1,966 @@
+// Fast multipole evaluation of the hybrid representation (App. E, Alg. 8).
+//
+// Expansion basis (App. E.1): I_k(z) = z^k / k!, O_k(z) = (k-1)!/z^k,
+// O_0 = -log z.  Coefficients are stored box-scaled so that no factorial or
+// power of the box size appears in FP32:
+//   multipole  Mt_k = M_k k! / r^k,   local  Lt_k = L_k r^k / k!,
+// r = half-width of the box.  Single and double layer share one coefficient
+// vector per colour channel (the double layer differs only in the source
+// terms, Sec. 6.3), so one pass evaluates u = FMM_G(Pi sigma) + FMM_F(Pi mu).
+//
+// Targets live in their own tree on the same canonical grid as the source
+// quadtree.  For every target box a we keep its near set N(a): for each of
+// the 3x3 neighbouring positions at a's level, the deepest source box at a
+// level <= level(a) covering it.  From N(parent(a)):
+//   - children (at level(a)) of internal boxes that do not touch a form the
+//     interaction list of a (incoming-from-outgoing, Eq. i-f-o);
+//   - source leaves coarser than a that do not touch a form its bigger
+//     separated list (incoming-from-source, App. E.10/E.11);
+//   - the rest is N(a).
+// At a target leaf the near set is descended: source leaves touching it are
+// summed directly (target-from-source, App. D), non-touching children of
+// touching boxes form the smaller separated list (target-from-outgoing,
+// Eq. t-f-o).  When the target tree is the source tree (the solve) this is
+// exactly Alg. 8; for a render the target tree is the complete quadtree over
+// the viewport down to pixel tiles.
+#include <cmath>
+
+#include "scene.h"
+
+namespace dc {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kUCap = 128;   // near leaves per round
+constexpr int kWCap = 256;   // smaller-separated boxes per round
+constexpr int kSCap = 256;   // traversal stack (>= 9 + 4 * max depth)
+// work counters (dc_work_counts order)
+enum { kStatP2P = 0, kStatP2P64, kStatM2P, kStatL2P, kStatM2L, kStatP2L, kStatL2L, kStatLeaf,
+       kNStat };
+
+struct TreeView {
+    int n_cells;
+    double X0, Y0, side;
+    const int *lvl, *child, *parent, *pbeg, *pend, *npc, *nbeg, *nend, *node_perm;
+    const long long *ix, *iy;
+};
+
+struct PieceView {
+    int n;
+    const double *x0, *y0, *x1, *y1, *tx, *ty, *len;
+    const int* seg;
+    const double* w64;
+    const float* w32;
+};
+
+__device__ inline double half_width(const TreeView& t, int l) { return ldexp(t.side, -(l + 1)); }
+
+__device__ inline void center_of(const TreeView& t, int l, long long i, long long j, double& cx,
+                                 double& cy) {
+    const double h = ldexp(t.side, -(l + 1));
+    cx = t.X0 + (double)(2 * i + 1) * h;
+    cy = t.Y0 + (double)(2 * j + 1) * h;
+}
+
+// Does source box c (any level <= l... or finer) touch target box (l, ti, tj)?
+// Boxes touch when their closed squares intersect (edges or corners).
+__device__ inline bool touches(const TreeView& t, int c, int l, long long ti, long long tj) {
+    const int lc = t.lvl[c];
+    long long cx = t.ix[c], cy = t.iy[c];
+    if (lc <= l) {
+        const int s = l - lc;
+        const long long lo_x = cx << s, hi_x = ((cx + 1) << s) - 1;
+        const long long lo_y = cy << s, hi_y = ((cy + 1) << s) - 1;
+        return ti >= lo_x - 1 && ti <= hi_x + 1 && tj >= lo_y - 1 && tj <= hi_y + 1;
+    }
+    const int s = lc - l;
+    const long long lo_x = ti << s, hi_x = ((ti + 1) << s) - 1;
+    const long long lo_y = tj << s, hi_y = ((tj + 1) << s) - 1;
+    return cx >= lo_x - 1 && cx <= hi_x + 1 && cy >= lo_y - 1 && cy <= hi_y + 1;
+}
+
+template <typename T>
+__device__ inline cpx<T> to_c(double re, double im) {
+    return {(T)re, (T)im};
+}
+
+template <typename T>
+__device__ inline const T* weights(const PieceView& pv);
+template <>
+__device__ inline const double* weights<double>(const PieceView& pv) { return pv.w64; }
+template <>
+__device__ inline const float* weights<float>(const PieceView& pv) { return pv.w32; }
+
+// ------------------------------------------------------------------ upward
+// Outgoing-from-source on every leaf (App. E.8, E.9), lane k = coefficient:
+//   Mt_k += r wbar qs (B^{k+1} - A^{k+1})/(k+1) + i qm (B^k - A^k),
+// A, B = piece end points relative to the box centre in units of r,
+// wbar = conjugate unit tangent, qs = kappa sigma_bar, qm = kappa mu_bar
+// (the left normal nu = i w makes nu wbar = i).
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
+    const int c = blockIdx.x;
+    if (tv.child[c] >= 0) return;
+    const int k = threadIdx.x;
+    if (k > p) return;
+    const int l = tv.lvl[c];
+    const double r = half_width(tv, l);
+    double cx, cy;
+    center_of(tv, l, tv.ix[c], tv.iy[c], cx, cy);
+    const double inv_r = 1.0 / r;
+    const T* w = weights<T>(pv);
+    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    const T rk = (T)(r / (k + 1));
+    for (int e = tv.pbeg[c]; e < tv.pend[c]; ++e) {
+        const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
+        const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
+        const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
+        const cpx<T> Ak = cpow(A, k), Bk = cpow(B, k);
+        const cpx<T> ds = cmul(cscale(csub(cmul(Bk, B), cmul(Ak, A)), rk), wbar);
+        const cpx<T> dk = csub(Bk, Ak);
+        const cpx<T> dm = {-dk.im, dk.re};
+        for (int ch = 0; ch < 3; ++ch) {
+            const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
+            acc[ch] = cadd(acc[ch], cadd(cscale(ds, qs), cscale(dm, qm)));
+        }
+    }
+    cpx<T>* out = M + ((size_t)c * (p + 1) + k) * 3;
+    for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+}
+
+// Outgoing-from-outgoing (Eq. o-f-o) in scaled form, child quadrant q:
+//   Mt'_k = sum_{l<=k} C(k,l) z0^{k-l} 2^{-l} Mt_l,  z0 = (c_child - c)/r'.
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_m2m(TreeView tv, int first, int p, cpx<T>* __restrict__ M) {
+    const int c = first + blockIdx.x;
+    if (tv.child[c] < 0) return;
+    const int k = threadIdx.x;
+    if (k > p) return;
+    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int q = 0; q < 4; ++q) {
+        const int cc = tv.child[c] + q;
+        if (tv.npc[cc] == 0) continue;
+        const cpx<T> z0 = {(T)((q & 1) ? 0.5 : -0.5), (T)((q >> 1) ? 0.5 : -0.5)};
+        const cpx<T>* src = M + (size_t)cc * (p + 1) * 3;
+        cpx<T> pw = {1, 0};
+        T binom = 1, sc = (T)ldexp(1.0, -k);
+        for (int l = k; l >= 0; --l) {
+            const cpx<T> f = cscale(pw, binom * sc);
+            for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[l * 3 + ch]));
+            binom = binom * (T)l / (T)(k - l + 1);
+            sc *= (T)2;
+            pw = cmul(pw, z0);
+        }
+    }
+    cpx<T>* out = M + ((size_t)c * (p + 1) + k) * 3;
+    for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+}
+
+// ---------------------------------------------------------------- downward
+struct DownLevel {
+    int solve;             // 1: target boxes are the source boxes of level l
+    int l;
+    int first;             // solve: first box of level l
+    long long i0, j0;      // render: rectangle of target boxes at level l
+    int wl;
+    long long pi0, pj0;    // render: rectangle at level l-1
+    int pwl;
+    int off, poff;         // render: offsets of levels l and l-1
+    unsigned long long* stats;  // optional work counters (see kStat*)
+};
+
+// Incoming-from-outgoing (Eq. i-f-o), scaled, lane k = output index:
+//   Lt_k += (-1)^k sum_m c(k,m) w^{k+m} Mt_m,  c(k,m) = (k+m-1)!/(k! m!),
+//   w = r / (c_target - c_source); the k = m = 0 term is -log(c_t - c_s).
+template <typename T>
+__device__ inline void m2l_lane(cpx<T> acc[3], const cpx<T>* __restrict__ src, int p, int k,
+                                cpx<T> w, cpx<T> logd) {
+    cpx<T> pw = cpow(w, k);
+    const T sign = (k & 1) ? T(-1) : T(1);
+    T coef = k == 0 ? T(0) : T(1) / (T)k;
+    for (int m = 0; m <= p; ++m) {
+        cpx<T> t;
+        if (k == 0 && m == 0) {
+            t = {-logd.re, -logd.im};
+            coef = T(1);
+        } else {
+            t = cscale(pw, sign * coef);
+            coef = coef * (T)(k + m) / (T)(m + 1);
+        }
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(t, src[m * 3 + ch]));
+        pw = cmul(pw, w);
+    }
+}
+
+// Incoming-from-source of one piece (App. E.10, E.11), scaled, lane k.
+// A, B: piece ends relative to the box centre in units of r; zA = 1/A,
+// zB = 1/B; Lam = Log(B/A) (continuous branch: a chord seen from a point
+// off its line subtends less than pi).
+//   k = 0: -qs [|a| (log r + log A) + wbar r B Lam - |a|]  - i qm Lam
+//   k = 1:  qs wbar r Lam                               + i qm (zB - zA)
+//   k > 1:  qs wbar r (zA^{k-1} - zB^{k-1})/(k(k-1))    + i qm (zB^k - zA^k)/k
+template <typename T>
+__device__ inline void p2l_lane(cpx<T> acc[3], const PieceView& pv, int e, double cx, double cy,
+                                double r, int k) {
+    const double inv_r = 1.0 / r;
+    const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
+    const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
+    const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
+    const T len = (T)pv.len[e], rr = (T)r;
+    const cpx<T> Lam = clog(cmul(B, cpx<T>{A.re, -A.im}));
+    cpx<T> s, m;
+    if (k == 0) {
+        const cpx<T> lA = clog(A);
+        const cpx<T> t1 = {len * ((T)log(r) + lA.re), len * lA.im};
+        const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
+        s = {-(t1.re + t2.re - len), -(t1.im + t2.im)};
+        m = {Lam.im, -Lam.re};
+    } else {
+        const cpx<T> zA = cinv(A), zB = cinv(B);
+        if (k == 1) {
+            s = cmul(wbar, cscale(Lam, rr));
+            const cpx<T> d = csub(zB, zA);
+            m = {-d.im, d.re};
+        } else {
+            const cpx<T> a1 = cpow(zA, k - 1), b1 = cpow(zB, k - 1);
+            s = cmul(wbar, cscale(csub(a1, b1), rr / (T)(k * (k - 1))));
+            const cpx<T> d = cscale(csub(cmul(b1, zB), cmul(a1, zA)), T(1) / (T)k);
+            m = {-d.im, d.re};
+        }
+    }
+    const T* w = weights<T>(pv);
+    for (int ch = 0; ch < 3; ++ch) {
+        const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
+        acc[ch] = cadd(acc[ch], cadd(cscale(s, qs), cscale(m, qm)));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
+       cpx<T>* __restrict__ L, int* __restrict__ nset) {
+    __shared__ int sPN[9];
+    const int lane = threadIdx.x;
+    const int l = dl.l;
+    long long ti, tj;
+    int own, par;
+    if (dl.solve) {
+        own = dl.first + blockIdx.x;
+        if (tv.child[own] < 0 && tv.nend[own] == tv.nbeg[own]) return;  // no targets
+        ti = tv.ix[own];
+        tj = tv.iy[own];
+        par = tv.parent[own];
+    } else {
+        const int b = blockIdx.x;
+        ti = dl.i0 + b % dl.wl;
+        tj = dl.j0 + b / dl.wl;
+        own = dl.off + b;
+        par = dl.poff + (int)((ti >> 1) - dl.pi0) + (int)((tj >> 1) - dl.pj0) * dl.pwl;
+    }
+    if (lane < 9) sPN[lane] = nset[(size_t)par * 9 + lane];
+    __syncthreads();
+    if (lane < 9) {
+        const long long px = ti + (lane % 3) - 1, py = tj + (lane / 3) - 1;
+        int c = -1;
+        const long long lim = 1LL << l;
+        if (px >= 0 && py >= 0 && px < lim && py < lim) {
+            const int slot = (int)((px >> 1) - (ti >> 1) + 1) + 3 * (int)((py >> 1) - (tj >> 1) + 1);
+            c = sPN[slot];
+            if (c >= 0 && tv.lvl[c] == l - 1 && tv.child[c] >= 0)
+                c = tv.child[c] + (int)(px & 1) + 2 * (int)(py & 1);
+        }
+        nset[(size_t)own * 9 + lane] = c;
+    }
+    const int k = lane;
+    if (k > p) return;
+    const double r = half_width(tv, l);
+    double cx, cy;
+    center_of(tv, l, ti, tj, cx, cy);
+    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    // incoming-from-incoming from the parent (Eq. i-f-i), scaled:
+    //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
+    {
+        const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
+        const cpx<T>* src = L + (size_t)par * (p + 1) * 3;
+        cpx<T> pw = {1, 0};
+        T binom = 1;
+        const T sc = (T)ldexp(1.0, -k);
+        for (int m = k; m <= p; ++m) {
+            const cpx<T> f = cscale(pw, binom * sc);
+            for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
+            binom = binom * (T)(m + 1) / (T)(m + 1 - k);
+            pw = cmul(pw, z0);
+        }
+    }
+    // interaction list
+    const double log2r = log(2.0 * r);
+    for (int s = 0; s < 9; ++s) {
+        const int c = sPN[s];
+        if (c < 0 || tv.lvl[c] != l - 1 || tv.child[c] < 0) continue;
+        const long long ppx = (ti >> 1) + (s % 3) - 1, ppy = (tj >> 1) + (s / 3) - 1;
+        for (int q = 0; q < 4; ++q) {
+            const int d = tv.child[c] + q;
+            const long long dx = 2 * ppx + (q & 1) - ti, dy = 2 * ppy + (q >> 1) - tj;
+            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+            if (tv.npc[d] == 0) continue;
+            // c_target - c_source = -(dx, dy) * 2r
+            const double ddx = -(double)dx, ddy = -(double)dy;
+            const double inv = 1.0 / (2.0 * (ddx * ddx + ddy * ddy));
+            const cpx<T> w = {(T)(ddx * inv), (T)(-ddy * inv)};  // r / d
+            const cpx<T> logd = {(T)(log2r + 0.5 * log(ddx * ddx + ddy * ddy)),
+                                 (T)atan2(ddy, ddx)};
+            m2l_lane<T>(acc, M + (size_t)d * (p + 1) * 3, p, k, w, logd);
+            if (dl.stats && k == 0) atomicAdd(dl.stats + kStatM2L, 1ULL);
+        }
+    }
+    // bigger separated list: coarser source leaves that do not touch us
+    for (int s = 0; s < 9; ++s) {
+        const int c = sPN[s];
+        if (c < 0 || (tv.lvl[c] == l - 1 && tv.child[c] >= 0)) continue;
+        bool dup = false;
+        for (int s2 = 0; s2 < s; ++s2) dup |= (sPN[s2] == c);
+        if (dup || tv.npc[c] == 0 || touches(tv, c, l, ti, tj)) continue;
+        for (int e = tv.pbeg[c]; e < tv.pend[c]; ++e) p2l_lane<T>(acc, pv, e, cx, cy, r, k);
+        if (dl.stats && k == 0)
+            atomicAdd(dl.stats + kStatP2L, (unsigned long long)(tv.pend[c] - tv.pbeg[c]));
+    }
+    if (dl.stats && k == 0) atomicAdd(dl.stats + kStatL2L, 1ULL);
+    cpx<T>* out = L + ((size_t)own * (p + 1) + k) * 3;
+    for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+}
+
+template <typename T>
+__global__ void k_init_root(int p, cpx<T>* __restrict__ L, int* __restrict__ nset) {
+    const int t = threadIdx.x;
+    if (t < 9) nset[t] = (t == 4) ? 0 : -1;
+    for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[i] = {0, 0};
+}
+
+// -------------------------------------------------------------- leaf pass
+struct LeafArgs {
+    int solve;
+    int L;                   // target leaf level
+    // render
+    long long i0, j0;
+    int wl, off;
+    double vcx, vcy, vw, vh;
+    int W, H;
+    int out_f64;
+    void* out;
+    // solve
+    const int* target_leaves;
+    const double *node_x, *node_y;
+    double* y;
+    int N;
+    double near2;            // (near_fp64)^2, FP32 only
+    unsigned long long* stats;  // optional work counters
+};
+
+template <typename T, int NT>
+struct LeafShared {
+    T px[NT], py[NT], tx[NT], ty[NT], len[NT];
+    T w[6][NT];
+    int pid[NT];
+    int U[kUCap], Upre[kUCap + 1], W[kWCap], stack[kSCap];
+    int nU, nW, nS, more;
+};
+
+__device__ inline int first_true_col(const LeafArgs& a, double X0, double sideL, long long ti) {
+    int lo = 0, hi = a.W;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cell_coord(pixel_x(a.vcx, a.vw, a.W, mid), X0, sideL) >= ti) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+__device__ inline int first_true_row(const LeafArgs& a, double Y0, double sideL, long long tj) {
+    int lo = 0, hi = a.H;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cell_coord(pixel_y(a.vcy, a.vh, a.H, mid), Y0, sideL) <= tj) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
+k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ M,
+       const cpx<T>* __restrict__ Lc, const int* __restrict__ nset) {
+    __shared__ LeafShared<T, NT> sh;
+    const int tid = threadIdx.x;
+    long long ti, tj;
+    int own;
+    int n_targets, base_pos = 0;
+    int k_lo = 0, nx = 1, r_lo = 0;
+    const int Lv = a.L;
+    if (a.solve) {
+        own = a.target_leaves[blockIdx.x];
+        ti = tv.ix[own];
+        tj = tv.iy[own];
+        base_pos = tv.nbeg[own];
+        n_targets = tv.nend[own] - base_pos;
+    } else {
+        const int b = blockIdx.x;
+        ti = a.i0 + b % a.wl;
+        tj = a.j0 + b / a.wl;
+        own = a.off + b;
+        const double sideL = ldexp(tv.side, -Lv);
+        k_lo = first_true_col(a, tv.X0, sideL, ti);
+        const int k_hi = first_true_col(a, tv.X0, sideL, ti + 1);
+        r_lo = first_true_row(a, tv.Y0, sideL, tj);
+        const int r_hi = first_true_row(a, tv.Y0, sideL, tj - 1);
+        nx = k_hi - k_lo;
+        n_targets = nx > 0 ? nx * max(r_hi - r_lo, 0) : 0;
+    }
+    const int l = a.solve ? tv.lvl[own] : Lv;
+    const double r = half_width(tv, l);
+    double cx, cy;
+    center_of(tv, l, ti, tj, cx, cy);
+    const T* wts = weights<T>(pv);
+    const cpx<T>* loc = Lc + (size_t)own * (p + 1) * 3;
+
+    for (int tbase = 0; tbase < n_targets; tbase += NT) {
+        const int tgt = tbase + tid;
+        const bool active = tgt < n_targets;
+        double x = cx, y = cy;
+        int out_idx = 0;
+        if (active) {
+            if (a.solve) {
+                const int node = tv.node_perm[base_pos + tgt];
+                x = a.node_x[node];
+                y = a.node_y[node];
+                out_idx = node;
+            } else {
+                const int col = k_lo + tgt % nx, row = r_lo + tgt / nx;
+                x = pixel_x(a.vcx, a.vw, a.W, col);
+                y = pixel_y(a.vcy, a.vh, a.H, row);
+                out_idx = row * a.W + col;
+            }
+        }
+        const T xr = (T)(x - cx), yr = (T)(y - cy);
+        T accE[3] = {0, 0, 0}, accP[3] = {0, 0, 0};
+        double acc64[3] = {0, 0, 0};
+        // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
+        if (l >= 2) {
+            const cpx<T> z = {(T)((x - cx) / r), (T)((y - cy) / r)};
+            for (int ch = 0; ch < 3; ++ch) {
+                cpx<T> s = loc[p * 3 + ch];
+                for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
+                accE[ch] += s.re;
+            }
+        }
+        if (a.stats && tid == 0) {
+            const unsigned long long na = (unsigned long long)min(NT, n_targets - tbase);
+            if (l >= 2) atomicAdd(a.stats + kStatL2P, na);
+            if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
+        }
+        // near-set traversal, in rounds bounded by the list capacities
+        if (tid == 0) {
+            sh.nS = 0;
+            for (int s = 0; s < 9; ++s) {
+                const int c = nset[(size_t)own * 9 + s];
+                bool dup = c < 0;
+                for (int s2 = 0; s2 < s && !dup; ++s2) dup = nset[(size_t)own * 9 + s2] == c;
+                if (!dup && tv.npc[c] > 0) sh.stack[sh.nS++] = c;
+            }
+        }
+        __syncthreads();
+        for (;;) {
+            if (tid == 0) {
+                int nU = 0, nW = 0;
+                while (sh.nS > 0 && nU < kUCap && nW + 4 <= kWCap) {
+                    const int c = sh.stack[--sh.nS];
+                    if (tv.child[c] < 0) {
+                        sh.Upre[nU] = 0;
+                        sh.U[nU++] = c;
+                        continue;
+                    }
+                    for (int q = 0; q < 4; ++q) {
+                        const int d = tv.child[c] + q;
+                        if (tv.npc[d] == 0) continue;
+                        if (touches(tv, d, l, ti, tj)) {
+                            if (sh.nS < kSCap) sh.stack[sh.nS++] = d;
+                        } else {
+                            sh.W[nW++] = d;
+                        }
+                    }
+                }
+                int acc = 0;
+                for (int u = 0; u < nU; ++u) {
+                    sh.Upre[u] = acc;
+                    acc += tv.pend[sh.U[u]] - tv.pbeg[sh.U[u]];
+                }
+                sh.Upre[nU] = acc;
+                sh.nU = nU;
+                sh.nW = nW;
+                sh.more = sh.nS > 0;
+            }
+            __syncthreads();
+            // copy the round's shared scalars: thread 0 rewrites them only after
+            // the closing barrier of this round
+            const int nU = sh.nU, nW = sh.nW, more = sh.more;
+            if (a.stats && tid == 0) {
+                const unsigned long long na = (unsigned long long)min(NT, n_targets - tbase);
+                atomicAdd(a.stats + kStatM2P, na * nW);
+                atomicAdd(a.stats + kStatP2P, na * (unsigned long long)sh.Upre[nU]);
+            }
+            // target-from-outgoing (Eq. t-f-o), scaled:
+            //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
+            if (active) {
+                for (int u = 0; u < nW; ++u) {
+                    const int d = sh.W[u];
+                    const int ld = tv.lvl[d];
+                    const double rd = half_width(tv, ld);
+                    double dcx, dcy;
+                    center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
+                    const cpx<T> rel = {(T)((x - dcx) / rd), (T)((y - dcy) / rd)};
+                    const cpx<T> z = cinv(rel);
+                    const cpx<T> lg = clog(rel);
+                    const T lr = (T)log(rd);
+                    const cpx<T>* src = M + (size_t)d * (p + 1) * 3;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        cpx<T> s = cscale(src[p * 3 + ch], T(1) / (T)p);
+                        for (int kk = p - 1; kk >= 1; --kk)
+                            s = cadd(cmul(s, z), cscale(src[kk * 3 + ch], T(1) / (T)kk));
+                        s = cmul(s, z);
+                        const cpx<T> m0 = src[ch];
+                        // Re(-(lr + lg) * m0)
+                        accE[ch] += s.re - ((lr + lg.re) * m0.re - lg.im * m0.im);
+                    }
+                }
+            }
+            // target-from-source (App. D) over the pieces of the near leaves
+            const int total = sh.Upre[nU];
+            for (int pbase = 0; pbase < total; pbase += NT) {
+                __syncthreads();
+                const int g = pbase + tid;
+                if (g < total) {
+                    int lo = 0, hi = nU - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sh.Upre[mid] <= g) lo = mid; else hi = mid - 1;
+                    }
+                    const int e = tv.pbeg[sh.U[lo]] + (g - sh.Upre[lo]);
+                    sh.px[tid] = (T)(pv.x0[e] - cx);
+                    sh.py[tid] = (T)(pv.y0[e] - cy);
+                    sh.tx[tid] = (T)pv.tx[e];
+                    sh.ty[tid] = (T)pv.ty[e];
+                    sh.len[tid] = (T)pv.len[e];
+                    for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
+                    sh.pid[tid] = e;
+                }
+                __syncthreads();
+                if (active) {
+                    const int m = min(NT, total - pbase);
+                    for (int j = 0; j < m; ++j) {
+                        const T dx = sh.px[j] - xr, dy = sh.py[j] - yr;
+                        if (sizeof(T) == 4) {
+                            const T xi1 = dx * sh.tx[j] + dy * sh.ty[j];
+                            const T h = dy * sh.tx[j] - dx * sh.ty[j];
+                            const T xi2 = xi1 + sh.len[j];
+                            const T dd = xi1 > 0 ? xi1 * xi1 + h * h
+                                                 : (xi2 < 0 ? xi2 * xi2 + h * h : h * h);
+                            if ((double)dd < a.near2 * (double)sh.len[j] * (double)sh.len[j]) {
+                                // near-singular pair: closed form in FP64
+                                const int e = sh.pid[j];
+                                double il, th;
+                                chord_log_theta<double>(pv.x0[e] - x, pv.y0[e] - y, pv.tx[e],
+                                                        pv.ty[e], pv.len[e], il, th);
+                                for (int ch = 0; ch < 3; ++ch)
+                                    acc64[ch] += il * pv.w64[(size_t)ch * pv.n + e] +
+                                                 th * pv.w64[(size_t)(3 + ch) * pv.n + e];
+                                if (a.stats) atomicAdd(a.stats + kStatP2P64, 1ULL);
+                                continue;
+                            }
+                        }
+                        T il, th;
+                        chord_log_theta<T>(dx, dy, sh.tx[j], sh.ty[j], sh.len[j], il, th);
+                        for (int ch = 0; ch < 3; ++ch)
+                            accP[ch] += il * sh.w[ch][j] + th * sh.w[3 + ch][j];
+                    }
+                }
+            }
+            __syncthreads();
+            if (!more) break;
+        }
+        if (active) {
+            for (int ch = 0; ch < 3; ++ch) {
+                const double u = ((double)accE[ch] - (double)accP[ch] - acc64[ch]) / kTwoPi;
+                if (a.solve) {
+                    a.y[(size_t)ch * a.N + out_idx] = u;
+                } else if (a.out_f64) {
+                    static_cast<double*>(a.out)[(size_t)out_idx * 3 + ch] = u;
+                } else {
+                    static_cast<float*>(a.out)[(size_t)out_idx * 3 + ch] = (float)u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Self-segment correction at the nodes: the FMM summed every piece of the
+// node's own segment with the regular closed form; replace that by the
+// singular rule (App. C.1, D.3, D.4):
+//   y += [ (l - e1 ln e1 - e2 ln e2) sigma_bar + sum_pieces(il qs + th qm) ] / 2pi
+__global__ void __launch_bounds__(256)
+k_self_correct(int N, const double* __restrict__ nx, const double* __restrict__ ny,
+               const int* __restrict__ self_seg, const double* __restrict__ tstar, int s, int g,
+               const double* __restrict__ Pi, const double* __restrict__ kappa,
+               const double* __restrict__ ell, const double* __restrict__ sigma,
+               const double* __restrict__ mu, const int* __restrict__ spb,
+               const int* __restrict__ spi, PieceView pv, double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int j = self_seg[i];
+    const int panel = j / s, jj = j - panel * s;
+    const double* pr = Pi + (size_t)jj * g;
+    double sb[3] = {0, 0, 0}, mb[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+        for (int q = 0; q < g; ++q) {
+            if (sigma) sb[c] += pr[q] * sigma[(size_t)c * N + (size_t)panel * g + q];
+            if (mu) mb[c] += pr[q] * mu[(size_t)c * N + (size_t)panel * g + q];
+        }
+    }
+    const double x = nx[i], yy = ny[i];
+    double sil = 0, sth = 0;
+    for (int t = spb[j]; t < spb[j + 1]; ++t) {
+        const int e = spi[t];
+        double il, th;
+        chord_log_theta<double>(pv.x0[e] - x, pv.y0[e] - yy, pv.tx[e], pv.ty[e], pv.len[e], il, th);
+        sil += il;
+        sth += th;
+    }
+    const double g2 = self_segment_2pi_G(ell[j], tstar[i]);
+    const double kap = kappa[j];
+    for (int c = 0; c < 3; ++c)
+        y[(size_t)c * N + i] += (g2 * sb[c] + sil * kap * sb[c] + sth * kap * mb[c]) / kTwoPi;
+}
+
+TreeView tree_view(const FmmState& f) {
+    return {f.n_cells, f.X0, f.Y0, f.side, f.lvl.p, f.child.p, f.parent.p, f.pbeg.p,
+            f.pend.p, f.npc.p, f.nbeg.p, f.nend.p, f.node_perm.p, f.ix.p, f.iy.p};
+}
+PieceView piece_view(const FmmState& f) {
+    return {f.n_pieces, f.px0.p, f.py0.p, f.px1.p, f.py1.p, f.ptx.p, f.pty.p, f.plen.p, f.pseg.p,
+            f.w64.p, f.w32.p};
+}
+
+template <typename T>
+struct Bufs;
+template <>
+struct Bufs<double> {
+    static DevBuf<double>& M(FmmState& f) { return f.M64; }
+    static DevBuf<double>& L(FmmState& f) { return f.L64; }
+    static DevBuf<double>& TL(FmmState& f) { return f.TL64; }
+};
+template <>
+struct Bufs<float> {
+    static DevBuf<float>& M(FmmState& f) { return f.M32; }
+    static DevBuf<float>& L(FmmState& f) { return f.L32; }
+    static DevBuf<float>& TL(FmmState& f) { return f.TL32; }
+};
+
+template <typename T>
+cpx<T>* as_cpx(DevBuf<T>& b) {
+    return reinterpret_cast<cpx<T>*>(b.p);
+}
+
+// Piece weights and the upward pass for the given densities.
+template <typename T>
+void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, int p,
+            hipStream_t st) {
+    const Geometry& G = s.geo;
+    f.w64.alloc((size_t)6 * f.n_pieces);
+    if (sizeof(T) == 4) f.w32.alloc((size_t)6 * f.n_pieces);
+    launch_chord_weights(f.n_pieces, f.pseg.p, G.s, G.g, G.N, s.Pi.p, s.seg_kappa.p, sigma, mu,
+                         f.w64.p, sizeof(T) == 4 ? f.w32.p : nullptr, st);
+    DevBuf<T>& M = Bufs<T>::M(f);
+    M.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
+    const TreeView tv = tree_view(f);
+    const PieceView pv = piece_view(f);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(f.n_cells), dim3(kWave), 0, st, tv, pv, p, as_cpx(M));
+    DC_HIP(hipGetLastError());
+    for (int l = f.depth - 1; l >= 0; --l) {
+        const int first = f.level_start[l], cnt = f.level_start[l + 1] - first;
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL(k_m2m<T>, dim3(cnt), dim3(kWave), 0, st, tv, first, p, as_cpx(M));
+        DC_HIP(hipGetLastError());
+    }
+}
+
+template <typename T>
+void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, double* y,
+                   const dc_eval_opts& o, hipStream_t st) {
+    const int p = o.p;
+    upward<T>(s, f, sigma, mu, p, st);
+    f.up_valid = false;  // the cache now holds these densities, not the scene's
+    DevBuf<T>& L = Bufs<T>::L(f);
+    L.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
+    f.nsetS.alloc((size_t)f.n_cells * 9);
+    const TreeView tv = tree_view(f);
+    const PieceView pv = piece_view(f);
+    DevBuf<T>& M = Bufs<T>::M(f);
+    hipLaunchKernelGGL(k_init_root<T>, dim3(1), dim3(kWave), 0, st, p, as_cpx(L), f.nsetS.p);
+    DC_HIP(hipGetLastError());
+    for (int l = 1; l <= f.depth; ++l) {
+        DownLevel dl{};
+        dl.solve = 1;
+        dl.l = l;
+        dl.first = f.level_start[l];
+        const int cnt = f.level_start[l + 1] - dl.first;
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL(k_down<T>, dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p, as_cpx(M),
+                           as_cpx(L), f.nsetS.p);
+        DC_HIP(hipGetLastError());
+    }
+    LeafArgs a{};
+    a.solve = 1;
+    a.target_leaves = f.target_leaves.p;
+    a.node_x = s.node_x.p;
+    a.node_y = s.node_y.p;
+    a.y = y;
+    a.N = s.geo.N;
+    a.near2 = o.near_fp64 * o.near_fp64;
+    if (f.n_target_leaves > 0) {
+        hipLaunchKernelGGL((k_leaf<T, kWave>), dim3(f.n_target_leaves), dim3(kWave), 0, st, tv, pv,
+                           a, p, as_cpx(M), as_cpx(L), f.nsetS.p);
+        DC_HIP(hipGetLastError());
+    }
+    const Geometry& G = s.geo;
+    hipLaunchKernelGGL(k_self_correct, dim3((G.N + 255) / 256), dim3(256), 0, st, G.N,
+                       s.node_x.p, s.node_y.p, s.node_self.p, s.node_tstar.p, G.s, G.g, s.Pi.p,
+                       s.seg_kappa.p, s.seg_ell.p, sigma, mu, f.seg_piece_beg.p,
+                       f.seg_piece_idx.p, pv, y);
+    DC_HIP(hipGetLastError());
+}
+
+template <typename T>
+void render_t(dc_scene_s& s, FmmState& f, const dc_viewport& vp, const dc_eval_opts& o,
+              int out_dtype, void* out, hipStream_t st) {
+    const int p = o.p;
+    // Target tile level: boxes no wider than tile_px pixel pitches hold at
+    // most tile_px x tile_px pixel centres (rounding of the centres can add a
+    // row or column now and then; the leaf kernel loops over extra targets).
+    const double pitch = std::min(vp.width / vp.W, vp.height / vp.H);
+    int Lt = 2;
+    while (std::ldexp(f.side, -Lt) > o.tile_px * pitch * (1.0 + 1e-12)) {
+        ++Lt;
+        DC_REQUIRE(Lt <= 60, "viewport pixels are too small for the quadtree root");
+    }
+    std::vector<long long> i0(Lt + 1), i1(Lt + 1), j0(Lt + 1), j1(Lt + 1);
+    std::vector<int> off(Lt + 2);
+    off[0] = 0;
+    const double xa = pixel_x(vp.cx, vp.width, vp.W, 0), xb = pixel_x(vp.cx, vp.width, vp.W, vp.W - 1);
+    const double ya = pixel_y(vp.cy, vp.height, vp.H, vp.H - 1), yb = pixel_y(vp.cy, vp.height, vp.H, 0);
+    for (int l = 0; l <= Lt; ++l) {
+        const double sl = std::ldexp(f.side, -l);
+        i0[l] = cell_coord(xa, f.X0, sl);
+        i1[l] = cell_coord(xb, f.X0, sl);
+        j0[l] = cell_coord(ya, f.Y0, sl);
+        j1[l] = cell_coord(yb, f.Y0, sl);
+        const long long lim = 1LL << l;
+        DC_REQUIRE(i0[l] >= 0 && j0[l] >= 0 && i1[l] < lim && j1[l] < lim,
+                   "viewport extends outside the scene's quadtree root (enlarge the domain "
+                   "in dc_scene_opts)");
+        const long long cnt = (i1[l] - i0[l] + 1) * (j1[l] - j0[l] + 1);
+        DC_REQUIRE(off[l] + cnt < (1LL << 31), "viewport needs too many target boxes");
+        off[l + 1] = off[l] + (int)cnt;
+    }
+    if (f.timing) DC_HIP(hipEventRecord(f.ev[0], st));
+    if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
+        upward<T>(s, f, s.d_sigma.p, s.d_mu.p, p, st);
+        f.up_valid = true;
+        f.up_p = p;
+        f.up_prec = (int)sizeof(T);
+    }
+    DevBuf<T>& TL = Bufs<T>::TL(f);
+    const size_t need = (size_t)off[Lt + 1] * (p + 1) * 3 * 2;
+    if (TL.n < need) TL.alloc(need);
+    if (f.Tnset.n < (size_t)off[Lt + 1] * 9) f.Tnset.alloc((size_t)off[Lt + 1] * 9);
+    const TreeView tv = tree_view(f);
+    const PieceView pv = piece_view(f);
+    DevBuf<T>& M = Bufs<T>::M(f);
+    if (f.timing) DC_HIP(hipEventRecord(f.ev[1], st));
+    hipLaunchKernelGGL(k_init_root<T>, dim3(1), dim3(kWave), 0, st, p, as_cpx(TL), f.Tnset.p);
+    DC_HIP(hipGetLastError());
+    for (int l = 1; l <= Lt; ++l) {
+        DownLevel dl{};
+        dl.stats = f.stats;
+        dl.solve = 0;
+        dl.l = l;
+        dl.i0 = i0[l];
+        dl.j0 = j0[l];
+        dl.wl = (int)(i1[l] - i0[l] + 1);
+        dl.pi0 = i0[l - 1];
+        dl.pj0 = j0[l - 1];
+        dl.pwl = (int)(i1[l - 1] - i0[l - 1] + 1);
+        dl.off = off[l];
+        dl.poff = off[l - 1];
+        hipLaunchKernelGGL(k_down<T>, dim3(off[l + 1] - off[l]), dim3(kWave), 0, st, tv, pv, dl, p,
+                           as_cpx(M), as_cpx(TL), f.Tnset.p);
+        DC_HIP(hipGetLastError());
+    }
+    LeafArgs a{};
+    a.solve = 0;
+    a.L = Lt;
+    a.i0 = i0[Lt];
+    a.j0 = j0[Lt];
+    a.wl = (int)(i1[Lt] - i0[Lt] + 1);
+    a.off = off[Lt];
+    a.vcx = vp.cx;
+    a.vcy = vp.cy;
+    a.vw = vp.width;
+    a.vh = vp.height;
+    a.W = vp.W;
+    a.H = vp.H;
+    a.out_f64 = out_dtype == DC_OUT_F64;
+    a.out = out;
+    a.near2 = o.near_fp64 * o.near_fp64;
+    a.stats = f.stats;
+    const int nblk = off[Lt + 1] - off[Lt];
+    if (f.timing) DC_HIP(hipEventRecord(f.ev[2], st));
+    if (o.tile_px <= 8)
+        hipLaunchKernelGGL((k_leaf<T, 64>), dim3(nblk), dim3(64), 0, st, tv, pv, a, p, as_cpx(M),
+                           as_cpx(TL), f.Tnset.p);
+    else
+        hipLaunchKernelGGL((k_leaf<T, 256>), dim3(nblk), dim3(256), 0, st, tv, pv, a, p,
+                           as_cpx(M), as_cpx(TL), f.Tnset.p);
+    DC_HIP(hipGetLastError());
+    if (f.timing) {
+        DC_HIP(hipEventRecord(f.ev[3], st));
+        DC_HIP(hipEventSynchronize(f.ev[3]));
+        float ms[3];
+        for (int i = 0; i < 3; ++i) DC_HIP(hipEventElapsedTime(&ms[i], f.ev[i], f.ev[i + 1]));
+        f.tms[0] += ms[0];
+        f.tms[1] += ms[1];
+        f.tms[2] += ms[2];
+        f.tms[3] += (double)ms[0] + ms[1] + ms[2];
+        f.tcalls++;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    const int i = threadIdx.x;
+    if (i < n) p[i] = 0ULL;
+}
+
+}  // namespace
+
+std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s) {
+    auto f = std::make_unique<FmmState>();
+    const Tree& T = s.tree;
+    f->n_cells = T.n_cells;
+    f->depth = T.depth;
+    f->X0 = T.X0;
+    f->Y0 = T.Y0;
+    f->side = T.side;
+    f->level_start = T.level_start;
+    f->lvl.upload(T.lvl);
+    f->child.upload(T.child);
+    f->parent.upload(T.parent);
+    f->pbeg.upload(T.pbeg);
+    f->pend.upload(T.pend);
+    f->npc.upload(T.npc);
+    f->nbeg.upload(T.nbeg);
+    f->nend.upload(T.nend);
+    f->node_perm.upload(T.node_perm);
+    f->ix.upload(T.ix);
+    f->iy.upload(T.iy);
+    const size_t np = T.pseg.size();
+    f->n_pieces = (int)np;
+    std::vector<double> tx(np), ty(np), len(np);
+    for (size_t e = 0; e < np; ++e) {
+        const double ax = T.px1[e] - T.px0[e], ay = T.py1[e] - T.py0[e];
+        len[e] = std::hypot(ax, ay);
+        tx[e] = ax / len[e];
+        ty[e] = ay / len[e];
+    }
+    f->px0.upload(T.px0);
+    f->py0.upload(T.py0);
+    f->px1.upload(T.px1);
+    f->py1.upload(T.py1);
+    f->ptx.upload(tx);
+    f->pty.upload(ty);
+    f->plen.upload(len);
+    f->pseg.upload(T.pseg);
+    // segment -> pieces
+    const int S = s.geo.S;
+    std::vector<int> beg(S + 1, 0), idx(np);
+    for (size_t e = 0; e < np; ++e) beg[T.pseg[e] + 1]++;
+    for (int j = 0; j < S; ++j) beg[j + 1] += beg[j];
+    std::vector<int> fill(beg.begin(), beg.end() - 1);
+    for (size_t e = 0; e < np; ++e) idx[fill[T.pseg[e]]++] = (int)e;
+    f->seg_piece_beg.upload(beg);
+    f->seg_piece_idx.upload(idx);
+    std::vector<int> tl;
+    for (int c = 0; c < T.n_cells; ++c)
+        if (T.child[c] < 0 && T.nend[c] > T.nbeg[c]) tl.push_back(c);
+    f->n_target_leaves = (int)tl.size();
+    f->target_leaves.upload(tl);
+    return f;
+}
+
+void fmm_invalidate(FmmState& f) { f.up_valid = false; }
+
+void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
+                       dc_work_counts* counts, hipStream_t st) {
+    FmmState& f = *s.fmm;
+    DevBuf<unsigned long long> stats;
+    stats.alloc(kNStat);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, stats.p, (int)kNStat);
+    DC_HIP(hipGetLastError());
+    DevBuf<float> scratch;
+    scratch.alloc((size_t)vp.W * vp.H * 3);
+    const bool timing = f.timing;
+    f.timing = false;
+    f.stats = stats.p;
+    try {
+        fmm_render(s, vp, o, DC_OUT_F32, scratch.p, st);
+    } catch (...) {
+        f.stats = nullptr;
+        f.timing = timing;
+        throw;
+    }
+    f.stats = nullptr;
+    f.timing = timing;
+    unsigned long long h[kNStat];
+    DC_HIP(hipMemcpyAsync(h, stats.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    counts->p2p_pairs = h[kStatP2P];
+    counts->p2p_fp64_pairs = h[kStatP2P64];
+    counts->m2p_pairs = h[kStatM2P];
+    counts->l2p_targets = h[kStatL2P];
+    counts->m2l_pairs = h[kStatM2L];
+    counts->p2l_pairs = h[kStatP2L];
+    counts->l2l_boxes = h[kStatL2L];
+    counts->leaf_boxes = h[kStatLeaf];
+    counts->pieces = (unsigned long long)f.n_pieces;
+    counts->source_cells = (unsigned long long)f.n_cells;
+    const double pitch = std::min(vp.width / vp.W, vp.height / vp.H);
+    int Lt = 2;
+    while (std::ldexp(f.side, -Lt) > o.tile_px * pitch * (1.0 + 1e-12)) ++Lt;
+    counts->levels = Lt + 1;
+    counts->p = o.p;
+}
+
+void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, double* y,
+                     const dc_eval_opts& o, hipStream_t st) {
+    if (o.precision == DC_PREC_F32)
+        apply_nodes_t<float>(s, *s.fmm, sigma, mu, y, o, st);
+    else
+        apply_nodes_t<double>(s, *s.fmm, sigma, mu, y, o, st);
+}
+
+void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int out_dtype,
+                void* out, hipStream_t st) {
+    if (o.precision == DC_PREC_F32)
+        render_t<float>(s, *s.fmm, vp, o, out_dtype, out, st);
+    else
+        render_t<double>(s, *s.fmm, vp, o, out_dtype, out, st);
+}
+
+}  // namespace dc

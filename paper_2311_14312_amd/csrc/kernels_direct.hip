@@ -1,0 +1,286 @@
+// Direct-sum kernels (brute-force evaluation, Sec. 5.5), density
+// interpolation onto chords (Sec. 5.2) and the vector kernels of GMRES.
+#include "kernels.h"
+
+namespace dc {
+
+namespace {
+
+constexpr int kNT = 256;
+
+__global__ void __launch_bounds__(kNT)
+k_chord_weights(int n, const int* __restrict__ seg, int s, int g, int N,
+                const double* __restrict__ Pi, const double* __restrict__ kappa,
+                const double* __restrict__ sigma, const double* __restrict__ mu,
+                double* __restrict__ w64, float* __restrict__ w32) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int j = seg ? seg[e] : e;
+    const int panel = j / s, jj = j - panel * s;
+    const double* pr = Pi + (size_t)jj * g;
+    const double kap = kappa[j];
+    const size_t base = (size_t)panel * g;
+    for (int c = 0; c < 3; ++c) {
+        double vs = 0.0, vm = 0.0;
+        if (sigma)
+            for (int i = 0; i < g; ++i) vs += pr[i] * sigma[(size_t)c * N + base + i];
+        if (mu)
+            for (int i = 0; i < g; ++i) vm += pr[i] * mu[(size_t)c * N + base + i];
+        vs *= kap;
+        vm *= kap;
+        if (w64) {
+            w64[(size_t)c * n + e] = vs;
+            w64[(size_t)(3 + c) * n + e] = vm;
+        }
+        if (w32) {
+            w32[(size_t)c * n + e] = (float)vs;
+            w32[(size_t)(3 + c) * n + e] = (float)vm;
+        }
+    }
+}
+
+// One chord element staged in LDS.
+struct SegTile {
+    double x0[kNT], y0[kNT], tx[kNT], ty[kNT], len[kNT];
+    double w[6][kNT];
+};
+
+__device__ inline void stage_segments(SegTile& sh, const ChordsView& segs, const double* w,
+                                      int base) {
+    const int t = threadIdx.x;
+    const int j = base + t;
+    if (j < segs.n) {
+        sh.x0[t] = segs.x0[j];
+        sh.y0[t] = segs.y0[j];
+        sh.tx[t] = segs.tx[j];
+        sh.ty[t] = segs.ty[j];
+        sh.len[t] = segs.len[j];
+        for (int c = 0; c < 6; ++c) sh.w[c][t] = w[(size_t)c * segs.n + j];
+    }
+}
+
+// u(q_i) for every collocation node: sum over all segments of the chord
+// closed forms, except the node's own segment, which takes the singular
+// single layer of App. D.3 and a zero double layer (App. C.1, D.4).
+__global__ void __launch_bounds__(kNT)
+k_direct_nodes(NodesView nodes, ChordsView segs, const double* __restrict__ ell,
+               const double* __restrict__ kappa, const double* __restrict__ w,
+               double* __restrict__ out) {
+    __shared__ SegTile sh;
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const bool active = i < nodes.N;
+    double x = 0, y = 0, ts = 0;
+    int self = -1;
+    if (active) {
+        x = nodes.x[i];
+        y = nodes.y[i];
+        self = nodes.self_seg[i];
+        ts = nodes.tstar[i];
+    }
+    double acc[3] = {0, 0, 0};
+    for (int base = 0; base < segs.n; base += kNT) {
+        __syncthreads();
+        stage_segments(sh, segs, w, base);
+        __syncthreads();
+        if (!active) continue;
+        const int m = min(kNT, segs.n - base);
+        for (int t = 0; t < m; ++t) {
+            const int j = base + t;
+            if (j == self) {
+                // acc holds -2 pi u; Ghat_self = (l - e1 ln e1 - e2 ln e2)/(2 pi)
+                const double g2 = self_segment_2pi_G(ell[j], ts);
+                const double inv_k = 1.0 / kappa[j];
+                for (int c = 0; c < 3; ++c) acc[c] -= g2 * sh.w[c][t] * inv_k;
+                continue;
+            }
+            double il, th;
+            chord_log_theta<double>(sh.x0[t] - x, sh.y0[t] - y, sh.tx[t], sh.ty[t], sh.len[t],
+                                    il, th);
+            for (int c = 0; c < 3; ++c) acc[c] += il * sh.w[c][t] + th * sh.w[3 + c][t];
+        }
+    }
+    if (active)
+        for (int c = 0; c < 3; ++c) out[(size_t)c * nodes.N + i] = -acc[c] / kTwoPi;
+}
+
+__global__ void __launch_bounds__(kNT)
+k_direct_targets(TargetGrid grid, int use_grid, const double* __restrict__ pts, int n_pts,
+                 ChordsView segs, const double* __restrict__ w, int out_f64, void* out) {
+    __shared__ SegTile sh;
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const int n = use_grid ? grid.W * grid.H : n_pts;
+    const bool active = i < n;
+    double x = 0, y = 0;
+    if (active) {
+        if (use_grid) {
+            const int r = i / grid.W, k = i - r * grid.W;
+            x = pixel_x(grid.cx, grid.w, grid.W, k);
+            y = pixel_y(grid.cy, grid.h, grid.H, r);
+        } else {
+            x = pts[2 * (size_t)i];
+            y = pts[2 * (size_t)i + 1];
+        }
+    }
+    double acc[3] = {0, 0, 0};
+    for (int base = 0; base < segs.n; base += kNT) {
+        __syncthreads();
+        stage_segments(sh, segs, w, base);
+        __syncthreads();
+        if (!active) continue;
+        const int m = min(kNT, segs.n - base);
+        for (int t = 0; t < m; ++t) {
+            double il, th;
+            chord_log_theta<double>(sh.x0[t] - x, sh.y0[t] - y, sh.tx[t], sh.ty[t], sh.len[t],
+                                    il, th);
+            for (int c = 0; c < 3; ++c) acc[c] += il * sh.w[c][t] + th * sh.w[3 + c][t];
+        }
+    }
+    if (!active) return;
+    for (int c = 0; c < 3; ++c) {
+        const double u = -acc[c] / kTwoPi;
+        if (out_f64)
+            static_cast<double*>(out)[3 * (size_t)i + c] = u;
+        else
+            static_cast<float*>(out)[3 * (size_t)i + c] = (float)u;
+    }
+}
+
+// ------------------------------------------------------------------ GMRES
+// Fixed-order block reductions (no atomics): results do not depend on
+// scheduling.
+__device__ inline double block_sum(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = kNT / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+__global__ void __launch_bounds__(kNT)
+k_block_dots(const double* __restrict__ V, const double* __restrict__ w, int N,
+             double* __restrict__ dots, int k) {
+    __shared__ double red[kNT];
+    const int j = blockIdx.x, c = blockIdx.y;
+    const double* v = V + ((size_t)j * 3 + c) * N;
+    const double* ww = w + (size_t)c * N;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < N; i += kNT) acc += v[i] * ww[i];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) dots[(size_t)c * k + j] = s;
+}
+
+__global__ void __launch_bounds__(kNT)
+k_block_update(const double* __restrict__ V, int k, const double* __restrict__ h, int kcap,
+               double* __restrict__ w, int N) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= N) return;
+    double acc = w[(size_t)c * N + i];
+    for (int j = 0; j < k; ++j) acc -= V[((size_t)j * 3 + c) * N + i] * h[(size_t)c * kcap + j];
+    w[(size_t)c * N + i] = acc;
+}
+
+__global__ void __launch_bounds__(kNT)
+k_scale3(const double* __restrict__ x, const double* __restrict__ alpha,
+         double* __restrict__ y, int N) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i < N) y[(size_t)c * N + i] = alpha[c] * x[(size_t)c * N + i];
+}
+
+__global__ void __launch_bounds__(kNT)
+k_combine(const double* __restrict__ V, int k, const double* __restrict__ y, int kcap,
+          double* __restrict__ x, int N) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= N) return;
+    double acc = x[(size_t)c * N + i];
+    for (int j = 0; j < k; ++j) acc += V[((size_t)j * 3 + c) * N + i] * y[(size_t)c * kcap + j];
+    x[(size_t)c * N + i] = acc;
+}
+
+__global__ void __launch_bounds__(kNT)
+k_axpby(int n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+        double* __restrict__ out) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i < n) out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+__global__ void __launch_bounds__(kNT) k_fill(int n, double v, double* __restrict__ out) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
+inline unsigned blocks(long long n) { return (unsigned)((n + kNT - 1) / kNT); }
+
+}  // namespace
+
+void launch_chord_weights(int n, const int* seg, int s, int g, int N, const double* Pi,
+                          const double* kappa, const double* sigma, const double* mu,
+                          double* w_f64, float* w_f32, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_chord_weights, dim3(blocks(n)), dim3(kNT), 0, st, n, seg, s, g, N, Pi,
+                       kappa, sigma, mu, w_f64, w_f32);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_direct_nodes(const NodesView& nodes, const ChordsView& segs, const double* ell,
+                         const double* kappa, const double* w, double* out, hipStream_t st) {
+    if (nodes.N <= 0) return;
+    hipLaunchKernelGGL(k_direct_nodes, dim3(blocks(nodes.N)), dim3(kNT), 0, st, nodes, segs,
+                       ell, kappa, w, out);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_direct_targets(const TargetGrid* grid, const double* pts, int n_pts,
+                           const ChordsView& segs, const double* w, int out_f64, void* out,
+                           hipStream_t st) {
+    TargetGrid gg = grid ? *grid : TargetGrid{0, 0, 0, 0, 0, 0};
+    const long long n = grid ? (long long)grid->W * grid->H : n_pts;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_direct_targets, dim3(blocks(n)), dim3(kNT), 0, st, gg, grid ? 1 : 0,
+                       pts, n_pts, segs, w, out_f64, out);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_block_dots(const double* V, int k, const double* w, int N, double* dots,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_block_dots, dim3(k, 3), dim3(kNT), 0, st, V, w, N, dots, k);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_block_update(const double* V, int k, const double* h, int kcap, double* w, int N,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_block_update, dim3(blocks(N), 3), dim3(kNT), 0, st, V, k, h, kcap, w,
+                       N);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_scale3(const double* x, const double* alpha, double* y, int N, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale3, dim3(blocks(N), 3), dim3(kNT), 0, st, x, alpha, y, N);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_combine(const double* V, int k, const double* y, int kcap, double* x, int N,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_combine, dim3(blocks(N), 3), dim3(kNT), 0, st, V, k, y, kcap, x, N);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_axpby(int n, double a, const double* x, double b, const double* y, double* out,
+                  hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(kNT), 0, st, n, a, x, b, y, out);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_fill(int n, double v, double* out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(blocks(n)), dim3(kNT), 0, st, n, v, out);
+    DC_HIP(hipGetLastError());
+}
+
+}  // namespace dc

@@ -1,0 +1,37 @@
+// Scene state shared by the entry points and the FMM driver.
+#pragma once
+
+#include <memory>
+
+#include "fmm.h"
+#include "geometry.h"
+#include "kernels.h"
+#include "tree.h"
+
+struct dc_scene_s {
+    dc_scene_opts opts{};
+    dc::Geometry geo;
+    dc::Tree tree;
+    std::vector<double> uplus, uminus;  // [3][N] host
+
+    // Segments (device).
+    dc::DevBuf<double> seg_x0, seg_y0, seg_tx, seg_ty, seg_len, seg_ell, seg_kappa;
+    // Nodes (device).
+    dc::DevBuf<double> node_x, node_y, node_tstar;
+    dc::DevBuf<int> node_self;
+    dc::DevBuf<double> Pi;
+    // Boundary data and densities (device, [3][N]).
+    dc::DevBuf<double> d_uplus, d_uminus, d_mu, d_sigma;
+    bool solved = false;
+    // Segment weights of the current densities for the direct path [6][S].
+    dc::DevBuf<double> seg_w;
+    bool seg_w_valid = false;
+
+    // FMM state (tree on device, expansions, scratch).
+    std::unique_ptr<dc::FmmState> fmm;
+
+    dc::ChordsView segs() const {
+        return {geo.S, seg_x0.p, seg_y0.p, seg_tx.p, seg_ty.p, seg_len.p};
+    }
+    dc::NodesView nodes() const { return {geo.N, node_x.p, node_y.p, node_self.p, node_tstar.p}; }
+};

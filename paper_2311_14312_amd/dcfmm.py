@@ -1,0 +1,286 @@
+"""Python binding of libdcfmm.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch supplies device memory
+and the current stream.  Importing this module fails loudly if the library
+has not been built (``python -m paper_2311_14312_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcfmm.so")
+
+DC_OK, DC_ERR_INVALID, DC_ERR_OOM, DC_ERR_NOT_CONVERGED, DC_ERR_HIP = 0, -1, -2, -3, -4
+PREC_F64, PREC_F32 = 0, 1
+METHOD_FMM, METHOD_DIRECT = 0, 1
+OUT_F32, OUT_F64 = 0, 1
+P_MAX = 40
+
+
+class SceneOpts(C.Structure):
+    _fields_ = [("panels_per_curve", C.c_int), ("gl_per_panel", C.c_int),
+                ("segs_per_panel", C.c_int), ("leaf_max", C.c_int),
+                ("max_depth", C.c_int), ("domain", C.c_double * 4)]
+
+
+class EvalOpts(C.Structure):
+    _fields_ = [("method", C.c_int), ("precision", C.c_int), ("p", C.c_int),
+                ("tile_px", C.c_int), ("near_fp64", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("matvec", EvalOpts)]
+
+
+class Viewport(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("width", C.c_double),
+                ("height", C.c_double), ("W", C.c_int), ("H", C.c_int)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("iters", C.c_int * 3), ("rel_residual", C.c_double * 3),
+                ("true_rel_residual", C.c_double * 3), ("seconds", C.c_double),
+                ("converged", C.c_int)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_curves", C.c_int), ("N", C.c_int), ("S", C.c_int),
+                ("n_pieces", C.c_int), ("n_cells", C.c_int), ("n_leaves", C.c_int),
+                ("depth", C.c_int), ("root", C.c_double * 3), ("solved", C.c_int)]
+
+
+class WorkCounts(C.Structure):
+    _fields_ = [("p2p_pairs", C.c_ulonglong), ("p2p_fp64_pairs", C.c_ulonglong),
+                ("m2p_pairs", C.c_ulonglong), ("l2p_targets", C.c_ulonglong),
+                ("m2l_pairs", C.c_ulonglong), ("p2l_pairs", C.c_ulonglong),
+                ("l2l_boxes", C.c_ulonglong), ("leaf_boxes", C.c_ulonglong),
+                ("pieces", C.c_ulonglong), ("source_cells", C.c_ulonglong),
+                ("levels", C.c_int), ("p", C.c_int)]
+
+
+class DcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dcfmm error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2311_14312_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, V = C.c_void_p, C.c_int, C.c_double, C.c_void_p
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "dc_default_scene_opts": (None, [C.POINTER(SceneOpts)]),
+        "dc_default_eval_opts": (None, [C.POINTER(EvalOpts)]),
+        "dc_scene_create": (I, [dp, I, dp, dp, I, C.POINTER(SceneOpts), C.POINTER(P)]),
+        "dc_scene_destroy": (None, [P]),
+        "dc_scene_get_info": (I, [P, C.POINTER(SceneInfo)]),
+        "dc_get_nodes": (I, [P, dp]),
+        "dc_set_boundary": (I, [P, dp, dp]),
+        "dc_solve_densities": (I, [P, C.POINTER(SolveOpts), C.POINTER(SolveReport), V]),
+        "dc_get_densities": (I, [P, dp]),
+        "dc_set_densities": (I, [P, dp]),
+        "dc_apply_operator": (I, [P, V, V, I, C.POINTER(EvalOpts), V]),
+        "dc_render": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, V, V]),
+        "dc_eval_points": (I, [P, V, I, C.POINTER(EvalOpts), I, V, V]),
+        "dc_render_counts": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts),
+                                 C.POINTER(WorkCounts), V]),
+        "dc_set_timing": (I, [P, I]),
+        "dc_get_timing": (I, [P, dp]),
+        "dc_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc, allow=()):
+    if rc != DC_OK and rc not in allow:
+        raise DcError(rc, _lib.dc_last_error().decode())
+    return rc
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def eval_opts(method="fmm", precision="f64", p=20, tile_px=8, near_fp64=1e-3):
+    e = EvalOpts()
+    _lib.dc_default_eval_opts(C.byref(e))
+    e.method = {"fmm": METHOD_FMM, "direct": METHOD_DIRECT}[method]
+    e.precision = {"f64": PREC_F64, "f32": PREC_F32}[precision]
+    e.p = int(p)
+    e.tile_px = int(tile_px)
+    e.near_fp64 = float(near_fp64)
+    return e
+
+
+class Scene:
+    """A resident scene: geometry, quadtree and densities on the device."""
+
+    def __init__(self, ctrl, left, right, panels=16, gl=16, segs=80, leaf_max=64,
+                 max_depth=40, domain=None):
+        o = SceneOpts()
+        _lib.dc_default_scene_opts(C.byref(o))
+        o.panels_per_curve, o.gl_per_panel, o.segs_per_panel = panels, gl, segs
+        o.leaf_max, o.max_depth = leaf_max, max_depth
+        if domain is not None:
+            for k in range(4):
+                o.domain[k] = float(domain[k])
+        self._ctrl = _f64(ctrl)
+        left, right = _f64(left), _f64(right)
+        n = self._ctrl.shape[0]
+        if self._ctrl.shape != (n, 4, 2) or left.shape[0] != n or left.shape != right.shape \
+                or left.ndim != 3 or left.shape[2] != 3:
+            raise ValueError("expected ctrl [n,4,2] and left/right [n,stops,3]")
+        h = C.c_void_p()
+        _check(_lib.dc_scene_create(_ptr(self._ctrl), n, _ptr(left), _ptr(right),
+                                    left.shape[1], C.byref(o), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_dict(cls, sc, **kw):
+        args = dict(panels=sc.get("panels", 16), gl=sc.get("gl", 16),
+                    segs=sc.get("segs", 80), leaf_max=sc.get("leaf_max", 64))
+        args.update(kw)
+        return cls(sc["ctrl"], sc["left"], sc["right"], **args)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dc_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = SceneInfo()
+        _check(_lib.dc_scene_get_info(self._h, C.byref(i)))
+        return {k: (list(getattr(i, k)) if k == "root" else getattr(i, k))
+                for k, _ in SceneInfo._fields_}
+
+    @property
+    def N(self):
+        return self.info()["N"]
+
+    def nodes(self):
+        out = np.empty((self.N, 2))
+        _check(_lib.dc_get_nodes(self._h, _ptr(out)))
+        return out
+
+    def set_boundary(self, u_plus, u_minus):
+        up, um = _f64(u_plus), _f64(u_minus)
+        if up.shape != (3, self.N) or um.shape != (3, self.N):
+            raise ValueError("boundary values must be [3, N]")
+        _check(_lib.dc_set_boundary(self._h, _ptr(up), _ptr(um)))
+
+    def solve(self, tol=1e-10, max_iter=1000, raise_on_fail=False, **ev):
+        o = SolveOpts()
+        o.tol, o.max_iter, o.matvec = tol, max_iter, eval_opts(**ev)
+        rep = SolveReport()
+        allow = () if raise_on_fail else (DC_ERR_NOT_CONVERGED,)
+        rc = _check(_lib.dc_solve_densities(self._h, C.byref(o), C.byref(rep), _stream()),
+                    allow)
+        return {"iters": list(rep.iters), "rel_residual": list(rep.rel_residual),
+                "true_rel_residual": list(rep.true_rel_residual),
+                "seconds": rep.seconds, "converged": bool(rep.converged), "rc": rc}
+
+    def densities(self):
+        out = np.empty((3, self.N))
+        _check(_lib.dc_get_densities(self._h, _ptr(out)))
+        return out
+
+    def set_densities(self, sigma):
+        s = _f64(sigma)
+        if s.shape != (3, self.N):
+            raise ValueError("densities must be [3, N]")
+        _check(_lib.dc_set_densities(self._h, _ptr(s)))
+
+    def apply_operator(self, x, y=None, c_mu=0, **ev):
+        """y = G_H x + c_mu F_H mu at the nodes; x, y torch cuda float64 [3, N]."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()
+        assert tuple(x.shape) == (3, self.N)
+        if y is None:
+            y = torch.empty_like(x)
+        o = eval_opts(**ev)
+        _check(_lib.dc_apply_operator(self._h, C.c_void_p(x.data_ptr()),
+                                      C.c_void_p(y.data_ptr()), int(c_mu), C.byref(o),
+                                      _stream()))
+        return y
+
+    def render(self, viewport, out=None, out_dtype=None, **ev):
+        """Image [H, W, 3] of viewport (cx, cy, width, height, W, H)."""
+        import torch
+        cx, cy, w, h, W, H = viewport
+        vp = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        if out is None:
+            out = torch.empty((int(H), int(W), 3), device="cuda",
+                              dtype=out_dtype or torch.float32)
+        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == (H, W, 3)
+        code = {torch.float32: OUT_F32, torch.float64: OUT_F64}[out.dtype]
+        o = eval_opts(**ev)
+        _check(_lib.dc_render(self._h, C.byref(vp), C.byref(o), code,
+                              C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def eval_points(self, xy, out_dtype=None, **ev):
+        """Representation at points xy (torch cuda float64 [n, 2]) -> [n, 3]."""
+        import torch
+        assert xy.is_cuda and xy.dtype == torch.float64 and xy.is_contiguous()
+        n = xy.shape[0]
+        out = torch.empty((n, 3), device="cuda", dtype=out_dtype or torch.float64)
+        code = {torch.float32: OUT_F32, torch.float64: OUT_F64}[out.dtype]
+        o = eval_opts(**ev)
+        _check(_lib.dc_eval_points(self._h, C.c_void_p(xy.data_ptr()), n, C.byref(o), code,
+                                   C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+
+    def render_counts(self, viewport, **ev):
+        """Device-counted work of one FMM render of viewport (synchronous)."""
+        cx, cy, w, h, W, H = viewport
+        vp = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        o = eval_opts(**ev)
+        wc = WorkCounts()
+        _check(_lib.dc_render_counts(self._h, C.byref(vp), C.byref(o), C.byref(wc),
+                                     _stream()))
+        return {k: getattr(wc, k) for k, _ in WorkCounts._fields_}
+
+    def set_timing(self, enable=True):
+        _check(_lib.dc_set_timing(self._h, int(bool(enable))))
+
+    def get_timing(self):
+        """Summed per-phase render times (ms) since the last call, and calls."""
+        ms = np.zeros(5)
+        _check(_lib.dc_get_timing(self._h, _ptr(ms)))
+        return {"upward_ms": ms[0], "downward_ms": ms[1], "leaf_ms": ms[2],
+                "total_ms": ms[3], "calls": int(ms[4])}
+
+
+def exported_symbols():
+    """Names of the dc_* functions the loaded library exports."""
+    return sorted(n for n in dir(_lib) if n.startswith("dc_"))

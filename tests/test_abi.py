@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU needed: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcfmm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(dc_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("dc_scene_create", "dc_solve_densities", "dc_render", "dc_scene_destroy",
+                 "dc_last_error", "dc_get_densities"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2311_14312_amd import dcfmm
+    lib = ctypes.CDLL(dcfmm.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_defaults_and_struct_sizes():
+    from paper_2311_14312_amd import dcfmm
+    o = dcfmm.SceneOpts()
+    dcfmm._lib.dc_default_scene_opts(ctypes.byref(o))
+    assert (o.panels_per_curve, o.gl_per_panel, o.segs_per_panel, o.leaf_max) == (16, 16, 80, 64)
+    e = dcfmm.EvalOpts()
+    dcfmm._lib.dc_default_eval_opts(ctypes.byref(e))
+    assert e.p == 20 and e.method == dcfmm.METHOD_FMM and e.precision == dcfmm.PREC_F64
+    assert ctypes.sizeof(dcfmm.EvalOpts) == 24
+    assert ctypes.sizeof(dcfmm.SolveOpts) == 40
+
+
+def test_invalid_arguments_fail_cleanly_without_gpu():
+    """Host-side validation rejects bad input before touching the device."""
+    import numpy as np
+    from paper_2311_14312_amd import dcfmm
+    ctrl = np.zeros((1, 4, 2))
+    ctrl[0, :, 0] = [0, 0.3, 0.6, 1.0]
+    left = np.zeros((1, 1, 3))          # one stop is not enough
+    with pytest.raises(dcfmm.DcError) as e:
+        dcfmm.Scene(ctrl, left, left)
+    assert e.value.code == dcfmm.DC_ERR_INVALID
+    bad = ctrl.copy()
+    bad[0, 1, 1] = np.nan
+    with pytest.raises(dcfmm.DcError) as e:
+        dcfmm.Scene(bad, np.zeros((1, 2, 3)), np.zeros((1, 2, 3)))
+    assert e.value.code == dcfmm.DC_ERR_INVALID
+    flat = np.zeros((1, 4, 2))          # zero-length curve
+    with pytest.raises(dcfmm.DcError) as e:
+        dcfmm.Scene(flat, np.zeros((1, 2, 3)), np.zeros((1, 2, 3)))
+    assert e.value.code == dcfmm.DC_ERR_INVALID
