@@ -46,7 +46,7 @@ def leaf_flops(c, p):
             + c["l2p_targets"] * flops_l2p(p))
 
 
-def sample_pixels(W, H, segs_p1, segs_p2, rng, n_near=1024, stride=64):
+def sample_pixels(W, H, segs_p1, segs_p2, rng, n_near=4096, stride=16):
     rows, cols = np.meshgrid(np.arange(stride // 2, H, stride),
                              np.arange(stride // 2, W, stride), indexing="ij")
     pick = rng.choice(segs_p1.shape[0], size=n_near, replace=False)
@@ -194,7 +194,7 @@ def main():
                    "p_fp32": args.p32, "p_fp64": args.p64, "tile_px": args.tile,
                    "leaf_max": args.leaf, "gmres_tol": cfg["gmres_tol"]},
         "max_err_vs_oracle": err32,
-        "err_sample": (f"{cpu['n']} pixels (32x32 stride-64 grid + 1024 near-chord)"
+        "err_sample": (f"{cpu['n']} pixels (128x128 stride-16 grid + 4096 near-chord)"
                        if cpu else None),
         "fp64_fmm": {"value": px / (ms64 * 1e-3), "unit": "RGB pixels/s", "ms_per_step": ms64,
                      "max_err_vs_oracle": err64,

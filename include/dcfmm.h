@@ -86,11 +86,17 @@ typedef struct {
 } dc_eval_opts;
 
 /* GMRES (Sec. 6.5.1): relative residual tolerance ||b - Ax|| / ||b|| per
- * channel, at most max_iter Arnoldi steps (no restart), initial guess 1. */
+ * channel, at most max_iter Arnoldi steps (no restart), initial guess 1.
+ * precond = DC_PRECOND_BLOCK applies GMRES to A M^-1 with M the block
+ * diagonal of A over the curves (each curve's own hybrid matrix, inverted
+ * on the device); the system and its solution are unchanged. */
+#define DC_PRECOND_NONE 0
+#define DC_PRECOND_BLOCK 1
 typedef struct {
     double tol;
     int max_iter;
     dc_eval_opts matvec;
+    int precond;
 } dc_solve_opts;
 
 typedef struct {

@@ -77,7 +77,29 @@ void apply_operator(dc_scene s, const double* x, const double* mu, double* y,
     }
 }
 
-// Alg. 3 with GMRES (Sec. 6.5.1): three channels share every matvec.
+// Inverted diagonal blocks of the curves (computed once per scene).
+void ensure_block_inverse(dc_scene s, hipStream_t st) {
+    if (s->dinv_valid) return;
+    const Geometry& G = s->geo;
+    const int n = G.P * G.g;
+    s->dinv.alloc((size_t)G.n_curves * n * n);
+    DevBuf<int> perm, flag;
+    perm.alloc((size_t)G.n_curves * n);
+    flag.alloc(1);
+    const int zero = 0;
+    DC_HIP(hipMemcpy(flag.p, &zero, sizeof(int), hipMemcpyHostToDevice));
+    launch_curve_blocks(s->nodes(), G.P, G.g, G.s, s->segs(), s->seg_ell.p, s->seg_kappa.p,
+                        s->Pi.p, s->dinv.p, st);
+    launch_invert_blocks(G.n_curves, n, s->dinv.p, perm.p, flag.p, st);
+    int singular = 0;
+    DC_HIP(hipMemcpyAsync(&singular, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    DC_REQUIRE(!singular, "a curve's diagonal block is singular; solve without preconditioner");
+    s->dinv_valid = true;
+}
+
+// Alg. 3 with GMRES (Sec. 6.5.1): three channels share every matvec; with
+// right preconditioning the Krylov space is built for A M^-1.
 int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStream_t st) {
     const int N = s->geo.N;
     const size_t n3 = 3 * (size_t)N;
@@ -93,6 +115,12 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     dev_small.alloc(3 * (size_t)kcap + 8);
     double* h1 = dev_h.p;
     double* h2 = dev_h.p + 3 * kcap;
+    const bool pre = o.precond == DC_PRECOND_BLOCK;
+    DevBuf<double> z;
+    if (pre) {
+        ensure_block_inverse(s, st);
+        z.alloc(n3);
+    }
 
     // b = (u+ + u-)/2 - F_H mu
     apply_operator(s, nullptr, s->d_mu.p, tmp.p, o.matvec, st);
@@ -134,7 +162,12 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
 
     for (int k = 0; k < m && (active[0] || active[1] || active[2]); ++k) {
         double* vk = V.p + (size_t)k * n3;
-        apply_operator(s, vk, nullptr, w.p, o.matvec, st);
+        if (pre) {
+            launch_block_apply(N, s->geo.P * s->geo.g, s->dinv.p, vk, z.p, st);
+            apply_operator(s, z.p, nullptr, w.p, o.matvec, st);
+        } else {
+            apply_operator(s, vk, nullptr, w.p, o.matvec, st);
+        }
         // classical Gram-Schmidt, twice (CGS2), against V[0..k]
         launch_block_dots(V.p, k + 1, w.p, N, h1, st);
         launch_block_update(V.p, k + 1, h1, k + 1, w.p, N, st);
@@ -190,7 +223,15 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     if (kmax > 0) {
         DevBuf<double> dy;
         dy.upload(y);
-        launch_combine(V.p, kmax, dy.p, kcap, x.p, N, st);
+        if (pre) {
+            // x += M^-1 (V y)
+            launch_fill((int)n3, 0.0, tmp.p, st);
+            launch_combine(V.p, kmax, dy.p, kcap, tmp.p, N, st);
+            launch_block_apply(N, s->geo.P * s->geo.g, s->dinv.p, tmp.p, z.p, st);
+            launch_axpby((int)n3, 1.0, x.p, 1.0, z.p, x.p, st);
+        } else {
+            launch_combine(V.p, kmax, dy.p, kcap, x.p, N, st);
+        }
         DC_HIP(hipStreamSynchronize(st));
     }
     // True residual.
@@ -323,6 +364,8 @@ int dc_solve_densities(dc_scene s, const dc_solve_opts* o, dc_solve_report* rep,
         DC_REQUIRE(s && o && rep, "null argument");
         check_eval(&o->matvec);
         DC_REQUIRE(o->tol > 0 && o->max_iter >= 1, "bad GMRES options");
+        DC_REQUIRE(o->precond == DC_PRECOND_NONE || o->precond == DC_PRECOND_BLOCK,
+                   "bad preconditioner");
         std::memset(rep, 0, sizeof(*rep));
         const auto t0 = std::chrono::steady_clock::now();
         rc = gmres_solve(s, *o, *rep, as_stream(stream));

@@ -26,6 +26,7 @@ struct FmmState {
     // Piece weights (kappa sigma_bar, kappa mu_bar) [6][n_pieces].
     DevBuf<double> w64;
     DevBuf<float> w32;
+    DevBuf<int> heavy;  // FP32 path: pieces evaluated in FP64
     // Multipole and local coefficients of the source tree, and near sets.
     DevBuf<double> M64, L64;
     DevBuf<float> M32, L32;

@@ -52,6 +52,7 @@ struct PieceView {
     const int* seg;
     const double* w64;
     const float* w32;
+    const int* heavy;   // FP32 path: piece evaluated in FP64 (large |q| * length)
 };
 
 __device__ inline double half_width(const TreeView& t, int l) { return ldexp(t.side, -(l + 1)); }
@@ -91,6 +92,42 @@ template <>
 __device__ inline const double* weights<double>(const PieceView& pv) { return pv.w64; }
 template <>
 __device__ inline const float* weights<float>(const PieceView& pv) { return pv.w32; }
+
+// FP32 arctangent: atan(t) ~ t P(t^2) on [0, 1] (coefficients from a minimax
+// fit by Lawson's iteration, fit_atan_poly.py; max error 7e-7), with the
+// usual octant reduction.
+__device__ inline float atan2_poly(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+    const float u = t * t;
+    float q = 8.00683815e-03f;
+    q = q * u - 3.74428146e-02f;
+    q = q * u + 8.43539238e-02f;
+    q = q * u - 1.35121688e-01f;
+    q = q * u + 1.98873192e-01f;
+    q = q * u - 3.33270133e-01f;
+    q = q * u + 9.99999404e-01f;
+    float r = t * q;
+    r = ay > ax ? 1.57079632679f - r : r;
+    r = x < 0.f ? 3.14159265359f - r : r;
+    return copysignf(r, y);
+}
+
+// FP32 chord integral for a pair that is neither near-singular nor heavy:
+// both endpoint logarithms from the hardware log2 (the cancellation of the
+// two x ln r terms costs at most (distance / chord) ulps, far inside the
+// FP32 error budget for near-field pairs).
+__device__ inline void chord_fast(float xi1, float h, float xi2, float la, float& il,
+                                  float& th) {
+    const float r1 = fmaxf(xi1 * xi1 + h * h, 1e-37f);
+    const float r2 = fmaxf(xi2 * xi2 + h * h, 1e-37f);
+    th = atan2_poly(h * la, h * h + xi1 * xi2);
+    constexpr float half_ln2 = 0.34657359028f;  // ln(2)/2: log2 -> ln of the square root
+    const float l1 = __builtin_amdgcn_logf(r1) * half_ln2;
+    const float l2 = __builtin_amdgcn_logf(r2) * half_ln2;
+    il = xi2 * l2 - xi1 * l1 - la + h * th;
+}
 
 // ------------------------------------------------------------------ upward
 // Outgoing-from-source on every leaf (App. E.8, E.9), lane k = coefficient:
@@ -195,46 +232,96 @@ __device__ inline void m2l_lane(cpx<T> acc[3], const cpx<T>* __restrict__ src, i
     }
 }
 
-// Incoming-from-source of one piece (App. E.10, E.11), scaled, lane k.
-// A, B: piece ends relative to the box centre in units of r; zA = 1/A,
-// zB = 1/B; Lam = Log(B/A) (continuous branch: a chord seen from a point
-// off its line subtends less than pi).
+// Incoming-from-source (App. E.10, E.11), scaled.  For a piece with ends
+// A, B relative to the box centre in units of r, zA = 1/A, zB = 1/B and
+// Lam = Log(B/A) (continuous branch: a chord seen from a point off its line
+// subtends less than pi), the contribution to Lt_k is
 //   k = 0: -qs [|a| (log r + log A) + wbar r B Lam - |a|]  - i qm Lam
 //   k = 1:  qs wbar r Lam                               + i qm (zB - zA)
 //   k > 1:  qs wbar r (zA^{k-1} - zB^{k-1})/(k(k-1))    + i qm (zB^k - zA^k)/k
+// The wave splits the pieces over its 64 lanes and walks k in blocks of KB
+// with running powers; block partial sums are reduced across the wave and
+// handed to the lane that owns coefficient k.
 template <typename T>
-__device__ inline void p2l_lane(cpx<T> acc[3], const PieceView& pv, int e, double cx, double cy,
-                                double r, int k) {
+__device__ inline T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+__device__ void p2l_wave(cpx<T> acc[3], const PieceView& pv, const TreeView& tv, const int* l4,
+                         const int* pre, int nl4, double cx, double cy, double r, int p,
+                         int lane) {
+    constexpr int KB = 8;
+    const int total = pre[nl4];
     const double inv_r = 1.0 / r;
-    const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
-    const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
-    const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
-    const T len = (T)pv.len[e], rr = (T)r;
-    const cpx<T> Lam = clog(cmul(B, cpx<T>{A.re, -A.im}));
-    cpx<T> s, m;
-    if (k == 0) {
-        const cpx<T> lA = clog(A);
-        const cpx<T> t1 = {len * ((T)log(r) + lA.re), len * lA.im};
-        const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
-        s = {-(t1.re + t2.re - len), -(t1.im + t2.im)};
-        m = {Lam.im, -Lam.re};
-    } else {
-        const cpx<T> zA = cinv(A), zB = cinv(B);
-        if (k == 1) {
-            s = cmul(wbar, cscale(Lam, rr));
-            const cpx<T> d = csub(zB, zA);
-            m = {-d.im, d.re};
-        } else {
-            const cpx<T> a1 = cpow(zA, k - 1), b1 = cpow(zB, k - 1);
-            s = cmul(wbar, cscale(csub(a1, b1), rr / (T)(k * (k - 1))));
-            const cpx<T> d = cscale(csub(cmul(b1, zB), cmul(a1, zA)), T(1) / (T)k);
-            m = {-d.im, d.re};
-        }
-    }
+    const T rr = (T)r, logr = (T)log(r);
     const T* w = weights<T>(pv);
-    for (int ch = 0; ch < 3; ++ch) {
-        const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
-        acc[ch] = cadd(acc[ch], cadd(cscale(s, qs), cscale(m, qm)));
+    for (int kb = 0; kb <= p; kb += KB) {
+        cpx<T> part[3][KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            for (int ch = 0; ch < 3; ++ch) part[ch][j] = {0, 0};
+        for (int base = 0; base < total; base += kWave) {
+            const int g = base + lane;
+            if (g >= total) continue;
+            int u = 0;
+            while (u + 1 < nl4 && pre[u + 1] <= g) ++u;
+            const int e = tv.pbeg[l4[u]] + (g - pre[u]);
+            const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
+            const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
+            const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
+            const T len = (T)pv.len[e];
+            const cpx<T> zA = cinv(A), zB = cinv(B);
+            T qs[3], qm[3];
+            for (int ch = 0; ch < 3; ++ch) {
+                qs[ch] = w[(size_t)ch * pv.n + e];
+                qm[ch] = w[(size_t)(3 + ch) * pv.n + e];
+            }
+            cpx<T> Lam = {0, 0};
+            if (kb == 0) {
+                const cpx<T> BA = cmul(B, cpx<T>{A.re, -A.im});
+                const T nA = A.re * A.re + A.im * A.im, nB = B.re * B.re + B.im * B.im;
+                Lam = {T(0.5) * log(nB / nA), atan2(BA.im, BA.re)};
+            }
+            // running powers zA^{k-1}, zB^{k-1} for the first k >= 1 of the block
+            const int k1 = kb == 0 ? 1 : kb;
+            cpx<T> pa = cpow(zA, k1 - 1), pb = cpow(zB, k1 - 1);
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                const int k = kb + j;
+                if (k > p) break;
+                cpx<T> sv, mv;
+                if (k == 0) {
+                    const cpx<T> lA = clog(A);
+                    const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
+                    sv = {-(len * (logr + lA.re) + t2.re - len), -(len * lA.im + t2.im)};
+                    mv = {Lam.im, -Lam.re};
+                } else if (k == 1) {
+                    sv = cmul(wbar, cscale(Lam, rr));
+                    const cpx<T> d = csub(zB, zA);
+                    mv = {-d.im, d.re};
+                    pa = zA;
+                    pb = zB;
+                } else {
+                    sv = cmul(wbar, cscale(csub(pa, pb), rr / (T)(k * (k - 1))));
+                    const cpx<T> na = cmul(pa, zA), nb = cmul(pb, zB);
+                    const cpx<T> d = cscale(csub(nb, na), T(1) / (T)k);
+                    mv = {-d.im, d.re};
+                    pa = na;
+                    pb = nb;
+                }
+                for (int ch = 0; ch < 3; ++ch)
+                    part[ch][j] = cadd(part[ch][j], cadd(cscale(sv, qs[ch]), cscale(mv, qm[ch])));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+            for (int ch = 0; ch < 3; ++ch) {
+                const cpx<T> v = {wave_sum(part[ch][j].re), wave_sum(part[ch][j].im)};
+                if (lane == kb + j) acc[ch] = cadd(acc[ch], v);
+            }
+        }
     }
 }
 
@@ -275,14 +362,14 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         nset[(size_t)own * 9 + lane] = c;
     }
     const int k = lane;
-    if (k > p) return;
+    const bool klane = k <= p;  // lanes above p only help with the pieces
     const double r = half_width(tv, l);
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
     cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     // incoming-from-incoming from the parent (Eq. i-f-i), scaled:
     //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
-    {
+    if (klane) {
         const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
         const cpx<T>* src = L + (size_t)par * (p + 1) * 3;
         cpx<T> pw = {1, 0};
@@ -297,7 +384,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
     }
     // interaction list
     const double log2r = log(2.0 * r);
-    for (int s = 0; s < 9; ++s) {
+    for (int s = 0; s < 9 && klane; ++s) {
         const int c = sPN[s];
         if (c < 0 || tv.lvl[c] != l - 1 || tv.child[c] < 0) continue;
         const long long ppx = (ti >> 1) + (s % 3) - 1, ppy = (tj >> 1) + (s / 3) - 1;
@@ -316,18 +403,35 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             if (dl.stats && k == 0) atomicAdd(dl.stats + kStatM2L, 1ULL);
         }
     }
-    // bigger separated list: coarser source leaves that do not touch us
+    // bigger separated list: coarser source leaves that do not touch us;
+    // their pieces are flattened into one list shared by the wave
+    int l4[9], pre[10], nl4 = 0;
+    pre[0] = 0;
     for (int s = 0; s < 9; ++s) {
         const int c = sPN[s];
         if (c < 0 || (tv.lvl[c] == l - 1 && tv.child[c] >= 0)) continue;
         bool dup = false;
         for (int s2 = 0; s2 < s; ++s2) dup |= (sPN[s2] == c);
         if (dup || tv.npc[c] == 0 || touches(tv, c, l, ti, tj)) continue;
-        for (int e = tv.pbeg[c]; e < tv.pend[c]; ++e) p2l_lane<T>(acc, pv, e, cx, cy, r, k);
-        if (dl.stats && k == 0)
-            atomicAdd(dl.stats + kStatP2L, (unsigned long long)(tv.pend[c] - tv.pbeg[c]));
+        l4[nl4] = c;
+        pre[nl4 + 1] = pre[nl4] + (tv.pend[c] - tv.pbeg[c]);
+        ++nl4;
     }
-    if (dl.stats && k == 0) atomicAdd(dl.stats + kStatL2L, 1ULL);
+    if (nl4 > 0) {
+        // always in FP64: pieces of one leaf can carry large charges of both
+        // signs whose sum cancels (near-cusps), beyond FP32's reach
+        cpx<double> accd[3] = {{0, 0}, {0, 0}, {0, 0}};
+        p2l_wave<double>(accd, pv, tv, l4, pre, nl4, cx, cy, r, p, k);
+        for (int ch = 0; ch < 3; ++ch) {
+            acc[ch].re += (T)accd[ch].re;
+            acc[ch].im += (T)accd[ch].im;
+        }
+    }
+    if (dl.stats && k == 0) {
+        atomicAdd(dl.stats + kStatP2L, (unsigned long long)pre[nl4]);
+        atomicAdd(dl.stats + kStatL2L, 1ULL);
+    }
+    if (!klane) return;
     cpx<T>* out = L + ((size_t)own * (p + 1) + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
 }
@@ -550,22 +654,26 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
                     sh.ty[tid] = (T)pv.ty[e];
                     sh.len[tid] = (T)pv.len[e];
                     for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
-                    sh.pid[tid] = e;
+                    sh.pid[tid] = sizeof(T) == 4 && pv.heavy[e] ? -1 - e : e;
                 }
                 __syncthreads();
                 if (active) {
                     const int m = min(NT, total - pbase);
+                    const float near2f = (float)a.near2;
                     for (int j = 0; j < m; ++j) {
                         const T dx = sh.px[j] - xr, dy = sh.py[j] - yr;
                         if (sizeof(T) == 4) {
-                            const T xi1 = dx * sh.tx[j] + dy * sh.ty[j];
-                            const T h = dy * sh.tx[j] - dx * sh.ty[j];
-                            const T xi2 = xi1 + sh.len[j];
-                            const T dd = xi1 > 0 ? xi1 * xi1 + h * h
-                                                 : (xi2 < 0 ? xi2 * xi2 + h * h : h * h);
-                            if ((double)dd < a.near2 * (double)sh.len[j] * (double)sh.len[j]) {
-                                // near-singular pair: closed form in FP64
-                                const int e = sh.pid[j];
+                            const float tx = (float)sh.tx[j], ty = (float)sh.ty[j];
+                            const float la = (float)sh.len[j];
+                            const float xi1 = (float)dx * tx + (float)dy * ty;
+                            const float h = (float)dy * tx - (float)dx * ty;
+                            const float xi2 = xi1 + la;
+                            const float dd = xi1 > 0.f ? xi1 * xi1 + h * h
+                                                       : (xi2 < 0.f ? xi2 * xi2 + h * h : h * h);
+                            const int pid = sh.pid[j];
+                            if (dd < near2f * la * la || pid < 0) {
+                                // near-singular pair or heavy piece: closed form in FP64
+                                const int e = pid < 0 ? -1 - pid : pid;
                                 double il, th;
                                 chord_log_theta<double>(pv.x0[e] - x, pv.y0[e] - y, pv.tx[e],
                                                         pv.ty[e], pv.len[e], il, th);
@@ -575,6 +683,11 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
                                 if (a.stats) atomicAdd(a.stats + kStatP2P64, 1ULL);
                                 continue;
                             }
+                            float il, th;
+                            chord_fast(xi1, h, xi2, la, il, th);
+                            for (int ch = 0; ch < 3; ++ch)
+                                accP[ch] += (T)(il * (float)sh.w[ch][j] + th * (float)sh.w[3 + ch][j]);
+                            continue;
                         }
                         T il, th;
                         chord_log_theta<T>(dx, dy, sh.tx[j], sh.ty[j], sh.len[j], il, th);
@@ -646,7 +759,7 @@ TreeView tree_view(const FmmState& f) {
 }
 PieceView piece_view(const FmmState& f) {
     return {f.n_pieces, f.px0.p, f.py0.p, f.px1.p, f.py1.p, f.ptx.p, f.pty.p, f.plen.p, f.pseg.p,
-            f.w64.p, f.w32.p};
+            f.w64.p, f.w32.p, f.heavy.p};
 }
 
 template <typename T>
@@ -669,25 +782,61 @@ cpx<T>* as_cpx(DevBuf<T>& b) {
     return reinterpret_cast<cpx<T>*>(b.p);
 }
 
-// Piece weights and the upward pass for the given densities.
-template <typename T>
+__global__ void __launch_bounds__(256)
+k_heavy_flags(int n, const double* __restrict__ len, const double* __restrict__ w, double tau,
+              int* __restrict__ heavy) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double m = 0;
+    for (int c = 0; c < 6; ++c) m = fmax(m, fabs(w[(size_t)c * n + e]));
+    heavy[e] = m * len[e] > tau ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_to_f32(size_t n, const double* __restrict__ a, float* __restrict__ b) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// Pieces whose charge times length exceeds this are evaluated in FP64 by the
+// FP32 path (their FP32 rounding alone would approach the error budget).
+constexpr double kHeavyTau = 1.0;
+
+// Piece weights and the upward pass for the given densities.  The upward
+// pass always runs in FP64 (a small share of the work): a leaf's multipole
+// coefficients are sums of charges that can cancel by orders of magnitude
+// near cusps; FP32 copies of the finished coefficients feed the FP32 path.
 void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, int p,
-            hipStream_t st) {
+            bool want32, hipStream_t st) {
     const Geometry& G = s.geo;
     f.w64.alloc((size_t)6 * f.n_pieces);
-    if (sizeof(T) == 4) f.w32.alloc((size_t)6 * f.n_pieces);
+    if (want32) {
+        f.w32.alloc((size_t)6 * f.n_pieces);
+        f.heavy.alloc(f.n_pieces);
+    }
     launch_chord_weights(f.n_pieces, f.pseg.p, G.s, G.g, G.N, s.Pi.p, s.seg_kappa.p, sigma, mu,
-                         f.w64.p, sizeof(T) == 4 ? f.w32.p : nullptr, st);
-    DevBuf<T>& M = Bufs<T>::M(f);
-    M.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
+                         f.w64.p, want32 ? f.w32.p : nullptr, st);
+    const size_t nm = (size_t)f.n_cells * (p + 1) * 3 * 2;
+    f.M64.alloc(nm);
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(f.n_cells), dim3(kWave), 0, st, tv, pv, p, as_cpx(M));
+    hipLaunchKernelGGL(k_p2m<double>, dim3(f.n_cells), dim3(kWave), 0, st, tv, pv, p,
+                       as_cpx(f.M64));
     DC_HIP(hipGetLastError());
     for (int l = f.depth - 1; l >= 0; --l) {
         const int first = f.level_start[l], cnt = f.level_start[l + 1] - first;
         if (cnt <= 0) continue;
-        hipLaunchKernelGGL(k_m2m<T>, dim3(cnt), dim3(kWave), 0, st, tv, first, p, as_cpx(M));
+        hipLaunchKernelGGL(k_m2m<double>, dim3(cnt), dim3(kWave), 0, st, tv, first, p,
+                           as_cpx(f.M64));
+        DC_HIP(hipGetLastError());
+    }
+    if (want32) {
+        hipLaunchKernelGGL(k_heavy_flags, dim3((f.n_pieces + 255) / 256), dim3(256), 0, st,
+                           f.n_pieces, f.plen.p, f.w64.p, kHeavyTau, f.heavy.p);
+        DC_HIP(hipGetLastError());
+        f.M32.alloc(nm);
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, st, nm,
+                           f.M64.p, f.M32.p);
         DC_HIP(hipGetLastError());
     }
 }
@@ -696,7 +845,7 @@ template <typename T>
 void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, double* y,
                    const dc_eval_opts& o, hipStream_t st) {
     const int p = o.p;
-    upward<T>(s, f, sigma, mu, p, st);
+    upward(s, f, sigma, mu, p, sizeof(T) == 4, st);
     f.up_valid = false;  // the cache now holds these densities, not the scene's
     DevBuf<T>& L = Bufs<T>::L(f);
     L.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
@@ -772,7 +921,7 @@ void render_t(dc_scene_s& s, FmmState& f, const dc_viewport& vp, const dc_eval_o
     }
     if (f.timing) DC_HIP(hipEventRecord(f.ev[0], st));
     if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
-        upward<T>(s, f, s.d_sigma.p, s.d_mu.p, p, st);
+        upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st);
         f.up_valid = true;
         f.up_p = p;
         f.up_prec = (int)sizeof(T);

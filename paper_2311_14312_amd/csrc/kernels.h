@@ -60,4 +60,15 @@ void launch_axpby(int n, double a, const double* x, double b, const double* y, d
                   hipStream_t st);
 void launch_fill(int n, double v, double* out, hipStream_t st);
 
+// ------------------------------------------------- block-Jacobi preconditioner
+// D[c] = diagonal block of curve c (n = P g rows), row-major.
+void launch_curve_blocks(const NodesView& nodes, int P, int g, int s, const ChordsView& segs,
+                         const double* ell, const double* kappa, const double* Pi, double* D,
+                         hipStream_t st);
+void launch_invert_blocks(int n_blocks, int n, double* D, int* perm, int* singular,
+                          hipStream_t st);
+// y[ch] = blockdiag(Dinv) x[ch] for the three channels
+void launch_block_apply(int N, int n, const double* Dinv, const double* x, double* y,
+                        hipStream_t st);
+
 }  // namespace dc

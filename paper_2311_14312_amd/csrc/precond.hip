@@ -1,0 +1,179 @@
+// Block-Jacobi preconditioner for the hybrid collocation system: the
+// diagonal block of every curve, A_cc[i][i'] = sum_{j in panel(i')} Ghat_ij
+// Pi[j][i'] with the singular self-segment rule (the matrix of Eq.
+// hybrid_sys restricted to one curve), inverted in place on the device.
+// GMRES solves A M^-1 y = b, x = M^-1 y with M = blockdiag(A_cc): the linear
+// system and its solution are unchanged; a curve whose own geometry makes
+// the first-kind system ill-conditioned (a near-cusp folds two branches onto
+// each other) no longer stalls the iteration.
+#include "kernels.h"
+
+namespace dc {
+
+namespace {
+
+constexpr int kNT = 256;
+
+// One thread per (node i, panel p' of the node's curve): 16 entries of row i.
+__global__ void __launch_bounds__(kNT)
+k_curve_blocks(int N, int P, int g, int s, const double* __restrict__ nx,
+               const double* __restrict__ ny, const int* __restrict__ self_seg,
+               const double* __restrict__ tstar, ChordsView segs,
+               const double* __restrict__ ell, const double* __restrict__ kappa,
+               const double* __restrict__ Pi, double* __restrict__ D) {
+    const long long t = (long long)blockIdx.x * kNT + threadIdx.x;
+    const int n = P * g;
+    if (t >= (long long)N * P) return;
+    const int i = (int)(t / P), pp = (int)(t - (long long)i * P);
+    const int c = i / n, iloc = i - c * n;
+    const int panel = c * P + pp;
+    const double x = nx[i], y = ny[i];
+    const int self = self_seg[i];
+    double acc[64];
+    for (int m = 0; m < g; ++m) acc[m] = 0.0;
+    for (int jj = 0; jj < s; ++jj) {
+        const int j = panel * s + jj;
+        double G;
+        if (j == self) {
+            G = self_segment_2pi_G(ell[j], tstar[i]) / kTwoPi;
+        } else {
+            double il, th;
+            chord_log_theta<double>(segs.x0[j] - x, segs.y0[j] - y, segs.tx[j], segs.ty[j],
+                                    segs.len[j], il, th);
+            G = -kappa[j] * il / kTwoPi;
+        }
+        const double* pr = Pi + (size_t)jj * g;
+        for (int m = 0; m < g; ++m) acc[m] += G * pr[m];
+    }
+    double* row = D + (size_t)c * n * n + (size_t)iloc * n + (size_t)pp * g;
+    for (int m = 0; m < g; ++m) row[m] = acc[m];
+}
+
+// In-place Gauss-Jordan inversion with partial (row) pivoting, one
+// workgroup per block; the row interchanges are undone as column swaps at
+// the end.  A singular block leaves the flag set and its inverse undefined.
+__global__ void __launch_bounds__(kNT)
+k_gauss_jordan(int n, double* __restrict__ D, int* __restrict__ perm_all,
+               int* __restrict__ singular) {
+    __shared__ double sval[kNT];
+    __shared__ int sidx[kNT];
+    __shared__ double rowk[512], colk[512];
+    double* a = D + (size_t)blockIdx.x * n * n;
+    int* perm = perm_all + (size_t)blockIdx.x * n;
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        // pivot: largest |a[i][k]|, i >= k (first index on ties)
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < n; i += kNT) {
+            const double v = fabs(a[(size_t)i * n + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        sval[tid] = best;
+        sidx[tid] = bi;
+        __syncthreads();
+        for (int st = kNT / 2; st > 0; st >>= 1) {
+            if (tid < st) {
+                const double o = sval[tid + st];
+                const int oi = sidx[tid + st];
+                if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
+                    sval[tid] = o;
+                    sidx[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int pr = sidx[0];
+        const double pv = a[(size_t)pr * n + k];
+        if (tid == 0) {
+            perm[k] = pr;
+            if (pv == 0.0) singular[0] = 1;
+        }
+        __syncthreads();
+        // swap rows k and pr, then scale row k by 1/pivot (a[k][k] := 1 first)
+        const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
+        // column k of the other rows, read before anyone changes it (after the
+        // swap row pr holds the old row k)
+        for (int i = tid; i < n; i += kNT)
+            colk[i] = (i == pr) ? a[(size_t)k * n + k] : a[(size_t)i * n + k];
+        __syncthreads();
+        for (int j = tid; j < n; j += kNT) {
+            double vk = a[(size_t)k * n + j], vp = a[(size_t)pr * n + j];
+            if (pr != k) {
+                a[(size_t)pr * n + j] = vk;
+                vk = vp;
+            }
+            vk = (j == k) ? inv : vk * inv;
+            a[(size_t)k * n + j] = vk;
+            rowk[j] = vk;
+        }
+        __syncthreads();
+        // eliminate column k from every other row (a[i][k] := 0 first)
+        for (long long q = tid; q < (long long)n * n; q += kNT) {
+            const int i = (int)(q / n), j = (int)(q - (long long)i * n);
+            if (i == k) continue;
+            const double f = colk[i];
+            if (f == 0.0) continue;
+            if (j == k)
+                a[(size_t)i * n + j] = -f * rowk[k];
+            else
+                a[(size_t)i * n + j] -= f * rowk[j];
+        }
+        __syncthreads();
+    }
+    // undo the row interchanges as column interchanges, in reverse order
+    for (int k = n - 1; k >= 0; --k) {
+        const int pr = perm[k];
+        if (pr == k) continue;
+        for (int i = tid; i < n; i += kNT) {
+            const double t = a[(size_t)i * n + k];
+            a[(size_t)i * n + k] = a[(size_t)i * n + pr];
+            a[(size_t)i * n + pr] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// y[ch][i] = sum_j Dinv[c][iloc][j] x[ch][c n + j]
+__global__ void __launch_bounds__(kNT)
+k_block_apply(int N, int n, const double* __restrict__ Dinv, const double* __restrict__ x,
+              double* __restrict__ y) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const int ch = blockIdx.y;
+    if (i >= N) return;
+    const int c = i / n, iloc = i - c * n;
+    const double* row = Dinv + (size_t)c * n * n + (size_t)iloc * n;
+    const double* xv = x + (size_t)ch * N + (size_t)c * n;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += row[j] * xv[j];
+    y[(size_t)ch * N + i] = acc;
+}
+
+}  // namespace
+
+void launch_curve_blocks(const NodesView& nodes, int P, int g, int s, const ChordsView& segs,
+                         const double* ell, const double* kappa, const double* Pi, double* D,
+                         hipStream_t st) {
+    DC_REQUIRE(g <= 64, "block preconditioner supports at most 64 GL nodes per panel");
+    const long long threads = (long long)nodes.N * P;
+    hipLaunchKernelGGL(k_curve_blocks, dim3((unsigned)((threads + kNT - 1) / kNT)), dim3(kNT), 0,
+                       st, nodes.N, P, g, s, nodes.x, nodes.y, nodes.self_seg, nodes.tstar,
+                       segs, ell, kappa, Pi, D);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_invert_blocks(int n_blocks, int n, double* D, int* perm, int* singular,
+                          hipStream_t st) {
+    DC_REQUIRE(n <= 512, "block preconditioner supports at most 512 nodes per curve");
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(n_blocks), dim3(kNT), 0, st, n, D, perm, singular);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_block_apply(int N, int n, const double* Dinv, const double* x, double* y,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_block_apply, dim3((N + kNT - 1) / kNT, 3), dim3(kNT), 0, st, N, n, Dinv,
+                       x, y);
+    DC_HIP(hipGetLastError());
+}
+
+}  // namespace dc

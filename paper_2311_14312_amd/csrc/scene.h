@@ -27,6 +27,10 @@ struct dc_scene_s {
     dc::DevBuf<double> seg_w;
     bool seg_w_valid = false;
 
+    // Inverted per-curve diagonal blocks (block-Jacobi preconditioner).
+    dc::DevBuf<double> dinv;
+    bool dinv_valid = false;
+
     // FMM state (tree on device, expansions, scratch).
     std::unique_ptr<dc::FmmState> fmm;
 

@@ -33,7 +33,8 @@ class EvalOpts(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("matvec", EvalOpts)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("matvec", EvalOpts),
+                ("precond", C.c_int)]
 
 
 class Viewport(C.Structure):
@@ -197,9 +198,10 @@ class Scene:
             raise ValueError("boundary values must be [3, N]")
         _check(_lib.dc_set_boundary(self._h, _ptr(up), _ptr(um)))
 
-    def solve(self, tol=1e-10, max_iter=1000, raise_on_fail=False, **ev):
+    def solve(self, tol=1e-10, max_iter=1000, raise_on_fail=False, precond="block", **ev):
         o = SolveOpts()
         o.tol, o.max_iter, o.matvec = tol, max_iter, eval_opts(**ev)
+        o.precond = {"none": 0, "block": 1}[precond]
         rep = SolveReport()
         allow = () if raise_on_fail else (DC_ERR_NOT_CONVERGED,)
         rc = _check(_lib.dc_solve_densities(self._h, C.byref(o), C.byref(rep), _stream()),

@@ -40,7 +40,7 @@ def test_defaults_and_struct_sizes():
     dcfmm._lib.dc_default_eval_opts(ctypes.byref(e))
     assert e.p == 20 and e.method == dcfmm.METHOD_FMM and e.precision == dcfmm.PREC_F64
     assert ctypes.sizeof(dcfmm.EvalOpts) == 24
-    assert ctypes.sizeof(dcfmm.SolveOpts) == 40
+    assert ctypes.sizeof(dcfmm.SolveOpts) == 48
 
 
 def test_invalid_arguments_fail_cleanly_without_gpu():

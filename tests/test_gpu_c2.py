@@ -1,0 +1,71 @@
+"""Full-size parity on the 200-curve FMM workload (51,200 nodes, 256,000
+segments, 2048 x 2048 pixels), in the launch configuration bench.py times,
+checked at 1,536 sampled pixels (stride-64 grid + pixels holding chord
+midpoints) against stored FP64 oracle values (tests/golden, written by the
+committed scripts there from the oracle's dense LU densities)."""
+import os
+
+import numpy as np
+import pytest
+
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden")
+CFG = scenegen.FMM
+VP = CFG["viewport"]
+
+
+@pytest.fixture(scope="module")
+def gold():
+    s = np.load(os.path.join(GOLD, "c2_sigma.npz"))
+    t = np.load(os.path.join(GOLD, "c2_samples.npz"))
+    return dict(sigma=s["sigma"], node_xy=s["node_xy"], rows=t["rows"], cols=t["cols"],
+                vals=t["vals"])
+
+
+@pytest.fixture(scope="module")
+def scene(gpu_lib):
+    sc = scenegen.sized_scene(n_curves=CFG["n_curves"], n_stops=CFG["n_stops"],
+                              seed=CFG["seed"])
+    s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=CFG["panels"],
+                      gl=CFG["gl"], segs=CFG["segs"], leaf_max=CFG["leaf_max"])
+    print("C2 scene", s.info(), flush=True)
+    yield s
+    s.close()
+
+
+def _err(img, gold):
+    return np.abs(img[gold["rows"], gold["cols"]] - gold["vals"]).max()
+
+
+def test_c2_nodes(scene, gold):
+    np.testing.assert_allclose(scene.nodes(), gold["node_xy"], atol=1e-12, rtol=0)
+
+
+def test_c2_render_with_oracle_densities(scene, gold):
+    import torch
+    scene.set_densities(gold["sigma"])
+    img32 = scene.render(VP, method="fmm", precision="f32", p=16, tile_px=8).cpu().numpy()
+    img64 = scene.render(VP, out_dtype=torch.float64, method="fmm", precision="f64",
+                         p=40).cpu().numpy()
+    e32, e64 = _err(img32, gold), _err(img64, gold)
+    print(f"C2 render vs oracle (oracle densities): FP32 {e32:.3e}  FP64 p=40 {e64:.3e}",
+          flush=True)
+    assert e64 <= 1e-8
+    assert e32 <= 1e-4
+
+
+def test_c2_solve_and_render(scene, gold):
+    rep = scene.solve(tol=CFG["gmres_tol"], max_iter=1000, method="fmm", p=CFG["p"])
+    print("C2 FMM GMRES", rep, flush=True)
+    import torch
+    img32 = scene.render(VP, method="fmm", precision="f32", p=16, tile_px=8).cpu().numpy()
+    img64 = scene.render(VP, out_dtype=torch.float64, method="fmm", p=40).cpu().numpy()
+    e32, e64 = _err(img32, gold), _err(img64, gold)
+    print(f"C2 end-to-end render vs oracle: FP32 {e32:.3e}  FP64 p=40 {e64:.3e}", flush=True)
+    assert rep["converged"]
+    assert e32 <= 1e-4
+    assert e64 <= 1e-6

@@ -140,3 +140,22 @@ def test_render_counts_are_consistent(scene, ref):
     # every pixel is evaluated from an incoming expansion exactly once
     assert c["l2p_targets"] == 256 * 256
     assert c["p2p_pairs"] > 0 and c["m2l_pairs"] > 0
+
+
+def test_block_preconditioner_same_solution(gpu_lib, ref):
+    """Right block-Jacobi preconditioning changes the iteration, not the
+    solution of the hybrid system."""
+    sc = ref["sc"]
+    s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=CFG["panels"],
+                      gl=CFG["gl"], segs=CFG["segs"], leaf_max=16)
+    r0 = s.solve(tol=1e-13, max_iter=512, method="fmm", p=40, precond="none")
+    s0 = s.densities()
+    r1 = s.solve(tol=1e-13, max_iter=512, method="fmm", p=40, precond="block")
+    s1 = s.densities()
+    print("iterations none/block", r0["iters"], r1["iters"], flush=True)
+    assert r0["converged"] and r1["converged"]
+    assert max(r1["iters"]) < max(r0["iters"])
+    scale = np.abs(ref["sigma"]).max()
+    assert np.abs(s1 - ref["sigma"]).max() <= 1e-8 * scale
+    assert np.abs(s0 - s1).max() <= 1e-8 * scale
+    s.close()
