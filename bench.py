@@ -90,10 +90,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--p32", type=int, default=16, help="expansion order, FP32 path")
+    ap.add_argument("--orders", default="8,10,12,14,16,18,20",
+                    help="expansion orders tried for the FP32 path (smallest meeting 5e-5)")
     ap.add_argument("--p64", type=int, default=20, help="expansion order, FP64 path")
-    ap.add_argument("--tile", type=int, default=8)
-    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--tiles", default="8,16")
+    ap.add_argument("--leaves", default="16,32,64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
@@ -118,36 +119,73 @@ def main():
     import torch
     from paper_2311_14312_amd import dcfmm
     torch.cuda.set_device(0)
-    t0 = time.time()
-    scene = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
-                        gl=cfg["gl"], segs=cfg["segs"], leaf_max=args.leaf)
-    t_create = time.time() - t0
-    info = scene.info()
-    print("scene", info, f"create {t_create:.2f} s", flush=True)
-    rep = scene.solve(tol=cfg["gmres_tol"], max_iter=1000, method="fmm", p=args.p64)
-    print("solve", rep, flush=True)
 
-    def timed(ev, steps, warmup, dtype):
+    def make_scene(leaf):
+        t0 = time.time()
+        sc_ = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
+                          gl=cfg["gl"], segs=cfg["segs"], leaf_max=leaf)
+        t_create = time.time() - t0
+        rep_ = sc_.solve(tol=cfg["gmres_tol"], max_iter=1000, method="fmm", p=args.p64)
+        print(f"leaf {leaf}: scene {sc_.info()} create {t_create:.2f} s, solve {rep_}",
+              flush=True)
+        return sc_, rep_, t_create
+
+    def timed(scene, ev, steps, warmup, dtype):
         out = torch.empty((H, W, 3), device="cuda", dtype=dtype)
         for _ in range(warmup):
             scene.render(vp, out=out, **ev)
         torch.cuda.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         stop = torch.cuda.Event(enable_timing=True)
-        t = time.perf_counter()
         start.record()
         for _ in range(steps):
             scene.render(vp, out=out, **ev)
         stop.record()
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t
-        return start.elapsed_time(stop) / steps, wall / steps, out
+        return start.elapsed_time(stop) / steps, out
 
-    ev32 = dict(method="fmm", precision="f32", p=args.p32, tile_px=args.tile)
-    ev64 = dict(method="fmm", precision="f64", p=args.p64, tile_px=args.tile)
-    ms32, wall32, img32 = timed(ev32, args.steps, args.warmup, torch.float32)
+    def sample_err(img):
+        if cpu is None or cpu["vals"] is None:
+            return None
+        return float(np.abs(img[cpu["rows"], cpu["cols"]] - cpu["vals"]).max())
+
+    # Autotune: leaf capacity and tile size by time; for each, the smallest
+    # expansion order whose sampled error against the oracle is <= 5e-5
+    # (half the bar).  Without oracle values the order is fixed.
+    leaves = [int(v) for v in args.leaves.split(",")]
+    tiles = [int(v) for v in args.tiles.split(",")]
+    orders = [int(v) for v in args.orders.split(",")]
+    tune = []
+    best = None
+    scenes = {}
+    for leaf in leaves:
+        scn, rep, t_create = make_scene(leaf)
+        scenes[leaf] = (scn, rep, t_create)
+        for tile in tiles:
+            chosen = orders[-1]
+            if cpu is not None and cpu["vals"] is not None:
+                for pp in orders:
+                    img = scn.render(vp, method="fmm", precision="f32", p=pp, tile_px=tile)
+                    if sample_err(img.cpu().numpy()) <= 5e-5:
+                        chosen = pp
+                        break
+            ev = dict(method="fmm", precision="f32", p=chosen, tile_px=tile)
+            ms, _ = timed(scn, ev, 5, 2, torch.float32)
+            tune.append({"leaf": leaf, "tile": tile, "p": chosen, "ms": ms})
+            print("autotune", tune[-1], flush=True)
+            if best is None or ms < best["ms"]:
+                best = dict(tune[-1])
+        if best["leaf"] != leaf:
+            scn.close()
+            del scenes[leaf]
+    scene, rep, t_create = scenes[best["leaf"]]
+    p32, tile, leaf = best["p"], best["tile"], best["leaf"]
+
+    ev32 = dict(method="fmm", precision="f32", p=p32, tile_px=tile)
+    ev64 = dict(method="fmm", precision="f64", p=args.p64, tile_px=tile)
+    ms32, img32 = timed(scene, ev32, args.steps, args.warmup, torch.float32)
     img32 = img32.cpu().numpy()
-    ms64, wall64, img64 = timed(ev64, max(1, args.steps // 2), 1, torch.float64)
+    ms64, img64 = timed(scene, ev64, max(1, args.steps // 2), 1, torch.float64)
     img64 = img64.cpu().numpy()
     print(f"FP32 {ms32:.3f} ms/step, FP64 {ms64:.3f} ms/step", flush=True)
 
@@ -159,7 +197,7 @@ def main():
     scene.set_timing(False)
     counts = scene.render_counts(vp, **ev32)
     leaf_ms = tm["leaf_ms"] / max(1, tm["calls"])
-    fl = leaf_flops(counts, args.p32)
+    fl = leaf_flops(counts, p32)
     achieved = fl / (leaf_ms * 1e-3)
     scene.set_timing(True)
     for _ in range(max(1, args.steps // 2)):
@@ -171,10 +209,7 @@ def main():
     achieved64 = leaf_flops(counts64, args.p64) / (leaf64_ms * 1e-3)
 
     px = W * H
-    err32 = err64 = None
-    if cpu is not None and cpu["vals"] is not None:
-        err32 = float(np.abs(img32[cpu["rows"], cpu["cols"]] - cpu["vals"]).max())
-        err64 = float(np.abs(img64[cpu["rows"], cpu["cols"]] - cpu["vals"]).max())
+    err32, err64 = sample_err(img32), sample_err(img64)
     line = {
         "metric": METRIC,
         "value": px / (ms32 * 1e-3),
@@ -191,8 +226,8 @@ def main():
         "config": {"workload": "200 random cubic Beziers (lengths log-uniform 0.01-0.5), "
                                "16 panels x 16 GL nodes (51,200 nodes), 80 segments/panel, "
                                "3 colour stops/side; 2048x2048 render of [0,1]^2",
-                   "p_fp32": args.p32, "p_fp64": args.p64, "tile_px": args.tile,
-                   "leaf_max": args.leaf, "gmres_tol": cfg["gmres_tol"]},
+                   "p_fp32": p32, "p_fp64": args.p64, "tile_px": tile,
+                   "leaf_max": leaf, "gmres_tol": cfg["gmres_tol"], "autotune": tune},
         "max_err_vs_oracle": err32,
         "err_sample": (f"{cpu['n']} pixels (128x128 stride-16 grid + 4096 near-chord)"
                        if cpu else None),
@@ -204,11 +239,12 @@ def main():
         "speedup_fp32_vs_fp64": ms64 / ms32,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_leaf<float,64>", "kernel_ms": leaf_ms,
+                     "kernel": f"k_leaf<float,{64 if tile <= 8 else 256}>",
+                     "kernel_ms": leaf_ms,
                      "flop_eq_per_launch": fl},
         "phases_ms": {k: v / max(1, tm["calls"]) for k, v in tm.items() if k.endswith("_ms")},
         "work": counts,
-        "solve": {"seconds": rep["seconds"], "iters": rep["iters"],
+        "solve": {"seconds": rep["seconds"], "iters": rep["iters"], "precond": "block",
                   "true_rel_residual": rep["true_rel_residual"], "p": args.p64,
                   "scene_create_s": t_create},
         "cpu_baseline": None if cpu is None else {
@@ -218,7 +254,8 @@ def main():
                       f"segments, FP64 NumPy direct sum ({cpu['seconds']:.1f} s)"},
     }
     print(json.dumps(line), flush=True)
-    scene.close()
+    for scn, _, _ in scenes.values():
+        scn.close()
 
 
 if __name__ == "__main__":

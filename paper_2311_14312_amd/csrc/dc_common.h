@@ -98,9 +98,12 @@ __device__ inline cpx<T> cdiv(cpx<T> a, cpx<T> b) {
         return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
     }
 }
+// 1/b = conj(b)/|b|^2 with one real division (the operands here are box-
+// relative coordinates of moderate magnitude, so no scaling is needed).
 template <typename T>
 __device__ inline cpx<T> cinv(cpx<T> b) {
-    return cdiv<T>({T(1), T(0)}, b);
+    const T r = T(1) / (b.re * b.re + b.im * b.im);
+    return {b.re * r, -b.im * r};
 }
 // Principal logarithm.
 template <typename T>

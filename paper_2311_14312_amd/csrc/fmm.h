@@ -27,16 +27,15 @@ struct FmmState {
     DevBuf<double> w64;
     DevBuf<float> w32;
     DevBuf<int> heavy;  // FP32 path: pieces evaluated in FP64
-    // Multipole and local coefficients of the source tree, and near sets.
+    // Multipole and local coefficients of the source tree (FP64 in both
+    // precision modes), and near sets.
     DevBuf<double> M64, L64;
-    DevBuf<float> M32, L32;
     DevBuf<int> nsetS;
     // Upward pass of the resident densities (render reuses it).
     bool up_valid = false;
     int up_p = -1, up_prec = -1;
     // Render scratch: local coefficients and near sets of target boxes.
     DevBuf<double> TL64;
-    DevBuf<float> TL32;
     DevBuf<int> Tnset;
     // Optional device work counters (counting runs only) and phase timing.
     unsigned long long* stats = nullptr;

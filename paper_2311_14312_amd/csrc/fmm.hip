@@ -39,6 +39,22 @@ constexpr int kSCap = 256;   // traversal stack (>= 9 + 4 * max depth)
 enum { kStatP2P = 0, kStatP2P64, kStatM2P, kStatL2P, kStatM2L, kStatP2L, kStatL2L, kStatLeaf,
        kNStat };
 
+// 1/n for n < 128 (entry 0 unused): the coefficient recurrences of the
+// translation operators multiply by these instead of dividing (an FP64
+// division is a long instruction sequence on this hardware).
+struct RecipTable {
+    double v[128];
+    constexpr RecipTable() : v() {
+        for (int i = 1; i < 128; ++i) v[i] = 1.0 / i;
+    }
+};
+__constant__ RecipTable kRecip = RecipTable();
+
+template <typename T>
+__device__ inline T recip(int n) {
+    return (T)kRecip.v[n];
+}
+
 struct TreeView {
     int n_cells;
     double X0, Y0, side;
@@ -114,19 +130,38 @@ __device__ inline float atan2_poly(float y, float x) {
     return copysignf(r, y);
 }
 
-// FP32 chord integral for a pair that is neither near-singular nor heavy:
-// both endpoint logarithms from the hardware log2 (the cancellation of the
-// two x ln r terms costs at most (distance / chord) ulps, far inside the
-// FP32 error budget for near-field pairs).
+// Natural logarithm from the hardware log2 (v_log_f32).
+__device__ inline float fast_ln(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718056f;
+}
+
+// log(1 + x) for x in [-1, 0] to a few ulps from one hardware logarithm:
+// with u = 1 + x rounded, log(u) * x / (u - 1) cancels the rounding of u
+// (the classical correction for log1p from a plain log).
+__device__ inline float fast_log1p(float x) {
+    const float u = 1.0f + x;
+    const float d = u - 1.0f;
+    const float v = fast_ln(fmaxf(u, 1e-37f)) * (x * __builtin_amdgcn_rcpf(d));
+    return d == 0.0f ? x : v;  // select, no branch
+}
+
+// FP32 chord integral for a pair that is neither near-singular nor heavy,
+// in the stable form of chord_log_theta (log of the farther endpoint plus a
+// log1p of the ratio), so the rounding error scales with the chord length,
+// not with the distance to the target.
 __device__ inline void chord_fast(float xi1, float h, float xi2, float la, float& il,
                                   float& th) {
-    const float r1 = fmaxf(xi1 * xi1 + h * h, 1e-37f);
-    const float r2 = fmaxf(xi2 * xi2 + h * h, 1e-37f);
+    const float r1 = xi1 * xi1 + h * h;
+    const float r2 = xi2 * xi2 + h * h;
     th = atan2_poly(h * la, h * h + xi1 * xi2);
-    constexpr float half_ln2 = 0.34657359028f;  // ln(2)/2: log2 -> ln of the square root
-    const float l1 = __builtin_amdgcn_logf(r1) * half_ln2;
-    const float l2 = __builtin_amdgcn_logf(r2) * half_ln2;
-    il = xi2 * l2 - xi1 * l1 - la + h * th;
+    const float sm = la * (xi1 + xi2);  // r2^2 - r1^2
+    const bool one = r1 >= r2;
+    const float big = fmaxf(one ? r1 : r2, 1e-37f);
+    const float xo = one ? xi2 : -xi1;
+    const float arg = (one ? sm : -sm) * __builtin_amdgcn_rcpf(big);
+    const float l1p = fast_log1p(arg);
+    const float tail = xo == 0.f ? 0.f : xo * 0.5f * l1p;
+    il = la * 0.5f * fast_ln(big) + tail - la + h * th;
 }
 
 // ------------------------------------------------------------------ upward
@@ -187,7 +222,7 @@ k_m2m(TreeView tv, int first, int p, cpx<T>* __restrict__ M) {
         for (int l = k; l >= 0; --l) {
             const cpx<T> f = cscale(pw, binom * sc);
             for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[l * 3 + ch]));
-            binom = binom * (T)l / (T)(k - l + 1);
+            binom = binom * (T)l * recip<T>(k - l + 1);
             sc *= (T)2;
             pw = cmul(pw, z0);
         }
@@ -217,7 +252,7 @@ __device__ inline void m2l_lane(cpx<T> acc[3], const cpx<T>* __restrict__ src, i
                                 cpx<T> w, cpx<T> logd) {
     cpx<T> pw = cpow(w, k);
     const T sign = (k & 1) ? T(-1) : T(1);
-    T coef = k == 0 ? T(0) : T(1) / (T)k;
+    T coef = k == 0 ? T(0) : recip<T>(k);
     for (int m = 0; m <= p; ++m) {
         cpx<T> t;
         if (k == 0 && m == 0) {
@@ -225,7 +260,7 @@ __device__ inline void m2l_lane(cpx<T> acc[3], const cpx<T>* __restrict__ src, i
             coef = T(1);
         } else {
             t = cscale(pw, sign * coef);
-            coef = coef * (T)(k + m) / (T)(m + 1);
+            coef = coef * (T)(k + m) * recip<T>(m + 1);
         }
         for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(t, src[m * 3 + ch]));
         pw = cmul(pw, w);
@@ -304,9 +339,9 @@ __device__ void p2l_wave(cpx<T> acc[3], const PieceView& pv, const TreeView& tv,
                     pa = zA;
                     pb = zB;
                 } else {
-                    sv = cmul(wbar, cscale(csub(pa, pb), rr / (T)(k * (k - 1))));
+                    sv = cmul(wbar, cscale(csub(pa, pb), rr * recip<T>(k) * recip<T>(k - 1)));
                     const cpx<T> na = cmul(pa, zA), nb = cmul(pb, zB);
-                    const cpx<T> d = cscale(csub(nb, na), T(1) / (T)k);
+                    const cpx<T> d = cscale(csub(nb, na), recip<T>(k));
                     mv = {-d.im, d.re};
                     pa = na;
                     pb = nb;
@@ -361,8 +396,15 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         }
         nset[(size_t)own * 9 + lane] = c;
     }
-    const int k = lane;
-    const bool klane = k <= p;  // lanes above p only help with the pieces
+    // Lane layout: the wave holds ngrp groups of p+1 lanes; lane k of group g
+    // owns coefficient k for the interaction-list entries g, g + ngrp, ...
+    // Group 0 owns the result (L2L, P2L and the final sum).
+    const int P1 = p + 1;
+    const int ngrp = kWave / P1;
+    const int grp = lane / P1;
+    const int k = lane - grp * P1;
+    const bool klane = grp == 0;           // owns coefficient k of the result
+    const bool glane = grp < ngrp;         // takes part in the interaction list
     const double r = half_width(tv, l);
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
@@ -371,37 +413,67 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
     //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
     if (klane) {
         const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
-        const cpx<T>* src = L + (size_t)par * (p + 1) * 3;
+        const cpx<T>* src = L + (size_t)par * P1 * 3;
         cpx<T> pw = {1, 0};
         T binom = 1;
         const T sc = (T)ldexp(1.0, -k);
         for (int m = k; m <= p; ++m) {
             const cpx<T> f = cscale(pw, binom * sc);
             for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
-            binom = binom * (T)(m + 1) / (T)(m + 1 - k);
+            binom = binom * (T)(m + 1) * recip<T>(m + 1 - k);
             pw = cmul(pw, z0);
         }
     }
-    // interaction list
-    const double log2r = log(2.0 * r);
-    for (int s = 0; s < 9 && klane; ++s) {
-        const int c = sPN[s];
-        if (c < 0 || tv.lvl[c] != l - 1 || tv.child[c] < 0) continue;
-        const long long ppx = (ti >> 1) + (s % 3) - 1, ppy = (tj >> 1) + (s / 3) - 1;
-        for (int q = 0; q < 4; ++q) {
-            const int d = tv.child[c] + q;
-            const long long dx = 2 * ppx + (q & 1) - ti, dy = 2 * ppy + (q >> 1) - tj;
-            if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
-            if (tv.npc[d] == 0) continue;
-            // c_target - c_source = -(dx, dy) * 2r
-            const double ddx = -(double)dx, ddy = -(double)dy;
-            const double inv = 1.0 / (2.0 * (ddx * ddx + ddy * ddy));
-            const cpx<T> w = {(T)(ddx * inv), (T)(-ddy * inv)};  // r / d
-            const cpx<T> logd = {(T)(log2r + 0.5 * log(ddx * ddx + ddy * ddy)),
-                                 (T)atan2(ddy, ddx)};
-            m2l_lane<T>(acc, M + (size_t)d * (p + 1) * 3, p, k, w, logd);
-            if (dl.stats && k == 0) atomicAdd(dl.stats + kStatM2L, 1ULL);
+    // interaction list: 36 candidates (children of the parent's 9 near-set
+    // boxes), compacted with a ballot so every group gets one entry per round
+    __shared__ int sIL[36];
+    __shared__ signed char sDx[36], sDy[36];
+    {
+        bool valid = false;
+        int d = -1;
+        long long dx = 0, dy = 0;
+        if (lane < 36) {
+            const int sl = lane >> 2, q = lane & 3;
+            const int c = sPN[sl];
+            if (c >= 0 && tv.lvl[c] == l - 1 && tv.child[c] >= 0) {
+                const long long ppx = (ti >> 1) + (sl % 3) - 1, ppy = (tj >> 1) + (sl / 3) - 1;
+                d = tv.child[c] + q;
+                dx = 2 * ppx + (q & 1) - ti;
+                dy = 2 * ppy + (q >> 1) - tj;
+                valid = !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) && tv.npc[d] > 0;
+            }
         }
+        const unsigned long long mask = __ballot(valid);
+        if (valid) {
+            const int at = __popcll(mask & ((1ULL << lane) - 1ULL));
+            sIL[at] = d;
+            sDx[at] = (signed char)dx;
+            sDy[at] = (signed char)dy;
+        }
+        __syncthreads();
+        const int nIL = __popcll(mask);
+        const double log2r = log(2.0 * r);
+        cpx<T> gacc[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int base = 0; base < nIL; base += ngrp) {
+            const int e = base + grp;
+            if (!glane || e >= nIL) continue;
+            // c_target - c_source = -(dx, dy) * 2r
+            const double ddx = -(double)sDx[e], ddy = -(double)sDy[e];
+            const double n2 = ddx * ddx + ddy * ddy;
+            const double inv = 0.5 / n2;
+            const cpx<T> w = {(T)(ddx * inv), (T)(-ddy * inv)};  // r / d
+            const cpx<T> logd = {(T)(log2r + 0.5 * log(n2)), (T)atan2(ddy, ddx)};
+            m2l_lane<T>(gacc, M + (size_t)sIL[e] * P1 * 3, p, k, w, logd);
+        }
+        if (dl.stats && lane == 0) atomicAdd(dl.stats + kStatM2L, (unsigned long long)nIL);
+        // reduce the groups into group 0
+        __shared__ cpx<T> sRed[kWave][3];
+        if (glane)
+            for (int ch = 0; ch < 3; ++ch) sRed[lane][ch] = gacc[ch];
+        __syncthreads();
+        if (klane)
+            for (int g = 0; g < ngrp; ++g)
+                for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], sRed[g * P1 + k][ch]);
     }
     // bigger separated list: coarser source leaves that do not touch us;
     // their pieces are flattened into one list shared by the wave
@@ -421,7 +493,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         // always in FP64: pieces of one leaf can carry large charges of both
         // signs whose sum cancels (near-cusps), beyond FP32's reach
         cpx<double> accd[3] = {{0, 0}, {0, 0}, {0, 0}};
-        p2l_wave<double>(accd, pv, tv, l4, pre, nl4, cx, cy, r, p, k);
+        p2l_wave<double>(accd, pv, tv, l4, pre, nl4, cx, cy, r, p, lane);
         for (int ch = 0; ch < 3; ++ch) {
             acc[ch].re += (T)accd[ch].re;
             acc[ch].im += (T)accd[ch].im;
@@ -432,7 +504,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         atomicAdd(dl.stats + kStatL2L, 1ULL);
     }
     if (!klane) return;
-    cpx<T>* out = L + ((size_t)own * (p + 1) + k) * 3;
+    cpx<T>* out = L + ((size_t)own * P1 + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
 }
 
@@ -491,8 +563,8 @@ __device__ inline int first_true_row(const LeafArgs& a, double Y0, double sideL,
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
-k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ M,
-       const cpx<T>* __restrict__ Lc, const int* __restrict__ nset) {
+k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
+       const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
     __shared__ LeafShared<T, NT> sh;
     const int tid = threadIdx.x;
     long long ti, tj;
@@ -524,7 +596,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
     const T* wts = weights<T>(pv);
-    const cpx<T>* loc = Lc + (size_t)own * (p + 1) * 3;
+    const cpx<double>* loc = Lc + (size_t)own * (p + 1) * 3;
 
     for (int tbase = 0; tbase < n_targets; tbase += NT) {
         const int tgt = tbase + tid;
@@ -545,13 +617,15 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
             }
         }
         const T xr = (T)(x - cx), yr = (T)(y - cy);
-        T accE[3] = {0, 0, 0}, accP[3] = {0, 0, 0};
+        double accE[3] = {0, 0, 0};
+        // near-field sums are kept in FP64 (an FP64 add issues at the FP32 rate)
+        double accP[3] = {0, 0, 0};
         double acc64[3] = {0, 0, 0};
         // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
         if (l >= 2) {
-            const cpx<T> z = {(T)((x - cx) / r), (T)((y - cy) / r)};
+            const cpx<double> z = {(x - cx) / r, (y - cy) / r};
             for (int ch = 0; ch < 3; ++ch) {
-                cpx<T> s = loc[p * 3 + ch];
+                cpx<double> s = loc[p * 3 + ch];
                 for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
                 accE[ch] += s.re;
             }
@@ -620,17 +694,17 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
                     const double rd = half_width(tv, ld);
                     double dcx, dcy;
                     center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
-                    const cpx<T> rel = {(T)((x - dcx) / rd), (T)((y - dcy) / rd)};
-                    const cpx<T> z = cinv(rel);
-                    const cpx<T> lg = clog(rel);
-                    const T lr = (T)log(rd);
-                    const cpx<T>* src = M + (size_t)d * (p + 1) * 3;
+                    const cpx<double> rel = {(x - dcx) / rd, (y - dcy) / rd};
+                    const cpx<double> z = cinv(rel);
+                    const cpx<double> lg = clog(rel);
+                    const double lr = log(rd);
+                    const cpx<double>* src = M + (size_t)d * (p + 1) * 3;
                     for (int ch = 0; ch < 3; ++ch) {
-                        cpx<T> s = cscale(src[p * 3 + ch], T(1) / (T)p);
+                        cpx<double> s = cscale(src[p * 3 + ch], recip<double>(p));
                         for (int kk = p - 1; kk >= 1; --kk)
-                            s = cadd(cmul(s, z), cscale(src[kk * 3 + ch], T(1) / (T)kk));
+                            s = cadd(cmul(s, z), cscale(src[kk * 3 + ch], recip<double>(kk)));
                         s = cmul(s, z);
-                        const cpx<T> m0 = src[ch];
+                        const cpx<double> m0 = src[ch];
                         // Re(-(lr + lg) * m0)
                         accE[ch] += s.re - ((lr + lg.re) * m0.re - lg.im * m0.im);
                     }
@@ -668,8 +742,9 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
                             const float xi1 = (float)dx * tx + (float)dy * ty;
                             const float h = (float)dy * tx - (float)dx * ty;
                             const float xi2 = xi1 + la;
-                            const float dd = xi1 > 0.f ? xi1 * xi1 + h * h
-                                                       : (xi2 < 0.f ? xi2 * xi2 + h * h : h * h);
+                            // squared distance to the chord, branch-free
+                            const float along = fmaxf(xi1, 0.f) + fmaxf(-xi2, 0.f);
+                            const float dd = along * along + h * h;
                             const int pid = sh.pid[j];
                             if (dd < near2f * la * la || pid < 0) {
                                 // near-singular pair or heavy piece: closed form in FP64
@@ -686,7 +761,8 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
                             float il, th;
                             chord_fast(xi1, h, xi2, la, il, th);
                             for (int ch = 0; ch < 3; ++ch)
-                                accP[ch] += (T)(il * (float)sh.w[ch][j] + th * (float)sh.w[3 + ch][j]);
+                                accP[ch] += (double)(il * (float)sh.w[ch][j] +
+                                                     th * (float)sh.w[3 + ch][j]);
                             continue;
                         }
                         T il, th;
@@ -701,7 +777,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<T>* __restrict__ 
         }
         if (active) {
             for (int ch = 0; ch < 3; ++ch) {
-                const double u = ((double)accE[ch] - (double)accP[ch] - acc64[ch]) / kTwoPi;
+                const double u = (accE[ch] - accP[ch] - acc64[ch]) / kTwoPi;
                 if (a.solve) {
                     a.y[(size_t)ch * a.N + out_idx] = u;
                 } else if (a.out_f64) {
@@ -763,21 +839,6 @@ PieceView piece_view(const FmmState& f) {
 }
 
 template <typename T>
-struct Bufs;
-template <>
-struct Bufs<double> {
-    static DevBuf<double>& M(FmmState& f) { return f.M64; }
-    static DevBuf<double>& L(FmmState& f) { return f.L64; }
-    static DevBuf<double>& TL(FmmState& f) { return f.TL64; }
-};
-template <>
-struct Bufs<float> {
-    static DevBuf<float>& M(FmmState& f) { return f.M32; }
-    static DevBuf<float>& L(FmmState& f) { return f.L32; }
-    static DevBuf<float>& TL(FmmState& f) { return f.TL32; }
-};
-
-template <typename T>
 cpx<T>* as_cpx(DevBuf<T>& b) {
     return reinterpret_cast<cpx<T>*>(b.p);
 }
@@ -792,20 +853,16 @@ k_heavy_flags(int n, const double* __restrict__ len, const double* __restrict__ 
     heavy[e] = m * len[e] > tau ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(256)
-k_to_f32(size_t n, const double* __restrict__ a, float* __restrict__ b) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
-}
-
 // Pieces whose charge times length exceeds this are evaluated in FP64 by the
 // FP32 path (their FP32 rounding alone would approach the error budget).
 constexpr double kHeavyTau = 1.0;
 
-// Piece weights and the upward pass for the given densities.  The upward
-// pass always runs in FP64 (a small share of the work): a leaf's multipole
-// coefficients are sums of charges that can cancel by orders of magnitude
-// near cusps; FP32 copies of the finished coefficients feed the FP32 path.
+// Piece weights and the upward pass for the given densities.  Expansions are
+// FP64 in both precision modes: on this hardware an FP64 FMA issues at the
+// rate of an unpacked FP32 one, and a leaf's coefficients are sums of charges
+// that can cancel by orders of magnitude near cusps.  The FP32 mode keeps
+// FP32 for the near-field closed forms, whose logarithms and arctangent are
+// where FP64 costs many more instructions.
 void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, int p,
             bool want32, hipStream_t st) {
     const Geometry& G = s.geo;
@@ -834,10 +891,6 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
         hipLaunchKernelGGL(k_heavy_flags, dim3((f.n_pieces + 255) / 256), dim3(256), 0, st,
                            f.n_pieces, f.plen.p, f.w64.p, kHeavyTau, f.heavy.p);
         DC_HIP(hipGetLastError());
-        f.M32.alloc(nm);
-        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, st, nm,
-                           f.M64.p, f.M32.p);
-        DC_HIP(hipGetLastError());
     }
 }
 
@@ -847,13 +900,13 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
     const int p = o.p;
     upward(s, f, sigma, mu, p, sizeof(T) == 4, st);
     f.up_valid = false;  // the cache now holds these densities, not the scene's
-    DevBuf<T>& L = Bufs<T>::L(f);
+    DevBuf<double>& L = f.L64;
     L.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
     f.nsetS.alloc((size_t)f.n_cells * 9);
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
-    DevBuf<T>& M = Bufs<T>::M(f);
-    hipLaunchKernelGGL(k_init_root<T>, dim3(1), dim3(kWave), 0, st, p, as_cpx(L), f.nsetS.p);
+    DevBuf<double>& M = f.M64;
+    hipLaunchKernelGGL(k_init_root<double>, dim3(1), dim3(kWave), 0, st, p, as_cpx(L), f.nsetS.p);
     DC_HIP(hipGetLastError());
     for (int l = 1; l <= f.depth; ++l) {
         DownLevel dl{};
@@ -862,7 +915,7 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
         dl.first = f.level_start[l];
         const int cnt = f.level_start[l + 1] - dl.first;
         if (cnt <= 0) continue;
-        hipLaunchKernelGGL(k_down<T>, dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p, as_cpx(M),
+        hipLaunchKernelGGL(k_down<double>, dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p, as_cpx(M),
                            as_cpx(L), f.nsetS.p);
         DC_HIP(hipGetLastError());
     }
@@ -926,15 +979,15 @@ void render_t(dc_scene_s& s, FmmState& f, const dc_viewport& vp, const dc_eval_o
         f.up_p = p;
         f.up_prec = (int)sizeof(T);
     }
-    DevBuf<T>& TL = Bufs<T>::TL(f);
+    DevBuf<double>& TL = f.TL64;
     const size_t need = (size_t)off[Lt + 1] * (p + 1) * 3 * 2;
     if (TL.n < need) TL.alloc(need);
     if (f.Tnset.n < (size_t)off[Lt + 1] * 9) f.Tnset.alloc((size_t)off[Lt + 1] * 9);
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
-    DevBuf<T>& M = Bufs<T>::M(f);
+    DevBuf<double>& M = f.M64;
     if (f.timing) DC_HIP(hipEventRecord(f.ev[1], st));
-    hipLaunchKernelGGL(k_init_root<T>, dim3(1), dim3(kWave), 0, st, p, as_cpx(TL), f.Tnset.p);
+    hipLaunchKernelGGL(k_init_root<double>, dim3(1), dim3(kWave), 0, st, p, as_cpx(TL), f.Tnset.p);
     DC_HIP(hipGetLastError());
     for (int l = 1; l <= Lt; ++l) {
         DownLevel dl{};
@@ -949,7 +1002,7 @@ void render_t(dc_scene_s& s, FmmState& f, const dc_viewport& vp, const dc_eval_o
         dl.pwl = (int)(i1[l - 1] - i0[l - 1] + 1);
         dl.off = off[l];
         dl.poff = off[l - 1];
-        hipLaunchKernelGGL(k_down<T>, dim3(off[l + 1] - off[l]), dim3(kWave), 0, st, tv, pv, dl, p,
+        hipLaunchKernelGGL(k_down<double>, dim3(off[l + 1] - off[l]), dim3(kWave), 0, st, tv, pv, dl, p,
                            as_cpx(M), as_cpx(TL), f.Tnset.p);
         DC_HIP(hipGetLastError());
     }
