@@ -172,6 +172,21 @@ int dc_apply_operator(dc_scene s, const double* x_dev, double* y_dev,
 int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
               int out_dtype, void* out_dev, void* stream);
 
+/* Alg. 4 for n viewports of one scene in one set of launches: one
+ * downward launch per quadtree level covers every viewport that reaches
+ * that level and one leaf launch covers every viewport's pixel tiles (the
+ * viewports are independent, so this is a batching of Alg. 4, not a change
+ * of what it computes).  vps[v] and outs[v] (device [H][W][3], FP32 or FP64
+ * per out_dtype) as in dc_render; each image equals dc_render of its
+ * viewport alone.  o->method must be DC_METHOD_FMM.  n >= 1; the host
+ * arrays are read before the call returns.  Asynchronous on stream; the
+ * descriptor tables are copied from host memory owned by the scene, so a
+ * second batch call on the same scene waits for nothing but must not run
+ * concurrently on another stream. */
+int dc_render_batch(dc_scene s, const dc_viewport* vps, int n,
+                    const dc_eval_opts* o, int out_dtype, void* const* outs_dev,
+                    void* stream);
+
 /* The same representation at n arbitrary points xy_dev (device [n][2]
  * FP64), out_dev [n][3].  Uses the direct sum (method is ignored). */
 int dc_eval_points(dc_scene s, const double* xy_dev, int n,

@@ -11,6 +11,60 @@ struct dc_scene_s;
 
 namespace dc {
 
+// One viewport's target boxes at one level of a (batched) render.
+struct VpLevel {
+    long long i0, j0;      // rectangle of boxes at this level
+    long long pi0, pj0;    // rectangle at the parent level
+    int wl, pwl;           // rectangle widths
+    int off, poff;         // global index of the first box, and of the parent's
+    int first_block;       // first block of this viewport in the level's launch
+    int pad;
+};
+
+// One viewport's target leaves (pixel tiles) in a (batched) render.
+struct VpLeaf {
+    long long i0, j0;
+    double vcx, vcy, vw, vh;
+    void* out;
+    int L, wl, off, W, H, first_block, pad;
+};
+
+// Pinned host staging for descriptor uploads: reused once the copy that
+// last read it has completed.
+struct PinnedStage {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    PinnedStage() = default;
+    PinnedStage(const PinnedStage&) = delete;
+    PinnedStage& operator=(const PinnedStage&) = delete;
+    ~PinnedStage() {
+        if (done) (void)hipEventSynchronize(done), (void)hipEventDestroy(done);
+        if (p) (void)hipHostFree(p);
+    }
+    // Host pointer of at least nbytes, free for writing.
+    void* acquire(size_t nbytes) {
+        if (pending) DC_HIP(hipEventSynchronize(done));
+        pending = false;
+        if (nbytes > bytes) {
+            if (p) DC_HIP(hipHostFree(p));
+            p = nullptr;
+            bytes = 0;
+            DC_HIP(hipHostMalloc(&p, nbytes, hipHostMallocDefault));
+            bytes = nbytes;
+        }
+        if (!done) DC_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        return p;
+    }
+    // Copy nbytes to dev on st and mark the staging busy until it is done.
+    void upload(void* dev, size_t nbytes, hipStream_t st) {
+        DC_HIP(hipMemcpyAsync(dev, p, nbytes, hipMemcpyHostToDevice, st));
+        DC_HIP(hipEventRecord(done, st));
+        pending = true;
+    }
+};
+
 struct FmmState {
     // Quadtree on the device (copied from the host tree).
     int n_cells = 0, depth = 0, n_pieces = 0, n_target_leaves = 0;
@@ -37,6 +91,9 @@ struct FmmState {
     // Render scratch: local coefficients and near sets of target boxes.
     DevBuf<double> TL64;
     DevBuf<int> Tnset;
+    // Render descriptors: per (viewport, level) boxes and per-viewport tiles.
+    PinnedStage stage;
+    DevBuf<char> d_desc;
     // Optional device work counters (counting runs only) and phase timing.
     unsigned long long* stats = nullptr;
     bool timing = false;
@@ -56,6 +113,9 @@ void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, doubl
                      const dc_eval_opts& o, hipStream_t st);
 void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int out_dtype,
                 void* out, hipStream_t st);
+// Render of n viewports in one set of launches (outs[v] is [H][W][3]).
+void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,
+                      int out_dtype, void* const* outs, hipStream_t st);
 // Run one render with device work counters; fills counts (synchronous).
 void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
                        dc_work_counts* counts, hipStream_t st);

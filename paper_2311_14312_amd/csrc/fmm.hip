@@ -24,6 +24,7 @@
 // exactly Alg. 8; for a render the target tree is the complete quadtree over
 // the viewport down to pixel tiles.
 #include <cmath>
+#include <cstring>
 
 #include "scene.h"
 
@@ -232,15 +233,23 @@ k_m2m(TreeView tv, int first, int p, cpx<T>* __restrict__ M) {
 }
 
 // ---------------------------------------------------------------- downward
+// Largest entry with first_block <= b (entries sorted by first_block).
+template <typename E>
+__device__ inline const E& find_entry(const E* e, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (e[mid].first_block <= b) lo = mid; else hi = mid - 1;
+    }
+    return e[lo];
+}
+
 struct DownLevel {
     int solve;             // 1: target boxes are the source boxes of level l
     int l;
     int first;             // solve: first box of level l
-    long long i0, j0;      // render: rectangle of target boxes at level l
-    int wl;
-    long long pi0, pj0;    // render: rectangle at level l-1
-    int pwl;
-    int off, poff;         // render: offsets of levels l and l-1
+    const VpLevel* vl;     // render: one entry per viewport that has level l
+    int nvl;
     unsigned long long* stats;  // optional work counters (see kStat*)
 };
 
@@ -376,11 +385,12 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         tj = tv.iy[own];
         par = tv.parent[own];
     } else {
-        const int b = blockIdx.x;
-        ti = dl.i0 + b % dl.wl;
-        tj = dl.j0 + b / dl.wl;
-        own = dl.off + b;
-        par = dl.poff + (int)((ti >> 1) - dl.pi0) + (int)((tj >> 1) - dl.pj0) * dl.pwl;
+        const VpLevel& e = find_entry(dl.vl, dl.nvl, (int)blockIdx.x);
+        const int b = (int)blockIdx.x - e.first_block;
+        ti = e.i0 + b % e.wl;
+        tj = e.j0 + b / e.wl;
+        own = e.off + b;
+        par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
     }
     if (lane < 9) sPN[lane] = nset[(size_t)par * 9 + lane];
     __syncthreads();
@@ -533,6 +543,8 @@ struct LeafArgs {
     int N;
     double near2;            // (near_fp64)^2, FP32 only
     unsigned long long* stats;  // optional work counters
+    const VpLeaf* vleaf;     // render: one entry per viewport
+    int nvleaf;
 };
 
 template <typename T, int NT>
@@ -563,8 +575,26 @@ __device__ inline int first_true_row(const LeafArgs& a, double Y0, double sideL,
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
-k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
+k_leaf(TreeView tv, PieceView pv, LeafArgs a0, int p, const cpx<double>* __restrict__ M,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
+    LeafArgs a = a0;
+    int blk = (int)blockIdx.x;
+    if (!a.solve) {  // take this block's viewport from the batch table
+        const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
+        blk -= v.first_block;
+        a.L = v.L;
+        a.i0 = v.i0;
+        a.j0 = v.j0;
+        a.wl = v.wl;
+        a.off = v.off;
+        a.vcx = v.vcx;
+        a.vcy = v.vcy;
+        a.vw = v.vw;
+        a.vh = v.vh;
+        a.W = v.W;
+        a.H = v.H;
+        a.out = v.out;
+    }
     __shared__ LeafShared<T, NT> sh;
     const int tid = threadIdx.x;
     long long ti, tj;
@@ -579,7 +609,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
         base_pos = tv.nbeg[own];
         n_targets = tv.nend[own] - base_pos;
     } else {
-        const int b = blockIdx.x;
+        const int b = blk;
         ti = a.i0 + b % a.wl;
         tj = a.j0 + b / a.wl;
         own = a.off + b;
@@ -940,38 +970,130 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
     DC_HIP(hipGetLastError());
 }
 
-template <typename T>
-void render_t(dc_scene_s& s, FmmState& f, const dc_viewport& vp, const dc_eval_opts& o,
-              int out_dtype, void* out, hipStream_t st) {
-    const int p = o.p;
-    // Target tile level: boxes no wider than tile_px pixel pitches hold at
-    // most tile_px x tile_px pixel centres (rounding of the centres can add a
-    // row or column now and then; the leaf kernel loops over extra targets).
+// Target tile level of a viewport: boxes no wider than tile_px pixel pitches
+// hold at most tile_px x tile_px pixel centres (rounding of the centres can
+// add a row or column now and then; the leaf kernel loops over extra
+// targets).
+int tile_level(double side, const dc_viewport& vp, int tile_px) {
     const double pitch = std::min(vp.width / vp.W, vp.height / vp.H);
     int Lt = 2;
-    while (std::ldexp(f.side, -Lt) > o.tile_px * pitch * (1.0 + 1e-12)) {
+    while (std::ldexp(side, -Lt) > tile_px * pitch * (1.0 + 1e-12)) {
         ++Lt;
         DC_REQUIRE(Lt <= 60, "viewport pixels are too small for the quadtree root");
     }
-    std::vector<long long> i0(Lt + 1), i1(Lt + 1), j0(Lt + 1), j1(Lt + 1);
-    std::vector<int> off(Lt + 2);
-    off[0] = 0;
-    const double xa = pixel_x(vp.cx, vp.width, vp.W, 0), xb = pixel_x(vp.cx, vp.width, vp.W, vp.W - 1);
-    const double ya = pixel_y(vp.cy, vp.height, vp.H, vp.H - 1), yb = pixel_y(vp.cy, vp.height, vp.H, 0);
-    for (int l = 0; l <= Lt; ++l) {
-        const double sl = std::ldexp(f.side, -l);
-        i0[l] = cell_coord(xa, f.X0, sl);
-        i1[l] = cell_coord(xb, f.X0, sl);
-        j0[l] = cell_coord(ya, f.Y0, sl);
-        j1[l] = cell_coord(yb, f.Y0, sl);
-        const long long lim = 1LL << l;
-        DC_REQUIRE(i0[l] >= 0 && j0[l] >= 0 && i1[l] < lim && j1[l] < lim,
-                   "viewport extends outside the scene's quadtree root (enlarge the domain "
-                   "in dc_scene_opts)");
-        const long long cnt = (i1[l] - i0[l] + 1) * (j1[l] - j0[l] + 1);
-        DC_REQUIRE(off[l] + cnt < (1LL << 31), "viewport needs too many target boxes");
-        off[l + 1] = off[l] + (int)cnt;
+    return Lt;
+}
+
+__global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
+                             cpx<double>* __restrict__ L, int* __restrict__ nset) {
+    const int v = blockIdx.x;
+    if (v >= n) return;
+    const int own = roots[v].off;
+    const int t = threadIdx.x;
+    if (t < 9) nset[(size_t)own * 9 + t] = (t == 4) ? 0 : -1;
+    for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[(size_t)own * (p + 1) * 3 + i] = {0, 0};
+}
+
+// Render of n viewports: one downward launch per level covers every
+// viewport that reaches it, and one leaf launch covers every viewport's
+// pixel tiles.  Target boxes of all viewports live in one array, level by
+// level.
+template <typename T>
+void render_batch_t(dc_scene_s& s, FmmState& f, const dc_viewport* vps, int n,
+                    const dc_eval_opts& o, int out_dtype, void* const* outs, hipStream_t st) {
+    const int p = o.p;
+    std::vector<int> Lt(n);
+    int maxL = 0;
+    for (int v = 0; v < n; ++v) {
+        Lt[v] = tile_level(f.side, vps[v], o.tile_px);
+        maxL = std::max(maxL, Lt[v]);
     }
+    // rectangles per (viewport, level)
+    std::vector<std::vector<long long>> ri0(n), ri1(n), rj0(n), rj1(n);
+    for (int v = 0; v < n; ++v) {
+        const dc_viewport& vp = vps[v];
+        const double xa = pixel_x(vp.cx, vp.width, vp.W, 0);
+        const double xb = pixel_x(vp.cx, vp.width, vp.W, vp.W - 1);
+        const double ya = pixel_y(vp.cy, vp.height, vp.H, vp.H - 1);
+        const double yb = pixel_y(vp.cy, vp.height, vp.H, 0);
+        for (int l = 0; l <= Lt[v]; ++l) {
+            const double sl = std::ldexp(f.side, -l);
+            const long long a0 = cell_coord(xa, f.X0, sl), a1 = cell_coord(xb, f.X0, sl);
+            const long long b0 = cell_coord(ya, f.Y0, sl), b1 = cell_coord(yb, f.Y0, sl);
+            const long long lim = 1LL << l;
+            DC_REQUIRE(a0 >= 0 && b0 >= 0 && a1 < lim && b1 < lim,
+                       "viewport extends outside the scene's quadtree root (enlarge the "
+                       "domain in dc_scene_opts)");
+            ri0[v].push_back(a0);
+            ri1[v].push_back(a1);
+            rj0[v].push_back(b0);
+            rj1[v].push_back(b1);
+        }
+    }
+    // global layout: level-major, viewports in order inside a level
+    std::vector<std::vector<int>> offs(n);
+    std::vector<VpLevel> lev;
+    std::vector<int> lev_begin(maxL + 2, 0), lev_blocks(maxL + 1, 0);
+    long long total = 0;
+    for (int l = 0; l <= maxL; ++l) {
+        lev_begin[l] = (int)lev.size();
+        int fb = 0;
+        for (int v = 0; v < n; ++v) {
+            if (l > Lt[v]) continue;
+            VpLevel e{};
+            e.i0 = ri0[v][l];
+            e.j0 = rj0[v][l];
+            e.wl = (int)(ri1[v][l] - ri0[v][l] + 1);
+            const long long cnt = (long long)e.wl * (rj1[v][l] - rj0[v][l] + 1);
+            DC_REQUIRE(total + cnt < (1LL << 31), "render needs too many target boxes");
+            e.off = (int)total;
+            offs[v].push_back(e.off);
+            if (l > 0) {
+                e.pi0 = ri0[v][l - 1];
+                e.pj0 = rj0[v][l - 1];
+                e.pwl = (int)(ri1[v][l - 1] - ri0[v][l - 1] + 1);
+                e.poff = offs[v][l - 1];
+            }
+            e.first_block = fb;
+            fb += (int)cnt;
+            total += cnt;
+            lev.push_back(e);
+        }
+        lev_blocks[l] = fb;
+    }
+    lev_begin[maxL + 1] = (int)lev.size();
+    std::vector<VpLeaf> lf(n);
+    int leaf_blocks = 0;
+    for (int v = 0; v < n; ++v) {
+        VpLeaf& e = lf[v];
+        const int L = Lt[v];
+        e.L = L;
+        e.i0 = ri0[v][L];
+        e.j0 = rj0[v][L];
+        e.wl = (int)(ri1[v][L] - ri0[v][L] + 1);
+        e.off = offs[v][L];
+        e.vcx = vps[v].cx;
+        e.vcy = vps[v].cy;
+        e.vw = vps[v].width;
+        e.vh = vps[v].height;
+        e.W = vps[v].W;
+        e.H = vps[v].H;
+        e.out = outs[v];
+        e.first_block = leaf_blocks;
+        leaf_blocks += e.wl * (int)(rj1[v][L] - rj0[v][L] + 1);
+    }
+    // one upload of both tables (the leaf table 16-byte aligned after the
+    // level table)
+    const size_t lev_bytes = lev.size() * sizeof(VpLevel);
+    const size_t leaf_at = (lev_bytes + 255) & ~size_t(255);
+    const size_t desc_bytes = leaf_at + lf.size() * sizeof(VpLeaf);
+    char* hs = static_cast<char*>(f.stage.acquire(desc_bytes));
+    std::memcpy(hs, lev.data(), lev_bytes);
+    std::memcpy(hs + leaf_at, lf.data(), lf.size() * sizeof(VpLeaf));
+    if (f.d_desc.n < desc_bytes) f.d_desc.alloc(desc_bytes);
+    f.stage.upload(f.d_desc.p, desc_bytes, st);
+    const VpLevel* d_lev = reinterpret_cast<const VpLevel*>(f.d_desc.p);
+    const VpLeaf* d_leaf = reinterpret_cast<const VpLeaf*>(f.d_desc.p + leaf_at);
     if (f.timing) DC_HIP(hipEventRecord(f.ev[0], st));
     if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
         upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st);
@@ -980,56 +1102,40 @@ void render_t(dc_scene_s& s, FmmState& f, const dc_viewport& vp, const dc_eval_o
         f.up_prec = (int)sizeof(T);
     }
     DevBuf<double>& TL = f.TL64;
-    const size_t need = (size_t)off[Lt + 1] * (p + 1) * 3 * 2;
+    const size_t need = (size_t)total * (p + 1) * 3 * 2;
     if (TL.n < need) TL.alloc(need);
-    if (f.Tnset.n < (size_t)off[Lt + 1] * 9) f.Tnset.alloc((size_t)off[Lt + 1] * 9);
+    if (f.Tnset.n < (size_t)total * 9) f.Tnset.alloc((size_t)total * 9);
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
     DevBuf<double>& M = f.M64;
     if (f.timing) DC_HIP(hipEventRecord(f.ev[1], st));
-    hipLaunchKernelGGL(k_init_root<double>, dim3(1), dim3(kWave), 0, st, p, as_cpx(TL), f.Tnset.p);
+    hipLaunchKernelGGL(k_init_roots, dim3(lev_begin[1] - lev_begin[0]), dim3(kWave), 0, st,
+                       lev_begin[1] - lev_begin[0], d_lev, p, as_cpx(TL), f.Tnset.p);
     DC_HIP(hipGetLastError());
-    for (int l = 1; l <= Lt; ++l) {
+    for (int l = 1; l <= maxL; ++l) {
         DownLevel dl{};
         dl.stats = f.stats;
         dl.solve = 0;
         dl.l = l;
-        dl.i0 = i0[l];
-        dl.j0 = j0[l];
-        dl.wl = (int)(i1[l] - i0[l] + 1);
-        dl.pi0 = i0[l - 1];
-        dl.pj0 = j0[l - 1];
-        dl.pwl = (int)(i1[l - 1] - i0[l - 1] + 1);
-        dl.off = off[l];
-        dl.poff = off[l - 1];
-        hipLaunchKernelGGL(k_down<double>, dim3(off[l + 1] - off[l]), dim3(kWave), 0, st, tv, pv, dl, p,
+        dl.vl = d_lev + lev_begin[l];
+        dl.nvl = lev_begin[l + 1] - lev_begin[l];
+        hipLaunchKernelGGL(k_down<double>, dim3(lev_blocks[l]), dim3(kWave), 0, st, tv, pv, dl, p,
                            as_cpx(M), as_cpx(TL), f.Tnset.p);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
     a.solve = 0;
-    a.L = Lt;
-    a.i0 = i0[Lt];
-    a.j0 = j0[Lt];
-    a.wl = (int)(i1[Lt] - i0[Lt] + 1);
-    a.off = off[Lt];
-    a.vcx = vp.cx;
-    a.vcy = vp.cy;
-    a.vw = vp.width;
-    a.vh = vp.height;
-    a.W = vp.W;
-    a.H = vp.H;
     a.out_f64 = out_dtype == DC_OUT_F64;
-    a.out = out;
     a.near2 = o.near_fp64 * o.near_fp64;
     a.stats = f.stats;
-    const int nblk = off[Lt + 1] - off[Lt];
+    a.vleaf = d_leaf;
+    a.nvleaf = n;
     if (f.timing) DC_HIP(hipEventRecord(f.ev[2], st));
     if (o.tile_px <= 8)
-        hipLaunchKernelGGL((k_leaf<T, 64>), dim3(nblk), dim3(64), 0, st, tv, pv, a, p, as_cpx(M),
-                           as_cpx(TL), f.Tnset.p);
+        hipLaunchKernelGGL((k_leaf<T, 64>), dim3(leaf_blocks), dim3(64), 0, st, tv, pv, a, p,
+                           as_cpx(M), as_cpx(TL), f.Tnset.p);
     else
-        hipLaunchKernelGGL((k_leaf<T, 256>), dim3(nblk), dim3(256), 0, st, tv, pv, a, p,
+        hipLaunchKernelGGL((k_leaf<T, 256>), dim3(leaf_blocks), dim3(256), 0, st, tv, pv, a, p,
                            as_cpx(M), as_cpx(TL), f.Tnset.p);
     DC_HIP(hipGetLastError());
     if (f.timing) {
@@ -1142,10 +1248,7 @@ void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts&
     counts->leaf_boxes = h[kStatLeaf];
     counts->pieces = (unsigned long long)f.n_pieces;
     counts->source_cells = (unsigned long long)f.n_cells;
-    const double pitch = std::min(vp.width / vp.W, vp.height / vp.H);
-    int Lt = 2;
-    while (std::ldexp(f.side, -Lt) > o.tile_px * pitch * (1.0 + 1e-12)) ++Lt;
-    counts->levels = Lt + 1;
+    counts->levels = tile_level(f.side, vp, o.tile_px) + 1;
     counts->p = o.p;
 }
 
@@ -1159,10 +1262,16 @@ void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, doubl
 
 void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int out_dtype,
                 void* out, hipStream_t st) {
+    void* outs[1] = {out};
+    fmm_render_batch(s, &vp, 1, o, out_dtype, outs, st);
+}
+
+void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,
+                      int out_dtype, void* const* outs, hipStream_t st) {
     if (o.precision == DC_PREC_F32)
-        render_t<float>(s, *s.fmm, vp, o, out_dtype, out, st);
+        render_batch_t<float>(s, *s.fmm, vps, n, o, out_dtype, outs, st);
     else
-        render_t<double>(s, *s.fmm, vp, o, out_dtype, out, st);
+        render_batch_t<double>(s, *s.fmm, vps, n, o, out_dtype, outs, st);
 }
 
 }  // namespace dc

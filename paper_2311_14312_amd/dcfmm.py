@@ -89,6 +89,8 @@ def _load():
         "dc_set_densities": (I, [P, dp]),
         "dc_apply_operator": (I, [P, V, V, I, C.POINTER(EvalOpts), V]),
         "dc_render": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, V, V]),
+        "dc_render_batch": (I, [P, C.POINTER(Viewport), I, C.POINTER(EvalOpts), I,
+                                C.POINTER(V), V]),
         "dc_eval_points": (I, [P, V, I, C.POINTER(EvalOpts), I, V, V]),
         "dc_render_counts": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts),
                                  C.POINTER(WorkCounts), V]),
@@ -248,6 +250,25 @@ class Scene:
         _check(_lib.dc_render(self._h, C.byref(vp), C.byref(o), code,
                               C.c_void_p(out.data_ptr()), _stream()))
         return out
+
+    def render_batch(self, viewports, outs=None, out_dtype=None, **ev):
+        """Images of several viewports of this scene in one batched render."""
+        import torch
+        n = len(viewports)
+        vps = (Viewport * n)()
+        for i, (cx, cy, w, h, W, H) in enumerate(viewports):
+            vps[i] = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        if outs is None:
+            outs = [torch.empty((int(v[5]), int(v[4]), 3), device="cuda",
+                                dtype=out_dtype or torch.float32) for v in viewports]
+        assert len(outs) == n and len({o.dtype for o in outs}) == 1
+        for o, v in zip(outs, viewports):
+            assert o.is_cuda and o.is_contiguous() and tuple(o.shape) == (v[5], v[4], 3)
+        code = {torch.float32: OUT_F32, torch.float64: OUT_F64}[outs[0].dtype]
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        o = eval_opts(**ev)
+        _check(_lib.dc_render_batch(self._h, vps, n, C.byref(o), code, ptrs, _stream()))
+        return outs
 
     def eval_points(self, xy, out_dtype=None, **ev):
         """Representation at points xy (torch cuda float64 [n, 2]) -> [n, 3]."""
