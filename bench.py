@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 import scenegen  # noqa: E402
 
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_sigma.npz")
+GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "c4_golden.npz")
 METRIC = "RGB pixels/s at max err <=1e-4 vs FP64 oracle; FP32-batched vs plain FP64 FMM"
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector (packed) TFLOP/s
 PEAK_FP64 = 78.6e12
@@ -85,6 +86,201 @@ def cpu_baseline(cfg, sc, workers):
                 t_disc=t_disc, golden=have_golden)
 
 
+def batch_bench(args, torch, dcfmm):
+    """The 500-curve scene with 64 zoomed viewports (128..2048 px a side,
+    zoom 1..1e6): one batched FP32 render of all viewports vs the same
+    viewports rendered one at a time (FP32, and the plain FP64 FMM).  Order
+    and leaf capacity are autotuned against the stored oracle samples."""
+    cfg = scenegen.BATCH
+    sc, vps = scenegen.batch_scene(cfg)
+    gold = np.load(GOLDEN_C4) if os.path.exists(GOLDEN_C4) else None
+    px = sum(v[4] * v[5] for v in vps)
+    outs = [torch.empty((v[5], v[4], 3), device="cuda", dtype=torch.float32) for v in vps]
+
+    def err(imgs):
+        if gold is None:
+            return None
+        e = 0.0
+        for v, img in enumerate(imgs):
+            m = gold["vid"] == v
+            got = img[gold["rows"][m], gold["cols"][m]].cpu().numpy()
+            e = max(e, float(np.abs(got - gold["vals"][m]).max()))
+        return e
+
+    def time_it(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    orders = [int(v) for v in args.batch_orders.split(",")]
+    tune, best, scenes = [], None, {}
+    for leaf in [int(v) for v in args.batch_leaves.split(",")]:
+        scn = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
+                          gl=cfg["gl"], segs=cfg["segs"], leaf_max=leaf,
+                          domain=cfg["domain"])
+        if gold is not None:
+            scn.set_densities(gold["sigma"])
+            rep = None
+        else:
+            rep = scn.solve(tol=1e-10, max_iter=1000, method="fmm", p=20)
+        scenes[leaf] = (scn, rep)
+        for tile in (8, 16):
+            chosen = orders[-1]
+            if gold is not None:
+                for pp in orders:
+                    scn.render_batch(vps, outs=outs, method="fmm", precision="f32", p=pp,
+                                     tile_px=tile)
+                    if err(outs) <= 5e-5:
+                        chosen = pp
+                        break
+            ev = dict(method="fmm", precision="f32", p=chosen, tile_px=tile)
+            ms = time_it(lambda: scn.render_batch(vps, outs=outs, **ev), 3, 1)
+            tune.append({"leaf": leaf, "tile": tile, "p": chosen, "ms": ms})
+            print("batch autotune", tune[-1], flush=True)
+            if best is None or ms < best["ms"]:
+                best = dict(tune[-1])
+    scn, rep = scenes[best["leaf"]]
+    ev32 = dict(method="fmm", precision="f32", p=best["p"], tile_px=best["tile"])
+    ms_batch = time_it(lambda: scn.render_batch(vps, outs=outs, **ev32), args.steps,
+                       args.warmup)
+    e_batch = err(outs)
+
+    def one_by_one(ev, bufs):
+        for v, o in zip(vps, bufs):
+            scn.render(v, out=o, **ev)
+
+    ms_seq = time_it(lambda: one_by_one(ev32, outs), max(1, args.steps // 2), 1)
+    del outs
+    outs64 = [torch.empty((v[5], v[4], 3), device="cuda", dtype=torch.float64) for v in vps]
+    ev64 = dict(method="fmm", precision="f64", p=args.p64, tile_px=best["tile"])
+    ms64 = time_it(lambda: one_by_one(ev64, outs64), max(1, args.steps // 4), 1)
+    e64 = err(outs64)
+    del outs64
+    for s_, _ in scenes.values():
+        s_.close()
+    return {
+        "workload": "500 cubic Beziers (lengths log-uniform 0.01-0.5), 4 panels x 16 GL nodes (32,000 nodes), "
+                    "64 viewports, side U{128..2048} px, zoom 10^U(0,6), on curve points",
+        "pixels": px,
+        "value": px / (ms_batch * 1e-3), "unit": "RGB pixels/s", "ms_per_batch": ms_batch,
+        "p": best["p"], "tile_px": best["tile"], "leaf_max": best["leaf"],
+        "max_err_vs_oracle": e_batch,
+        "err_sample": None if gold is None else f"{len(gold['vals'])} oracle pixels "
+                                                "(8x8 grid + 8x8 centre block per viewport)",
+        "one_at_a_time_fp32": {"value": px / (ms_seq * 1e-3), "ms": ms_seq},
+        "one_at_a_time_fp64": {"value": px / (ms64 * 1e-3), "ms": ms64, "p": args.p64,
+                               "max_err_vs_oracle": e64},
+        "densities": "oracle (stored)" if gold is not None else "GPU FMM GMRES",
+        "autotune": tune,
+    }
+
+
+def serving_bench(args, torch, dcfmm):
+    """16 resident scenes of 10..5000 curves; requests of 256..2048 px a side
+    at zoom 1..1e6 on curve points.  Capacity is measured with a burst of
+    requests; then Poisson arrivals at 0.5x, 1x and 2x capacity, each
+    n_warmup + n_requests requests, report p50/p99 latency (submit to
+    observed completion) and pixels/s."""
+    import threading
+    cfg = scenegen.SERVING
+    t0 = time.time()
+    raw = scenegen.serving_scenes(n_scenes=cfg["n_scenes"], seed0=cfg["seed0"],
+                                  panels=cfg["panels"], gl=cfg["gl"], segs=cfg["segs"])
+    scenes, solve = [], []
+    for k, sc in enumerate(raw):
+        s = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
+                        gl=cfg["gl"], segs=cfg["segs"], leaf_max=32, domain=cfg["domain"])
+        rep = s.solve(tol=1e-8, max_iter=600, method="fmm", p=16, raise_on_fail=False)
+        solve.append({"curves": int(sc["ctrl"].shape[0]), "N": s.info()["N"],
+                      "iters": max(rep["iters"]), "s": round(rep["seconds"], 3),
+                      "converged": bool(rep["converged"])})
+        print("serving scene", k, solve[-1], flush=True)
+        scenes.append(s)
+    t_setup = time.time() - t0
+    ev = dict(precision="f32", p=args.serve_p, tile_px=args.serve_tile)
+    srv = dcfmm.Server(**ev, n_streams=4, max_batch=32, max_batch_pixels=1 << 25,
+                       hbm_budget=32 << 30)
+    for s in scenes:
+        srv.add_scene(s)
+    n_req, n_warm = cfg["n_requests"], cfg["n_warmup"]
+    reqs = scenegen.serving_requests(raw, n_req + n_warm, seed=7)
+    sink = torch.empty(2048 * 2048 * 3, device="cuda", dtype=torch.float32)
+
+    def fetch(t, vp):
+        srv.fetch(t, out=sink[:vp[4] * vp[5] * 3].view(vp[5], vp[4], 3))
+
+    # capacity: everything submitted at once
+    t_b = time.time()
+    tickets = [srv.submit(scenes[k], vp) for k, vp in reqs[:400]]
+    for t, (k, vp) in zip(tickets, reqs[:400]):
+        srv.wait(t)
+        fetch(t, vp)
+    dt = time.time() - t_b
+    cap = 400 / dt
+    cap_px = sum(vp[4] * vp[5] for _, vp in reqs[:400]) / dt
+    print(f"serving capacity {cap:.0f} req/s, {cap_px:.3e} px/s", flush=True)
+    runs = []
+    for mult in (0.5, 1.0, 2.0):
+        rate = mult * cap
+        arr = scenegen.poisson_arrivals(len(reqs), rate, seed=11)
+        tick = [None] * len(reqs)
+        lock = threading.Condition()
+
+        def submitter():
+            start = time.perf_counter()
+            for i, (k, vp) in enumerate(reqs):
+                d = arr[i] - (time.perf_counter() - start)
+                if d > 0:
+                    time.sleep(d)
+                t = srv.submit(scenes[k], vp)
+                with lock:
+                    tick[i] = t
+                    lock.notify()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        infos = []
+        for i, (k, vp) in enumerate(reqs):
+            with lock:
+                while tick[i] is None:
+                    lock.wait()
+            infos.append(srv.wait(tick[i]))
+            fetch(tick[i], vp)
+        th.join()
+        meas = infos[n_warm:]
+        lat = np.array([x["t_done"] - x["t_submit"] for x in meas]) * 1e3
+        span = max(x["t_done"] for x in meas) - min(x["t_submit"] for x in meas)
+        px = sum(vp[4] * vp[5] for _, vp in reqs[n_warm:])
+        runs.append({"load": mult, "rate_req_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                     "pixels_per_s": px / span,
+                     "mean_batch": float(np.mean([x["batch_size"] for x in meas]))})
+        print("serving", runs[-1], flush=True)
+    st = srv.stats()
+    srv.close()
+    for s in scenes:
+        s.close()
+    return {
+        "workload": "16 resident scenes (10-5000 curves, log-uniform; 16 panels x 16 GL "
+                    "nodes), requests 256-2048 px a side, zoom 10^U(0,6), Poisson arrivals",
+        "p": args.serve_p, "tile_px": args.serve_tile, "precision": "f32",
+        "capacity_req_s": cap, "capacity_pixels_per_s": cap_px,
+        "requests_per_run": n_req, "warmup_per_run": n_warm, "runs": runs,
+        "server": {"n_streams": 4, "max_batch": 32, "hbm_budget_GiB": 32,
+                   "batches": st["batches"], "max_in_flight": st["max_in_flight"],
+                   "bytes_peak": st["bytes_peak"], "admission_waits": st["admission_waits"]},
+        "setup_s": t_setup, "scenes": solve,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +292,12 @@ def main():
     ap.add_argument("--tiles", default="8,16")
     ap.add_argument("--leaves", default="16,32,64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-viewport batch")
+    ap.add_argument("--batch-orders", default="10,12,14,16,18,20,24")
+    ap.add_argument("--batch-leaves", default="16,32")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-p", type=int, default=12)
+    ap.add_argument("--serve-tile", type=int, default=16)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -253,9 +455,13 @@ def main():
             "sample": f"{cpu['n']} sampled pixels of the 2048x2048 viewport x {cpu['S']} "
                       f"segments, FP64 NumPy direct sum ({cpu['seconds']:.1f} s)"},
     }
-    print(json.dumps(line), flush=True)
     for scn, _, _ in scenes.values():
         scn.close()
+    if not args.no_batch:
+        line["batch"] = batch_bench(args, torch, dcfmm)
+    if not args.no_serving:
+        line["serving"] = serving_bench(args, torch, dcfmm)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

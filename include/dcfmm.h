@@ -44,6 +44,7 @@ extern "C" {
 #define DC_ERR_OOM (-2)            /* device or host allocation failed */
 #define DC_ERR_NOT_CONVERGED (-3)  /* GMRES hit max_iter; report filled */
 #define DC_ERR_HIP (-4)            /* HIP runtime error; message kept */
+#define DC_ERR_TIMEOUT (-5)        /* dc_server_wait: not done in time */
 
 #define DC_PREC_F64 0   /* everything in FP64 */
 #define DC_PREC_F32 1   /* FP32 expansions and near field; FP64 for
@@ -219,6 +220,90 @@ int dc_render_counts(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
  * over calls), number of calls} and resets the sums. */
 int dc_set_timing(dc_scene s, int enable);
 int dc_get_timing(dc_scene s, double* ms);
+
+/* ------------------------------------------------------------------------
+ * Serving: a render loop over resident scenes with continuous batching.
+ *
+ * Alg. 4 is evaluated once per request (a viewport of a registered scene)
+ * exactly as dc_render does, so a result does not depend on which other
+ * requests share its batch.  A worker thread owned by the server takes
+ * queued requests in arrival order, groups the oldest request with later
+ * requests of the same scene (up to max_batch requests and
+ * max_batch_pixels pixels), and admits the group when its device footprint
+ * (images plus render scratch, computed exactly from the render plan) fits
+ * in the free part of an arena of hbm_budget bytes; otherwise the oldest
+ * request waits (no reordering past it) until completed batches or fetched
+ * images free memory.  Admitted batches run on up to n_streams HIP streams
+ * at once, so batches of different scenes and new arrivals overlap on the
+ * device with batches already running.  Images stay in the arena until
+ * fetched: a client that never fetches eventually blocks admission.
+ *
+ * Threading: submit, wait, fetch and get_stats may be called from any host
+ * threads.  A registered scene is read-only: dc_solve_densities,
+ * dc_set_densities, dc_set_boundary and dc_apply_operator fail on it, renders
+ * must use the server's order and precision, and dc_scene_destroy leaves it
+ * alive, until dc_server_destroy.
+ * ------------------------------------------------------------------------ */
+typedef struct dc_server_s* dc_server;
+
+typedef struct {
+    dc_eval_opts eval;          /* options of every render (method FMM) */
+    int out_dtype;              /* DC_OUT_F32 or DC_OUT_F64 */
+    int n_streams;              /* batches in flight at once, 1..16 */
+    int max_batch;              /* requests per batch, >= 1 */
+    long long max_batch_pixels; /* pixels per batch, >= 1 */
+    long long hbm_budget;       /* device bytes for images + scratch */
+} dc_server_opts;
+
+typedef struct {
+    double t_submit, t_start, t_done;  /* seconds since server creation:
+                                          submitted, launched, observed done */
+    long long batch;                   /* id of the batch that rendered it */
+    int batch_size;                    /* requests in that batch */
+    int status;                        /* DC_OK or the batch's error code */
+    long long bytes;                   /* image bytes held until fetched */
+} dc_request_info;
+
+typedef struct {
+    long long submitted, completed, fetched, batches;
+    long long max_in_flight;           /* most batches running at once */
+    long long bytes_in_use, bytes_peak;
+    long long admission_waits;         /* admissions deferred for memory */
+} dc_server_stats;
+
+/* Defaults: FMM FP32 p=12 tile 8, FP32 images, 4 streams, 64 requests and
+ * 2^26 pixels per batch, 8 GiB. */
+void dc_default_server_opts(dc_server_opts* o);
+
+/* Create a server on the current HIP device: allocates the arena (one
+ * hipMalloc of hbm_budget bytes), the streams and the worker thread. */
+int dc_server_create(const dc_server_opts* o, dc_server* out);
+
+/* Register a scene with densities and run its upward pass for the server's
+ * options (synchronous).  The scene must live on the server's device. */
+int dc_server_add_scene(dc_server sv, dc_scene s);
+
+/* Queue a render of vp of registered scene s; *ticket identifies it.
+ * Fails with DC_ERR_INVALID for a viewport outside the scene's quadtree
+ * root and DC_ERR_OOM when the request alone exceeds hbm_budget. */
+int dc_server_submit(dc_server sv, dc_scene s, const dc_viewport* vp,
+                     long long* ticket);
+
+/* Wait up to timeout_s seconds (< 0: no limit) for a request; fills info
+ * (may be NULL).  DC_OK when it is done, DC_ERR_TIMEOUT otherwise. */
+int dc_server_wait(dc_server sv, long long ticket, double timeout_s,
+                   dc_request_info* info);
+
+/* Copy a finished request's image ([H][W][3] of out_dtype) to dst (device
+ * memory when dst_is_device, else host) and release it; the ticket is then
+ * forgotten.  Synchronous. */
+int dc_server_fetch(dc_server sv, long long ticket, void* dst, int dst_is_device);
+
+int dc_server_get_stats(dc_server sv, dc_server_stats* st);
+
+/* Finish every queued and running request, then free the server (unfetched
+ * images are dropped) and unregister its scenes. */
+void dc_server_destroy(dc_server sv);
 
 const char* dc_last_error(void);
 

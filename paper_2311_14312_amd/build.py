@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdcfmm.so")
-SOURCES = ["geometry.cpp", "tree.cpp", "api.cpp", "kernels_direct.hip", "fmm.hip",
-           "precond.hip"]
+SOURCES = ["geometry.cpp", "tree.cpp", "api.cpp", "server.cpp", "kernels_direct.hip",
+           "fmm.hip", "precond.hip"]
 ARCH = os.environ.get("DCFMM_ARCH", "gfx950")
 
 COMMON = [
@@ -50,7 +50,7 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-pthread", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -10,25 +10,12 @@
 using namespace dc;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-template <typename F>
-int guarded(F&& f) {
-    try {
-        f();
-        return DC_OK;
-    } catch (const Error& e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return DC_ERR_OOM;
-    } catch (const std::exception& e) {
-        g_last_error = e.what();
-        return DC_ERR_INVALID;
-    }
-}
+void dc::set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
 
 void check_eval(const dc_eval_opts* o) {
     DC_REQUIRE(o != nullptr, "null eval options");
@@ -40,6 +27,19 @@ void check_eval(const dc_eval_opts* o) {
 }
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// A scene registered with a server keeps its densities and upward pass
+// fixed: the server's streams read them at any time.
+void check_not_served(dc_scene s) {
+    DC_REQUIRE(s->served.load() == 0,
+               "the scene is registered with a server (destroy the server first)");
+}
+void check_served_opts(dc_scene s, const dc_eval_opts* o) {
+    if (s->served.load() == 0 || o->method != DC_METHOD_FMM) return;
+    const FmmState& f = *s->fmm;
+    DC_REQUIRE(f.up_p == o->p && f.up_prec == (o->precision == DC_PREC_F32 ? 4 : 8),
+               "the scene is registered with a server for another order or precision");
+}
 
 void upload_boundary(dc_scene s) {
     const int N = s->geo.N;
@@ -317,7 +317,15 @@ int dc_scene_create(const double* ctrl, int n_curves, const double* left_rgb,
     });
 }
 
-void dc_scene_destroy(dc_scene s) { delete s; }
+void dc_scene_destroy(dc_scene s) {
+    if (!s) return;
+    if (s->served.load() != 0) {
+        // still read by a server's streams: keep it alive (documented misuse)
+        g_last_error = "dc_scene_destroy: scene is registered with a server; not destroyed";
+        return;
+    }
+    delete s;
+}
 
 int dc_scene_get_info(dc_scene s, dc_scene_info* info) {
     return guarded([&] {
@@ -349,6 +357,7 @@ int dc_get_nodes(dc_scene s, double* xy) {
 int dc_set_boundary(dc_scene s, const double* up, const double* um) {
     return guarded([&] {
         DC_REQUIRE(s && up && um, "null argument");
+        check_not_served(s);
         const size_t n3 = 3 * (size_t)s->geo.N;
         for (size_t i = 0; i < n3; ++i)
             DC_REQUIRE(std::isfinite(up[i]) && std::isfinite(um[i]), "non-finite boundary value");
@@ -362,6 +371,7 @@ int dc_solve_densities(dc_scene s, const dc_solve_opts* o, dc_solve_report* rep,
     int rc = DC_OK;
     int g = guarded([&] {
         DC_REQUIRE(s && o && rep, "null argument");
+        check_not_served(s);
         check_eval(&o->matvec);
         DC_REQUIRE(o->tol > 0 && o->max_iter >= 1, "bad GMRES options");
         DC_REQUIRE(o->precond == DC_PRECOND_NONE || o->precond == DC_PRECOND_BLOCK,
@@ -387,6 +397,7 @@ int dc_get_densities(dc_scene s, double* sigma) {
 int dc_set_densities(dc_scene s, const double* sigma) {
     return guarded([&] {
         DC_REQUIRE(s && sigma, "null argument");
+        check_not_served(s);
         const size_t n3 = 3 * (size_t)s->geo.N;
         for (size_t i = 0; i < n3; ++i) DC_REQUIRE(std::isfinite(sigma[i]), "non-finite density");
         std::vector<double> v(sigma, sigma + n3);
@@ -401,6 +412,7 @@ int dc_apply_operator(dc_scene s, const double* x, double* y, int c_mu, const dc
                       void* stream) {
     return guarded([&] {
         DC_REQUIRE(s && x && y, "null argument");
+        check_not_served(s);
         check_eval(o);
         apply_operator(s, x, c_mu ? s->d_mu.p : nullptr, y, *o, as_stream(stream));
     });
@@ -411,6 +423,7 @@ int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o, int out_
     return guarded([&] {
         DC_REQUIRE(s && vp && out, "null argument");
         check_eval(o);
+        check_served_opts(s, o);
         DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
         DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0 &&
                        std::isfinite(vp->cx) && std::isfinite(vp->cy) &&
@@ -433,6 +446,7 @@ int dc_render_batch(dc_scene s, const dc_viewport* vps, int n, const dc_eval_opt
     return guarded([&] {
         DC_REQUIRE(s && vps && outs && n >= 1, "bad argument");
         check_eval(o);
+        check_served_opts(s, o);
         DC_REQUIRE(o->method == DC_METHOD_FMM, "batched render is an FMM path");
         DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
         for (int v = 0; v < n; ++v) {
@@ -466,6 +480,7 @@ int dc_render_counts(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
     return guarded([&] {
         DC_REQUIRE(s && vp && o && counts, "null argument");
         check_eval(o);
+        check_served_opts(s, o);
         DC_REQUIRE(o->method == DC_METHOD_FMM, "work counts are defined for the FMM path");
         DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
         DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0, "bad viewport");

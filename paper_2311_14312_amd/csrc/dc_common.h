@@ -35,6 +35,28 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::dc::Error(DC_ERR_INVALID, msg);                \
     } while (0)
 
+// Thread-local message returned by dc_last_error().
+void set_last_error(const std::string& msg);
+
+// Run f and map exceptions to the ABI's error codes (no exception crosses
+// the C ABI).
+template <typename F>
+int guarded(F&& f) {
+    try {
+        f();
+        return DC_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return DC_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return DC_ERR_INVALID;
+    }
+}
+
 // Owning device buffer (hipMalloc / hipFree).
 template <typename T>
 struct DevBuf {

@@ -57,12 +57,27 @@ struct PinnedStage {
         if (!done) DC_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
         return p;
     }
-    // Copy nbytes to dev on st and mark the staging busy until it is done.
-    void upload(void* dev, size_t nbytes, hipStream_t st) {
-        DC_HIP(hipMemcpyAsync(dev, p, nbytes, hipMemcpyHostToDevice, st));
+    // Mark the staging busy until the work queued so far on st has run.
+    void mark_used(hipStream_t st) {
         DC_HIP(hipEventRecord(done, st));
         pending = true;
     }
+};
+
+// Host plan of one render of n viewports: per (viewport, level) rectangles
+// of target boxes, launch sizes and the layout of the render's device
+// scratch, [level table | leaf table | local coefficients | near sets].
+struct RenderPlan {
+    int n = 0, p = 0, tile_px = 0, maxL = 0;
+    std::vector<VpLevel> lev;
+    std::vector<int> lev_begin, lev_blocks;
+    std::vector<VpLeaf> leaf;
+    int leaf_blocks = 0;
+    long long total_boxes = 0;
+    size_t leaf_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0, scratch_bytes = 0;
+    // Write both descriptor tables (desc_bytes) to host, with output
+    // pointers outs[v].
+    void write_tables(void* host, void* const* outs) const;
 };
 
 struct FmmState {
@@ -88,12 +103,11 @@ struct FmmState {
     // Upward pass of the resident densities (render reuses it).
     bool up_valid = false;
     int up_p = -1, up_prec = -1;
-    // Render scratch: local coefficients and near sets of target boxes.
-    DevBuf<double> TL64;
-    DevBuf<int> Tnset;
-    // Render descriptors: per (viewport, level) boxes and per-viewport tiles.
+    // Render of the dc_render / dc_render_batch calls: plan, descriptor
+    // staging and device scratch (see RenderPlan).
+    RenderPlan plan;
     PinnedStage stage;
-    DevBuf<char> d_desc;
+    DevBuf<char> scratch;
     // Optional device work counters (counting runs only) and phase timing.
     unsigned long long* stats = nullptr;
     bool timing = false;
@@ -116,6 +130,19 @@ void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int
 // Render of n viewports in one set of launches (outs[v] is [H][W][3]).
 void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,
                       int out_dtype, void* const* outs, hipStream_t st);
+// Plan a render of n viewports (host only; throws DC_ERR_INVALID for a
+// viewport outside the quadtree root).
+void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, int p,
+                 RenderPlan& pl);
+// Upward pass of the resident densities for the options' order and
+// precision (a no-op when already done).
+void fmm_prepare(dc_scene_s& s, const dc_eval_opts& o, hipStream_t st);
+// Launch a planned render on st: scratch is device memory of
+// pl.scratch_bytes and stage pinned host memory holding pl.write_tables();
+// both must stay untouched until the launch has run.  Needs fmm_prepare for
+// the same options first when other streams may render the scene.
+void fmm_launch_render(dc_scene_s& s, const RenderPlan& pl, const dc_eval_opts& o,
+                       int out_dtype, char* scratch, const void* stage, hipStream_t st);
 // Run one render with device work counters; fills counts (synchronous).
 void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
                        dc_work_counts* counts, hipStream_t st);

@@ -994,151 +994,64 @@ __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
     for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[(size_t)own * (p + 1) * 3 + i] = {0, 0};
 }
 
-// Render of n viewports: one downward launch per level covers every
-// viewport that reaches it, and one leaf launch covers every viewport's
-// pixel tiles.  Target boxes of all viewports live in one array, level by
-// level.
+// Launch of a planned render (plan_render) with its scratch at `scratch`
+// (RenderPlan::scratch_bytes, 256-byte aligned) and its descriptor tables
+// already written to the pinned host buffer `stage` (RenderPlan::write_tables).
+// One downward launch per level covers every viewport that reaches it, and
+// one leaf launch covers every viewport's pixel tiles.
 template <typename T>
-void render_batch_t(dc_scene_s& s, FmmState& f, const dc_viewport* vps, int n,
-                    const dc_eval_opts& o, int out_dtype, void* const* outs, hipStream_t st) {
+void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_eval_opts& o,
+                     int out_dtype, char* scratch, const void* stage, bool timed,
+                     unsigned long long* stats, hipStream_t st) {
     const int p = o.p;
-    std::vector<int> Lt(n);
-    int maxL = 0;
-    for (int v = 0; v < n; ++v) {
-        Lt[v] = tile_level(f.side, vps[v], o.tile_px);
-        maxL = std::max(maxL, Lt[v]);
-    }
-    // rectangles per (viewport, level)
-    std::vector<std::vector<long long>> ri0(n), ri1(n), rj0(n), rj1(n);
-    for (int v = 0; v < n; ++v) {
-        const dc_viewport& vp = vps[v];
-        const double xa = pixel_x(vp.cx, vp.width, vp.W, 0);
-        const double xb = pixel_x(vp.cx, vp.width, vp.W, vp.W - 1);
-        const double ya = pixel_y(vp.cy, vp.height, vp.H, vp.H - 1);
-        const double yb = pixel_y(vp.cy, vp.height, vp.H, 0);
-        for (int l = 0; l <= Lt[v]; ++l) {
-            const double sl = std::ldexp(f.side, -l);
-            const long long a0 = cell_coord(xa, f.X0, sl), a1 = cell_coord(xb, f.X0, sl);
-            const long long b0 = cell_coord(ya, f.Y0, sl), b1 = cell_coord(yb, f.Y0, sl);
-            const long long lim = 1LL << l;
-            DC_REQUIRE(a0 >= 0 && b0 >= 0 && a1 < lim && b1 < lim,
-                       "viewport extends outside the scene's quadtree root (enlarge the "
-                       "domain in dc_scene_opts)");
-            ri0[v].push_back(a0);
-            ri1[v].push_back(a1);
-            rj0[v].push_back(b0);
-            rj1[v].push_back(b1);
-        }
-    }
-    // global layout: level-major, viewports in order inside a level
-    std::vector<std::vector<int>> offs(n);
-    std::vector<VpLevel> lev;
-    std::vector<int> lev_begin(maxL + 2, 0), lev_blocks(maxL + 1, 0);
-    long long total = 0;
-    for (int l = 0; l <= maxL; ++l) {
-        lev_begin[l] = (int)lev.size();
-        int fb = 0;
-        for (int v = 0; v < n; ++v) {
-            if (l > Lt[v]) continue;
-            VpLevel e{};
-            e.i0 = ri0[v][l];
-            e.j0 = rj0[v][l];
-            e.wl = (int)(ri1[v][l] - ri0[v][l] + 1);
-            const long long cnt = (long long)e.wl * (rj1[v][l] - rj0[v][l] + 1);
-            DC_REQUIRE(total + cnt < (1LL << 31), "render needs too many target boxes");
-            e.off = (int)total;
-            offs[v].push_back(e.off);
-            if (l > 0) {
-                e.pi0 = ri0[v][l - 1];
-                e.pj0 = rj0[v][l - 1];
-                e.pwl = (int)(ri1[v][l - 1] - ri0[v][l - 1] + 1);
-                e.poff = offs[v][l - 1];
-            }
-            e.first_block = fb;
-            fb += (int)cnt;
-            total += cnt;
-            lev.push_back(e);
-        }
-        lev_blocks[l] = fb;
-    }
-    lev_begin[maxL + 1] = (int)lev.size();
-    std::vector<VpLeaf> lf(n);
-    int leaf_blocks = 0;
-    for (int v = 0; v < n; ++v) {
-        VpLeaf& e = lf[v];
-        const int L = Lt[v];
-        e.L = L;
-        e.i0 = ri0[v][L];
-        e.j0 = rj0[v][L];
-        e.wl = (int)(ri1[v][L] - ri0[v][L] + 1);
-        e.off = offs[v][L];
-        e.vcx = vps[v].cx;
-        e.vcy = vps[v].cy;
-        e.vw = vps[v].width;
-        e.vh = vps[v].height;
-        e.W = vps[v].W;
-        e.H = vps[v].H;
-        e.out = outs[v];
-        e.first_block = leaf_blocks;
-        leaf_blocks += e.wl * (int)(rj1[v][L] - rj0[v][L] + 1);
-    }
-    // one upload of both tables (the leaf table 16-byte aligned after the
-    // level table)
-    const size_t lev_bytes = lev.size() * sizeof(VpLevel);
-    const size_t leaf_at = (lev_bytes + 255) & ~size_t(255);
-    const size_t desc_bytes = leaf_at + lf.size() * sizeof(VpLeaf);
-    char* hs = static_cast<char*>(f.stage.acquire(desc_bytes));
-    std::memcpy(hs, lev.data(), lev_bytes);
-    std::memcpy(hs + leaf_at, lf.data(), lf.size() * sizeof(VpLeaf));
-    if (f.d_desc.n < desc_bytes) f.d_desc.alloc(desc_bytes);
-    f.stage.upload(f.d_desc.p, desc_bytes, st);
-    const VpLevel* d_lev = reinterpret_cast<const VpLevel*>(f.d_desc.p);
-    const VpLeaf* d_leaf = reinterpret_cast<const VpLeaf*>(f.d_desc.p + leaf_at);
-    if (f.timing) DC_HIP(hipEventRecord(f.ev[0], st));
+    DC_REQUIRE(pl.p == p && pl.tile_px == o.tile_px, "render plan does not match the options");
+    DC_HIP(hipMemcpyAsync(scratch, stage, pl.desc_bytes, hipMemcpyHostToDevice, st));
+    const VpLevel* d_lev = reinterpret_cast<const VpLevel*>(scratch);
+    const VpLeaf* d_leaf = reinterpret_cast<const VpLeaf*>(scratch + pl.leaf_at);
+    cpx<double>* TL = reinterpret_cast<cpx<double>*>(scratch + pl.tl_at);
+    int* nset = reinterpret_cast<int*>(scratch + pl.nset_at);
+    if (timed) DC_HIP(hipEventRecord(f.ev[0], st));
     if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
         upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st);
         f.up_valid = true;
         f.up_p = p;
         f.up_prec = (int)sizeof(T);
     }
-    DevBuf<double>& TL = f.TL64;
-    const size_t need = (size_t)total * (p + 1) * 3 * 2;
-    if (TL.n < need) TL.alloc(need);
-    if (f.Tnset.n < (size_t)total * 9) f.Tnset.alloc((size_t)total * 9);
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
-    DevBuf<double>& M = f.M64;
-    if (f.timing) DC_HIP(hipEventRecord(f.ev[1], st));
-    hipLaunchKernelGGL(k_init_roots, dim3(lev_begin[1] - lev_begin[0]), dim3(kWave), 0, st,
-                       lev_begin[1] - lev_begin[0], d_lev, p, as_cpx(TL), f.Tnset.p);
+    const cpx<double>* M = as_cpx(f.M64);
+    if (timed) DC_HIP(hipEventRecord(f.ev[1], st));
+    const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
+    hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
+                       nset);
     DC_HIP(hipGetLastError());
-    for (int l = 1; l <= maxL; ++l) {
+    for (int l = 1; l <= pl.maxL; ++l) {
         DownLevel dl{};
-        dl.stats = f.stats;
+        dl.stats = stats;
         dl.solve = 0;
         dl.l = l;
-        dl.vl = d_lev + lev_begin[l];
-        dl.nvl = lev_begin[l + 1] - lev_begin[l];
-        hipLaunchKernelGGL(k_down<double>, dim3(lev_blocks[l]), dim3(kWave), 0, st, tv, pv, dl, p,
-                           as_cpx(M), as_cpx(TL), f.Tnset.p);
+        dl.vl = d_lev + pl.lev_begin[l];
+        dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
+        hipLaunchKernelGGL(k_down<double>, dim3(pl.lev_blocks[l]), dim3(kWave), 0, st, tv, pv,
+                           dl, p, M, TL, nset);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
     a.solve = 0;
     a.out_f64 = out_dtype == DC_OUT_F64;
     a.near2 = o.near_fp64 * o.near_fp64;
-    a.stats = f.stats;
+    a.stats = stats;
     a.vleaf = d_leaf;
-    a.nvleaf = n;
-    if (f.timing) DC_HIP(hipEventRecord(f.ev[2], st));
+    a.nvleaf = pl.n;
+    if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
     if (o.tile_px <= 8)
-        hipLaunchKernelGGL((k_leaf<T, 64>), dim3(leaf_blocks), dim3(64), 0, st, tv, pv, a, p,
-                           as_cpx(M), as_cpx(TL), f.Tnset.p);
+        hipLaunchKernelGGL((k_leaf<T, 64>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv, pv, a, p,
+                           M, TL, nset);
     else
-        hipLaunchKernelGGL((k_leaf<T, 256>), dim3(leaf_blocks), dim3(256), 0, st, tv, pv, a, p,
-                           as_cpx(M), as_cpx(TL), f.Tnset.p);
+        hipLaunchKernelGGL((k_leaf<T, 256>), dim3(pl.leaf_blocks), dim3(256), 0, st, tv, pv, a,
+                           p, M, TL, nset);
     DC_HIP(hipGetLastError());
-    if (f.timing) {
+    if (timed) {
         DC_HIP(hipEventRecord(f.ev[3], st));
         DC_HIP(hipEventSynchronize(f.ev[3]));
         float ms[3];
@@ -1260,6 +1173,136 @@ void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, doubl
         apply_nodes_t<double>(s, *s.fmm, sigma, mu, y, o, st);
 }
 
+void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, int p,
+                 RenderPlan& pl) {
+    DC_REQUIRE(n >= 1, "empty batch");
+    pl.n = n;
+    pl.p = p;
+    pl.tile_px = tile_px;
+    std::vector<int> Lt(n);
+    int maxL = 0;
+    for (int v = 0; v < n; ++v) {
+        Lt[v] = tile_level(f.side, vps[v], tile_px);
+        maxL = std::max(maxL, Lt[v]);
+    }
+    pl.maxL = maxL;
+    // rectangles of boxes per (viewport, level)
+    std::vector<std::vector<long long>> ri0(n), ri1(n), rj0(n), rj1(n);
+    for (int v = 0; v < n; ++v) {
+        const dc_viewport& vp = vps[v];
+        const double xa = pixel_x(vp.cx, vp.width, vp.W, 0);
+        const double xb = pixel_x(vp.cx, vp.width, vp.W, vp.W - 1);
+        const double ya = pixel_y(vp.cy, vp.height, vp.H, vp.H - 1);
+        const double yb = pixel_y(vp.cy, vp.height, vp.H, 0);
+        for (int l = 0; l <= Lt[v]; ++l) {
+            const double sl = std::ldexp(f.side, -l);
+            const long long a0 = cell_coord(xa, f.X0, sl), a1 = cell_coord(xb, f.X0, sl);
+            const long long b0 = cell_coord(ya, f.Y0, sl), b1 = cell_coord(yb, f.Y0, sl);
+            const long long lim = 1LL << l;
+            DC_REQUIRE(a0 >= 0 && b0 >= 0 && a1 < lim && b1 < lim,
+                       "viewport extends outside the scene's quadtree root (enlarge the "
+                       "domain in dc_scene_opts)");
+            ri0[v].push_back(a0);
+            ri1[v].push_back(a1);
+            rj0[v].push_back(b0);
+            rj1[v].push_back(b1);
+        }
+    }
+    // global layout: level-major, viewports in batch order inside a level
+    std::vector<std::vector<int>> offs(n);
+    pl.lev.clear();
+    pl.lev_begin.assign(maxL + 2, 0);
+    pl.lev_blocks.assign(maxL + 1, 0);
+    long long total = 0;
+    for (int l = 0; l <= maxL; ++l) {
+        pl.lev_begin[l] = (int)pl.lev.size();
+        long long fb = 0;
+        for (int v = 0; v < n; ++v) {
+            if (l > Lt[v]) continue;
+            VpLevel e{};
+            e.i0 = ri0[v][l];
+            e.j0 = rj0[v][l];
+            e.wl = (int)(ri1[v][l] - ri0[v][l] + 1);
+            const long long cnt = (long long)e.wl * (rj1[v][l] - rj0[v][l] + 1);
+            DC_REQUIRE(total + cnt < (1LL << 31), "render needs too many target boxes");
+            e.off = (int)total;
+            offs[v].push_back(e.off);
+            if (l > 0) {
+                e.pi0 = ri0[v][l - 1];
+                e.pj0 = rj0[v][l - 1];
+                e.pwl = (int)(ri1[v][l - 1] - ri0[v][l - 1] + 1);
+                e.poff = offs[v][l - 1];
+            }
+            e.first_block = (int)fb;
+            fb += cnt;
+            total += cnt;
+            pl.lev.push_back(e);
+        }
+        pl.lev_blocks[l] = (int)fb;
+    }
+    pl.lev_begin[maxL + 1] = (int)pl.lev.size();
+    pl.total_boxes = total;
+    pl.leaf.assign(n, VpLeaf{});
+    long long leaf_blocks = 0;
+    for (int v = 0; v < n; ++v) {
+        VpLeaf& e = pl.leaf[v];
+        const int L = Lt[v];
+        e.L = L;
+        e.i0 = ri0[v][L];
+        e.j0 = rj0[v][L];
+        e.wl = (int)(ri1[v][L] - ri0[v][L] + 1);
+        e.off = offs[v][L];
+        e.vcx = vps[v].cx;
+        e.vcy = vps[v].cy;
+        e.vw = vps[v].width;
+        e.vh = vps[v].height;
+        e.W = vps[v].W;
+        e.H = vps[v].H;
+        e.out = nullptr;
+        e.first_block = (int)leaf_blocks;
+        leaf_blocks += (long long)e.wl * (rj1[v][L] - rj0[v][L] + 1);
+    }
+    pl.leaf_blocks = (int)leaf_blocks;
+    // scratch layout: [level table | leaf table | local coefficients | near sets]
+    auto up256 = [](size_t x) { return (x + 255) & ~size_t(255); };
+    pl.leaf_at = up256(pl.lev.size() * sizeof(VpLevel));
+    pl.desc_bytes = pl.leaf_at + pl.leaf.size() * sizeof(VpLeaf);
+    pl.tl_at = up256(pl.desc_bytes);
+    pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
+    pl.scratch_bytes = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
+}
+
+void RenderPlan::write_tables(void* host, void* const* outs) const {
+    char* h = static_cast<char*>(host);
+    std::memcpy(h, lev.data(), lev.size() * sizeof(VpLevel));
+    VpLeaf* lf = reinterpret_cast<VpLeaf*>(h + leaf_at);
+    for (int v = 0; v < n; ++v) {
+        lf[v] = leaf[v];
+        lf[v].out = outs[v];
+    }
+}
+
+void fmm_launch_render(dc_scene_s& s, const RenderPlan& pl, const dc_eval_opts& o,
+                       int out_dtype, char* scratch, const void* stage, hipStream_t st) {
+    if (o.precision == DC_PREC_F32)
+        launch_render_t<float>(s, *s.fmm, pl, o, out_dtype, scratch, stage, false, nullptr,
+                               st);
+    else
+        launch_render_t<double>(s, *s.fmm, pl, o, out_dtype, scratch, stage, false, nullptr,
+                                st);
+}
+
+void fmm_prepare(dc_scene_s& s, const dc_eval_opts& o, hipStream_t st) {
+    FmmState& f = *s.fmm;
+    const int prec = o.precision == DC_PREC_F32 ? 4 : 8;
+    if (!f.up_valid || f.up_p != o.p || f.up_prec != prec) {
+        upward(s, f, s.d_sigma.p, s.d_mu.p, o.p, prec == 4, st);
+        f.up_valid = true;
+        f.up_p = o.p;
+        f.up_prec = prec;
+    }
+}
+
 void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int out_dtype,
                 void* out, hipStream_t st) {
     void* outs[1] = {out};
@@ -1268,10 +1311,19 @@ void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int
 
 void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,
                       int out_dtype, void* const* outs, hipStream_t st) {
+    FmmState& f = *s.fmm;
+    RenderPlan& pl = f.plan;
+    plan_render(f, vps, n, o.tile_px, o.p, pl);
+    void* stage = f.stage.acquire(pl.desc_bytes);
+    pl.write_tables(stage, outs);
+    if (f.scratch.n < pl.scratch_bytes) f.scratch.alloc(pl.scratch_bytes);
     if (o.precision == DC_PREC_F32)
-        render_batch_t<float>(s, *s.fmm, vps, n, o, out_dtype, outs, st);
+        launch_render_t<float>(s, f, pl, o, out_dtype, f.scratch.p, stage, f.timing, f.stats,
+                               st);
     else
-        render_batch_t<double>(s, *s.fmm, vps, n, o, out_dtype, outs, st);
+        launch_render_t<double>(s, f, pl, o, out_dtype, f.scratch.p, stage, f.timing, f.stats,
+                                st);
+    f.stage.mark_used(st);
 }
 
 }  // namespace dc

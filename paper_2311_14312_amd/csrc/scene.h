@@ -1,6 +1,7 @@
 // Scene state shared by the entry points and the FMM driver.
 #pragma once
 
+#include <atomic>
 #include <memory>
 
 #include "fmm.h"
@@ -33,6 +34,9 @@ struct dc_scene_s {
 
     // FMM state (tree on device, expansions, scratch).
     std::unique_ptr<dc::FmmState> fmm;
+    // Number of servers the scene is registered with (they read its
+    // densities and upward pass from their own streams).
+    std::atomic<int> served{0};
 
     dc::ChordsView segs() const {
         return {geo.S, seg_x0.p, seg_y0.p, seg_tx.p, seg_ty.p, seg_len.p};

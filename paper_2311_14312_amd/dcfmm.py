@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdcfmm.so")
 
 DC_OK, DC_ERR_INVALID, DC_ERR_OOM, DC_ERR_NOT_CONVERGED, DC_ERR_HIP = 0, -1, -2, -3, -4
+DC_ERR_TIMEOUT = -5
 PREC_F64, PREC_F32 = 0, 1
 METHOD_FMM, METHOD_DIRECT = 0, 1
 OUT_F32, OUT_F64 = 0, 1
@@ -63,6 +64,25 @@ class WorkCounts(C.Structure):
                 ("levels", C.c_int), ("p", C.c_int)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("eval", EvalOpts), ("out_dtype", C.c_int), ("n_streams", C.c_int),
+                ("max_batch", C.c_int), ("max_batch_pixels", C.c_longlong),
+                ("hbm_budget", C.c_longlong)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("batch", C.c_longlong), ("batch_size", C.c_int), ("status", C.c_int),
+                ("bytes", C.c_longlong)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_longlong), ("completed", C.c_longlong),
+                ("fetched", C.c_longlong), ("batches", C.c_longlong),
+                ("max_in_flight", C.c_longlong), ("bytes_in_use", C.c_longlong),
+                ("bytes_peak", C.c_longlong), ("admission_waits", C.c_longlong)]
+
+
 class DcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"dcfmm error {code}: {msg}")
@@ -96,6 +116,14 @@ def _load():
                                  C.POINTER(WorkCounts), V]),
         "dc_set_timing": (I, [P, I]),
         "dc_get_timing": (I, [P, dp]),
+        "dc_default_server_opts": (None, [C.POINTER(ServerOpts)]),
+        "dc_server_create": (I, [C.POINTER(ServerOpts), C.POINTER(P)]),
+        "dc_server_add_scene": (I, [P, P]),
+        "dc_server_submit": (I, [P, P, C.POINTER(Viewport), C.POINTER(C.c_longlong)]),
+        "dc_server_wait": (I, [P, C.c_longlong, C.c_double, C.POINTER(RequestInfo)]),
+        "dc_server_fetch": (I, [P, C.c_longlong, V, I]),
+        "dc_server_get_stats": (I, [P, C.POINTER(ServerStats)]),
+        "dc_server_destroy": (None, [P]),
         "dc_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -307,3 +335,71 @@ class Scene:
 def exported_symbols():
     """Names of the dc_* functions the loaded library exports."""
     return sorted(n for n in dir(_lib) if n.startswith("dc_"))
+
+
+class Server:
+    """Continuous-batching render server over resident scenes (the C-ABI
+    dc_server_*: a native worker thread batches, admits by device footprint
+    and launches on several streams)."""
+
+    def __init__(self, precision="f32", p=12, tile_px=8, near_fp64=1e-3, out_dtype=None,
+                 n_streams=4, max_batch=64, max_batch_pixels=1 << 26, hbm_budget=8 << 30):
+        import torch
+        o = ServerOpts()
+        _lib.dc_default_server_opts(C.byref(o))
+        o.eval = eval_opts(method="fmm", precision=precision, p=p, tile_px=tile_px,
+                           near_fp64=near_fp64)
+        self.dtype = out_dtype or torch.float32
+        o.out_dtype = {torch.float32: OUT_F32, torch.float64: OUT_F64}[self.dtype]
+        o.n_streams, o.max_batch = int(n_streams), int(max_batch)
+        o.max_batch_pixels, o.hbm_budget = int(max_batch_pixels), int(hbm_budget)
+        h = C.c_void_p()
+        _check(_lib.dc_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._shapes = {}
+        self._scenes = []
+
+    def add_scene(self, scene):
+        _check(_lib.dc_server_add_scene(self._h, scene._h))
+        self._scenes.append(scene)
+
+    def submit(self, scene, viewport):
+        cx, cy, w, h, W, H = viewport
+        vp = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        t = C.c_longlong()
+        _check(_lib.dc_server_submit(self._h, scene._h, C.byref(vp), C.byref(t)))
+        self._shapes[t.value] = (int(H), int(W), 3)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        """Request info dict once done; None on timeout."""
+        info = RequestInfo()
+        rc = _check(_lib.dc_server_wait(self._h, int(ticket), float(timeout), C.byref(info)),
+                    allow=(DC_ERR_TIMEOUT,))
+        if rc == DC_ERR_TIMEOUT:
+            return None
+        return {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+
+    def fetch(self, ticket, out=None):
+        """Copy the finished image into out (a CUDA tensor, new if None)."""
+        import torch
+        shape = self._shapes.pop(ticket)
+        if out is None:
+            out = torch.empty(shape, device="cuda", dtype=self.dtype)
+        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == shape
+        assert out.dtype == self.dtype
+        _check(_lib.dc_server_fetch(self._h, int(ticket), C.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.dc_server_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -24,7 +24,8 @@ import numpy as np
 __all__ = [
     "Scene", "uniform_scene", "sized_scene", "clustered_scene",
     "zoom_viewports", "serving_scenes", "polygon_ctrl", "circle_ctrl",
-    "bernstein_point", "TINY", "FMM", "PRECISION", "BATCH", "SERVING",
+    "bernstein_point", "batch_scene", "serving_requests", "poisson_arrivals",
+    "TINY", "FMM", "PRECISION", "BATCH", "SERVING",
 ]
 
 
@@ -124,6 +125,23 @@ def zoom_viewports(ctrl, n=64, sides=(128, 256, 512, 1024, 2048),
     return vps
 
 
+def batch_scene(cfg=None):
+    """The 500-curve scene of the batched-render workload and its 64 zoomed
+    viewports.
+
+    Curves are drawn by sized_scene (lengths log-uniform in [0.01, 0.5]),
+    not with control points uniform in [0,1]^2: at 500 curves the latter
+    cross so densely that the collocation system has a reciprocal condition
+    number near 1e-12, densities near 1e6 and pixel values far outside the
+    colour range, which is no diffusion-curve image.
+    """
+    cfg = BATCH if cfg is None else cfg
+    sc = sized_scene(n_curves=cfg["n_curves"], n_stops=cfg["n_stops"], seed=cfg["seed"],
+                     panels=cfg["panels"], gl=cfg["gl"], segs=cfg["segs"])
+    vps = zoom_viewports(sc["ctrl"], n=cfg["n_viewports"], seed=cfg["seed"])
+    return sc, vps
+
+
 def serving_scenes(n_scenes=16, seed0=100, nmin=10, nmax=5000, **kw):
     """Resident scenes of log-uniform curve counts for the serving loop."""
     out = []
@@ -132,6 +150,29 @@ def serving_scenes(n_scenes=16, seed0=100, nmin=10, nmax=5000, **kw):
         n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
         out.append(sized_scene(n_curves=n, seed=seed0 + k, **kw))
     return out
+
+
+def serving_requests(scenes, n, seed=7, sides=(256, 512, 1024, 2048), zoom=(1.0, 1e6)):
+    """Request stream of the serving workload: (scene index, viewport) with
+    the scene uniform, the side uniform over `sides`, zoom log-uniform and
+    the centre at a uniform parameter of a random curve of that scene."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        k = int(rng.integers(len(scenes)))
+        ctrl = scenes[k]["ctrl"]
+        side = int(rng.choice(sides))
+        z = 10.0 ** rng.uniform(np.log10(zoom[0]), np.log10(zoom[1]))
+        c = int(rng.integers(ctrl.shape[0]))
+        cx, cy = bernstein_point(ctrl[c], rng.uniform(0.0, 1.0))
+        out.append((k, (float(cx), float(cy), 1.0 / z, 1.0 / z, side, side)))
+    return out
+
+
+def poisson_arrivals(n, rate, seed=11):
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
 def polygon_ctrl(vertices):
@@ -174,6 +215,11 @@ FMM = dict(n_curves=200, n_stops=3, seed=1, panels=16, gl=16, segs=80,
            viewport=(0.5, 0.5, 1.0, 1.0, 2048, 2048))
 PRECISION = dict(seed=2, panels=32, gl=16, segs=80,
                  viewport=(0.5, 0.5, 1.0, 1.0, 4096, 4096))
+# The batch scene uses the sized generator: 500 curves with control points
+# uniform in the unit square cross each other thousands of times and make
+# the hybrid system numerically singular (see batch_scene).  The domain
+# covers zoom-1 viewports centred anywhere on a curve.
 BATCH = dict(n_curves=500, n_stops=2, seed=3, panels=4, gl=16, segs=80,
-             n_viewports=64)
-SERVING = dict(n_scenes=16, seed0=100, panels=16, gl=16, segs=80)
+             n_viewports=64, domain=(-1.0, -1.0, 2.0, 2.0))
+SERVING = dict(n_scenes=16, seed0=100, panels=16, gl=16, segs=80,
+               domain=(-1.0, -1.0, 2.0, 2.0), n_requests=2000, n_warmup=100)

@@ -1,7 +1,8 @@
 """Write tests/golden/c4_golden.npz: FP64 oracle data for the 500-curve
-batched-render workload (4 panels x 16 GL nodes per curve, 80 segments per
-panel, N = 32,000; 64 zoomed viewports of 128..2048 pixels a side, zoom
-1..1e6, centred on curve points):
+batched-render workload (curves of log-uniform length 0.01..0.5, 4 panels x
+16 GL nodes per curve, 80 segments per panel, N = 32,000; 64 zoomed
+viewports of 128..2048 pixels a side, zoom 1..1e6, centred on curve
+points):
 
   sigma      oracle densities from the dense LU solve [3][N]
   vp         the 64 viewports (cx, cy, w, h, W, H)
@@ -46,8 +47,7 @@ def sample_pixels(W, H):
 def main():
     cfg = scenegen.BATCH
     workers = int(os.environ.get("WORKERS", "8"))
-    sc = scenegen.uniform_scene(n_curves=cfg["n_curves"], n_stops=cfg["n_stops"],
-                                seed=cfg["seed"])
+    sc, vps = scenegen.batch_scene(cfg)
     t0 = time.time()
     disc = oracle.discretize(sc["ctrl"], cfg["panels"], cfg["gl"], cfg["segs"],
                              workers=workers)
@@ -57,7 +57,6 @@ def main():
     t0 = time.time()
     sigma, mu = oracle.solve(disc, up, um, workers=workers, report=rep)
     print(f"solve: {time.time() - t0:.1f} s, rcond={rep.get('rcond')}", flush=True)
-    vps = scenegen.zoom_viewports(sc["ctrl"], n=cfg["n_viewports"], seed=cfg["seed"])
     vid, rows, cols, pts = [], [], [], []
     for v, vp in enumerate(vps):
         r, c = sample_pixels(vp[4], vp[5])
@@ -70,6 +69,8 @@ def main():
     t0 = time.time()
     vals = oracle.evaluate(disc, sigma, mu, pts, workers=workers)
     print(f"evaluate {len(pts)} px: {time.time() - t0:.1f} s", flush=True)
+    print(f"|sigma| max {np.abs(sigma).max():.3e}, values in [{vals.min():.3f}, "
+          f"{vals.max():.3f}]", flush=True)
     np.savez_compressed(OUT, sigma=sigma, vp=np.array(vps), vid=np.concatenate(vid),
                         rows=np.concatenate(rows), cols=np.concatenate(cols), vals=vals,
                         rcond=rep.get("rcond", np.nan))

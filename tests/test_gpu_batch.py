@@ -91,12 +91,10 @@ def test_batch_rejects_bad_input(gpu_lib, tiny):
 @pytest.fixture(scope="module")
 def c4(gpu_lib):
     g = np.load(os.path.join(HERE, "golden", "c4_golden.npz"))
-    sc = scenegen.uniform_scene(n_curves=C4["n_curves"], n_stops=C4["n_stops"],
-                                seed=C4["seed"])
-    vps = scenegen.zoom_viewports(sc["ctrl"], n=C4["n_viewports"], seed=C4["seed"])
+    sc, vps = scenegen.batch_scene()
     np.testing.assert_array_equal(np.array(vps), g["vp"])
     s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=C4["panels"],
-                      gl=C4["gl"], segs=C4["segs"], leaf_max=16)
+                      gl=C4["gl"], segs=C4["segs"], leaf_max=16, domain=C4["domain"])
     print("C4 scene", s.info(), "pixels", sum(v[4] * v[5] for v in vps), flush=True)
     yield dict(s=s, vps=vps, g=g)
     s.close()
