@@ -292,23 +292,31 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Per-lane piece data of the incoming-from-source pass, kept in LDS so the
+// coefficient blocks reuse it without holding it in registers.
+struct P2LPiece {
+    double zAr[kWave], zAi[kWave], zBr[kWave], zBi[kWave];  // 1/A, 1/B
+    double par[kWave], pai[kWave], pbr[kWave], pbi[kWave];  // running zA^(k-1), zB^(k-1)
+    double wr[kWave], wi[kWave];                             // wbar
+    double qs[3][kWave], qm[3][kWave];
+};
+
 template <typename T>
 __device__ void p2l_wave(cpx<T> acc[3], const PieceView& pv, const TreeView& tv, const int* l4,
                          const int* pre, int nl4, double cx, double cy, double r, int p,
-                         int lane) {
-    constexpr int KB = 8;
+                         int lane, P2LPiece& sp) {
+    constexpr int KB = 4;
     const int total = pre[nl4];
     const double inv_r = 1.0 / r;
     const T rr = (T)r, logr = (T)log(r);
     const T* w = weights<T>(pv);
-    for (int kb = 0; kb <= p; kb += KB) {
-        cpx<T> part[3][KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j)
-            for (int ch = 0; ch < 3; ++ch) part[ch][j] = {0, 0};
-        for (int base = 0; base < total; base += kWave) {
-            const int g = base + lane;
-            if (g >= total) continue;
+    for (int base = 0; base < total; base += kWave) {
+        const int g = base + lane;
+        const bool valid = g < total;
+        // k = 0 and k = 1 terms of this lane's piece open the first block
+        cpx<T> c01[2][3];
+        for (int ch = 0; ch < 3; ++ch) c01[0][ch] = c01[1][ch] = {0, 0};
+        if (valid) {
             int u = 0;
             while (u + 1 < nl4 && pre[u + 1] <= g) ++u;
             const int e = tv.pbeg[l4[u]] + (g - pre[u]);
@@ -317,63 +325,89 @@ __device__ void p2l_wave(cpx<T> acc[3], const PieceView& pv, const TreeView& tv,
             const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
             const T len = (T)pv.len[e];
             const cpx<T> zA = cinv(A), zB = cinv(B);
-            T qs[3], qm[3];
+            const cpx<T> BA = cmul(B, cpx<T>{A.re, -A.im});
+            const T nA = A.re * A.re + A.im * A.im, nB = B.re * B.re + B.im * B.im;
+            const cpx<T> Lam = {T(0.5) * log(nB / nA), atan2(BA.im, BA.re)};
+            const cpx<T> lA = clog(A);
+            const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
+            const cpx<T> sv0 = {-(len * (logr + lA.re) + t2.re - len), -(len * lA.im + t2.im)};
+            const cpx<T> mv0 = {Lam.im, -Lam.re};
+            const cpx<T> sv1 = cmul(wbar, cscale(Lam, rr));
+            const cpx<T> d1 = csub(zB, zA);
+            const cpx<T> mv1 = {-d1.im, d1.re};
+            sp.zAr[lane] = zA.re;
+            sp.zAi[lane] = zA.im;
+            sp.zBr[lane] = zB.re;
+            sp.zBi[lane] = zB.im;
+            sp.par[lane] = zA.re;
+            sp.pai[lane] = zA.im;
+            sp.pbr[lane] = zB.re;
+            sp.pbi[lane] = zB.im;
+            sp.wr[lane] = wbar.re;
+            sp.wi[lane] = wbar.im;
             for (int ch = 0; ch < 3; ++ch) {
-                qs[ch] = w[(size_t)ch * pv.n + e];
-                qm[ch] = w[(size_t)(3 + ch) * pv.n + e];
-            }
-            cpx<T> Lam = {0, 0};
-            if (kb == 0) {
-                const cpx<T> BA = cmul(B, cpx<T>{A.re, -A.im});
-                const T nA = A.re * A.re + A.im * A.im, nB = B.re * B.re + B.im * B.im;
-                Lam = {T(0.5) * log(nB / nA), atan2(BA.im, BA.re)};
-            }
-            // running powers zA^{k-1}, zB^{k-1} for the first k >= 1 of the block
-            const int k1 = kb == 0 ? 1 : kb;
-            cpx<T> pa = cpow(zA, k1 - 1), pb = cpow(zB, k1 - 1);
-#pragma unroll
-            for (int j = 0; j < KB; ++j) {
-                const int k = kb + j;
-                if (k > p) break;
-                cpx<T> sv, mv;
-                if (k == 0) {
-                    const cpx<T> lA = clog(A);
-                    const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
-                    sv = {-(len * (logr + lA.re) + t2.re - len), -(len * lA.im + t2.im)};
-                    mv = {Lam.im, -Lam.re};
-                } else if (k == 1) {
-                    sv = cmul(wbar, cscale(Lam, rr));
-                    const cpx<T> d = csub(zB, zA);
-                    mv = {-d.im, d.re};
-                    pa = zA;
-                    pb = zB;
-                } else {
-                    sv = cmul(wbar, cscale(csub(pa, pb), rr * recip<T>(k) * recip<T>(k - 1)));
-                    const cpx<T> na = cmul(pa, zA), nb = cmul(pb, zB);
-                    const cpx<T> d = cscale(csub(nb, na), recip<T>(k));
-                    mv = {-d.im, d.re};
-                    pa = na;
-                    pb = nb;
-                }
-                for (int ch = 0; ch < 3; ++ch)
-                    part[ch][j] = cadd(part[ch][j], cadd(cscale(sv, qs[ch]), cscale(mv, qm[ch])));
+                const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
+                sp.qs[ch][lane] = qs;
+                sp.qm[ch][lane] = qm;
+                c01[0][ch] = cadd(cscale(sv0, qs), cscale(mv0, qm));
+                c01[1][ch] = cadd(cscale(sv1, qs), cscale(mv1, qm));
             }
         }
+        // coefficients in blocks of KB; the running powers live in LDS
+        for (int kb = 0; kb <= p; kb += KB) {
+            cpx<T> part[3][KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            for (int ch = 0; ch < 3; ++ch) {
-                const cpx<T> v = {wave_sum(part[ch][j].re), wave_sum(part[ch][j].im)};
-                if (lane == kb + j) acc[ch] = cadd(acc[ch], v);
+            for (int j = 0; j < KB; ++j)
+                for (int ch = 0; ch < 3; ++ch) part[ch][j] = {0, 0};
+            if (valid) {
+                const cpx<T> zA = {sp.zAr[lane], sp.zAi[lane]}, zB = {sp.zBr[lane], sp.zBi[lane]};
+                const cpx<T> wbar = {sp.wr[lane], sp.wi[lane]};
+                cpx<T> pa = {sp.par[lane], sp.pai[lane]}, pb = {sp.pbr[lane], sp.pbi[lane]};
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    const int k = kb + j;
+                    if (k > p) break;
+                    if (k <= 1) {
+                        for (int ch = 0; ch < 3; ++ch) part[ch][j] = c01[k][ch];
+                        continue;
+                    }
+                    // pa = zA^{k-1}, pb = zB^{k-1}
+                    const cpx<T> sv =
+                        cmul(wbar, cscale(csub(pa, pb), rr * recip<T>(k) * recip<T>(k - 1)));
+                    const cpx<T> na = cmul(pa, zA), nb = cmul(pb, zB);
+                    const cpx<T> d = cscale(csub(nb, na), recip<T>(k));
+                    const cpx<T> mv = {-d.im, d.re};
+                    pa = na;
+                    pb = nb;
+                    for (int ch = 0; ch < 3; ++ch)
+                        part[ch][j] = cadd(cscale(sv, sp.qs[ch][lane]),
+                                           cscale(mv, sp.qm[ch][lane]));
+                }
+                sp.par[lane] = pa.re;
+                sp.pai[lane] = pa.im;
+                sp.pbr[lane] = pb.re;
+                sp.pbi[lane] = pb.im;
+            }
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                for (int ch = 0; ch < 3; ++ch) {
+                    const cpx<T> v = {wave_sum(part[ch][j].re), wave_sum(part[ch][j].im)};
+                    if (lane == kb + j) acc[ch] = cadd(acc[ch], v);
+                }
             }
         }
     }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kWave, 4)
 k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
        cpx<T>* __restrict__ L, int* __restrict__ nset) {
     __shared__ int sPN[9];
+    // LDS shared by the interaction-list reduction and incoming-from-source
+    constexpr size_t kScratch = sizeof(P2LPiece) > sizeof(cpx<T>) * kWave * 3
+                                    ? sizeof(P2LPiece) : sizeof(cpx<T>) * kWave * 3;
+    __shared__ __align__(16) unsigned char sScratch[kScratch];
     const int lane = threadIdx.x;
     const int l = dl.l;
     long long ti, tj;
@@ -476,41 +510,50 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             m2l_lane<T>(gacc, M + (size_t)sIL[e] * P1 * 3, p, k, w, logd);
         }
         if (dl.stats && lane == 0) atomicAdd(dl.stats + kStatM2L, (unsigned long long)nIL);
-        // reduce the groups into group 0
-        __shared__ cpx<T> sRed[kWave][3];
+        // reduce the groups into group 0 (through the LDS the incoming-from-
+        // source pass reuses below)
+        cpx<T>(*sRed)[3] = reinterpret_cast<cpx<T>(*)[3]>(sScratch);
         if (glane)
             for (int ch = 0; ch < 3; ++ch) sRed[lane][ch] = gacc[ch];
         __syncthreads();
         if (klane)
             for (int g = 0; g < ngrp; ++g)
                 for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], sRed[g * P1 + k][ch]);
+        __syncthreads();
     }
     // bigger separated list: coarser source leaves that do not touch us;
     // their pieces are flattened into one list shared by the wave
-    int l4[9], pre[10], nl4 = 0;
-    pre[0] = 0;
-    for (int s = 0; s < 9; ++s) {
-        const int c = sPN[s];
-        if (c < 0 || (tv.lvl[c] == l - 1 && tv.child[c] >= 0)) continue;
-        bool dup = false;
-        for (int s2 = 0; s2 < s; ++s2) dup |= (sPN[s2] == c);
-        if (dup || tv.npc[c] == 0 || touches(tv, c, l, ti, tj)) continue;
-        l4[nl4] = c;
-        pre[nl4 + 1] = pre[nl4] + (tv.pend[c] - tv.pbeg[c]);
-        ++nl4;
+    __shared__ int sL4[9], sPre[10], sNl4;
+    P2LPiece& sP2L = *reinterpret_cast<P2LPiece*>(sScratch);
+    if (lane == 0) {
+        int nl4 = 0;
+        sPre[0] = 0;
+        for (int s = 0; s < 9; ++s) {
+            const int c = sPN[s];
+            if (c < 0 || (tv.lvl[c] == l - 1 && tv.child[c] >= 0)) continue;
+            bool dup = false;
+            for (int s2 = 0; s2 < s; ++s2) dup |= (sPN[s2] == c);
+            if (dup || tv.npc[c] == 0 || touches(tv, c, l, ti, tj)) continue;
+            sL4[nl4] = c;
+            sPre[nl4 + 1] = sPre[nl4] + (tv.pend[c] - tv.pbeg[c]);
+            ++nl4;
+        }
+        sNl4 = nl4;
     }
+    __syncthreads();
+    const int nl4 = sNl4;
     if (nl4 > 0) {
         // always in FP64: pieces of one leaf can carry large charges of both
         // signs whose sum cancels (near-cusps), beyond FP32's reach
         cpx<double> accd[3] = {{0, 0}, {0, 0}, {0, 0}};
-        p2l_wave<double>(accd, pv, tv, l4, pre, nl4, cx, cy, r, p, lane);
+        p2l_wave<double>(accd, pv, tv, sL4, sPre, nl4, cx, cy, r, p, lane, sP2L);
         for (int ch = 0; ch < 3; ++ch) {
             acc[ch].re += (T)accd[ch].re;
             acc[ch].im += (T)accd[ch].im;
         }
     }
     if (dl.stats && k == 0) {
-        atomicAdd(dl.stats + kStatP2L, (unsigned long long)pre[nl4]);
+        atomicAdd(dl.stats + kStatP2L, (unsigned long long)sPre[nl4]);
         atomicAdd(dl.stats + kStatL2L, 1ULL);
     }
     if (!klane) return;
@@ -821,6 +864,258 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a0, int p, const cpx<double>* __restr
     }
 }
 
+// Hardware dispatch places block b on XCD b % 8; renumber blocks so that
+// each XCD receives one contiguous run of tiles (neighbouring tiles share
+// their near pieces, which then stay in that XCD's L2).
+__device__ inline int xcd_block(int b, int nb) {
+    constexpr int kXcd = 8;
+    const int x = b % kXcd, q = nb / kXcd, rmd = nb % kXcd;
+    return x * q + min(x, rmd) + b / kXcd;
+}
+
+// Render leaf pass (Alg. 4 at pixel tiles), PX pixels per thread: each
+// piece staged in LDS is read once and evaluated against PX pixels, which
+// gives every lane PX independent chains of the closed forms.  Same
+// arithmetic per (pixel, source) pair as k_leaf; targets are pixels only.
+template <typename T, int NT, int PX>
+__global__ void __launch_bounds__(NT)
+k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
+       const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
+    int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
+    blk -= v.first_block;
+    a.L = v.L;
+    a.i0 = v.i0;
+    a.j0 = v.j0;
+    a.wl = v.wl;
+    a.off = v.off;
+    a.vcx = v.vcx;
+    a.vcy = v.vcy;
+    a.vw = v.vw;
+    a.vh = v.vh;
+    a.W = v.W;
+    a.H = v.H;
+    a.out = v.out;
+    __shared__ LeafShared<T, NT> sh;
+    const int tid = threadIdx.x;
+    const int l = a.L;
+    const long long ti = a.i0 + blk % a.wl, tj = a.j0 + blk / a.wl;
+    const int own = a.off + blk;
+    const double sideL = ldexp(tv.side, -l);
+    const int k_lo = first_true_col(a, tv.X0, sideL, ti);
+    const int nx = first_true_col(a, tv.X0, sideL, ti + 1) - k_lo;
+    const int r_lo = first_true_row(a, tv.Y0, sideL, tj);
+    const int ny = max(first_true_row(a, tv.Y0, sideL, tj - 1) - r_lo, 0);
+    const int n_targets = nx > 0 ? nx * ny : 0;
+    const double r = half_width(tv, l);
+    double cx, cy;
+    center_of(tv, l, ti, tj, cx, cy);
+    const T* wts = weights<T>(pv);
+    const cpx<double>* loc = Lc + (size_t)own * (p + 1) * 3;
+
+    for (int tbase = 0; tbase < n_targets; tbase += NT * PX) {
+        double x[PX], y[PX];
+        T xr[PX], yr[PX];
+        bool act[PX];
+        int out_idx[PX];
+        // u = (E - P) / 2pi: E from expansions, P the near field (FP64 sums)
+        double acc[PX][3];
+        for (int q = 0; q < PX; ++q) {
+            const int tgt = tbase + q * NT + tid;
+            act[q] = tgt < n_targets;
+            x[q] = cx;
+            y[q] = cy;
+            out_idx[q] = 0;
+            if (act[q]) {
+                const int col = k_lo + tgt % nx, row = r_lo + tgt / nx;
+                x[q] = pixel_x(a.vcx, a.vw, a.W, col);
+                y[q] = pixel_y(a.vcy, a.vh, a.H, row);
+                out_idx[q] = row * a.W + col;
+            }
+            xr[q] = (T)(x[q] - cx);
+            yr[q] = (T)(y[q] - cy);
+            for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
+        }
+        // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
+        if (l >= 2) {
+            for (int q = 0; q < PX; ++q) {
+                const cpx<double> z = {(x[q] - cx) / r, (y[q] - cy) / r};
+                for (int ch = 0; ch < 3; ++ch) {
+                    cpx<double> s = loc[p * 3 + ch];
+                    for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
+                    acc[q][ch] += s.re;
+                }
+            }
+        }
+        const int n_here = min(NT * PX, n_targets - tbase);
+        if (a.stats && tid == 0) {
+            if (l >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
+            if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
+        }
+        // near-set traversal, in rounds bounded by the list capacities
+        if (tid == 0) {
+            sh.nS = 0;
+            for (int s = 0; s < 9; ++s) {
+                const int c = nset[(size_t)own * 9 + s];
+                bool dup = c < 0;
+                for (int s2 = 0; s2 < s && !dup; ++s2) dup = nset[(size_t)own * 9 + s2] == c;
+                if (!dup && tv.npc[c] > 0) sh.stack[sh.nS++] = c;
+            }
+        }
+        __syncthreads();
+        for (;;) {
+            if (tid == 0) {
+                int nU = 0, nW = 0;
+                while (sh.nS > 0 && nU < kUCap && nW + 4 <= kWCap) {
+                    const int c = sh.stack[--sh.nS];
+                    if (tv.child[c] < 0) {
+                        sh.U[nU++] = c;
+                        continue;
+                    }
+                    for (int q = 0; q < 4; ++q) {
+                        const int d = tv.child[c] + q;
+                        if (tv.npc[d] == 0) continue;
+                        if (touches(tv, d, l, ti, tj)) {
+                            if (sh.nS < kSCap) sh.stack[sh.nS++] = d;
+                        } else {
+                            sh.W[nW++] = d;
+                        }
+                    }
+                }
+                int cum = 0;
+                for (int u = 0; u < nU; ++u) {
+                    sh.Upre[u] = cum;
+                    cum += tv.pend[sh.U[u]] - tv.pbeg[sh.U[u]];
+                }
+                sh.Upre[nU] = cum;
+                sh.nU = nU;
+                sh.nW = nW;
+                sh.more = sh.nS > 0;
+            }
+            __syncthreads();
+            const int nU = sh.nU, nW = sh.nW, more = sh.more;
+            if (a.stats && tid == 0) {
+                atomicAdd(a.stats + kStatM2P, (unsigned long long)n_here * nW);
+                atomicAdd(a.stats + kStatP2P, (unsigned long long)n_here * sh.Upre[nU]);
+            }
+            // target-from-outgoing (Eq. t-f-o), scaled:
+            //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
+            for (int u = 0; u < nW; ++u) {
+                const int d = sh.W[u];
+                const int ld = tv.lvl[d];
+                const double rd = half_width(tv, ld);
+                double dcx, dcy;
+                center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
+                const double lr = log(rd);
+                const cpx<double>* src = M + (size_t)d * (p + 1) * 3;
+                for (int q = 0; q < PX; ++q) {
+                    if (!act[q]) continue;
+                    const cpx<double> rel = {(x[q] - dcx) / rd, (y[q] - dcy) / rd};
+                    const cpx<double> z = cinv(rel);
+                    const cpx<double> lg = clog(rel);
+                    for (int ch = 0; ch < 3; ++ch) {
+                        cpx<double> s = cscale(src[p * 3 + ch], recip<double>(p));
+                        for (int kk = p - 1; kk >= 1; --kk)
+                            s = cadd(cmul(s, z), cscale(src[kk * 3 + ch], recip<double>(kk)));
+                        s = cmul(s, z);
+                        const cpx<double> m0 = src[ch];
+                        acc[q][ch] += s.re - ((lr + lg.re) * m0.re - lg.im * m0.im);
+                    }
+                }
+            }
+            // target-from-source (App. D) over the pieces of the near leaves
+            const int total = sh.Upre[nU];
+            for (int pbase = 0; pbase < total; pbase += NT) {
+                __syncthreads();
+                const int g = pbase + tid;
+                if (g < total) {
+                    int lo = 0, hi = nU - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sh.Upre[mid] <= g) lo = mid; else hi = mid - 1;
+                    }
+                    const int e = tv.pbeg[sh.U[lo]] + (g - sh.Upre[lo]);
+                    sh.px[tid] = (T)(pv.x0[e] - cx);
+                    sh.py[tid] = (T)(pv.y0[e] - cy);
+                    sh.tx[tid] = (T)pv.tx[e];
+                    sh.ty[tid] = (T)pv.ty[e];
+                    sh.len[tid] = (T)pv.len[e];
+                    for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
+                    sh.pid[tid] = sizeof(T) == 4 && pv.heavy[e] ? -1 - e : e;
+                }
+                __syncthreads();
+                const int m = min(NT, total - pbase);
+                const float near2f = (float)a.near2;
+                for (int j = 0; j < m; ++j) {
+                    const T px0 = sh.px[j], py0 = sh.py[j];
+                    const T tx = sh.tx[j], ty = sh.ty[j], la = sh.len[j];
+                    const int pid = sh.pid[j];
+                    if (sizeof(T) == 8) {
+                        for (int q = 0; q < PX; ++q) {
+                            T il, th;
+                            chord_log_theta<T>(px0 - xr[q], py0 - yr[q], tx, ty, la, il, th);
+                            for (int ch = 0; ch < 3; ++ch)
+                                acc[q][ch] -= il * sh.w[ch][j] + th * sh.w[3 + ch][j];
+                        }
+                        continue;
+                    }
+                    // FP32: the fast closed form for every pixel, straight-line
+                    // so the PX chains interleave; near-singular pairs and
+                    // heavy pieces are then redone in FP64 (rare, divergent)
+                    float il[PX], th[PX];
+                    bool slow[PX];
+                    bool any_slow = false;
+                    const float fla = (float)la, lim = near2f * fla * fla;
+                    for (int q = 0; q < PX; ++q) {
+                        const float dx = (float)(px0 - xr[q]), dy = (float)(py0 - yr[q]);
+                        const float xi1 = dx * (float)tx + dy * (float)ty;
+                        const float h = dy * (float)tx - dx * (float)ty;
+                        const float xi2 = xi1 + fla;
+                        // squared distance to the chord, branch-free
+                        const float along = fmaxf(xi1, 0.f) + fmaxf(-xi2, 0.f);
+                        slow[q] = along * along + h * h < lim || pid < 0;
+                        any_slow |= slow[q] && act[q];
+                        chord_fast(xi1, h, xi2, fla, il[q], th[q]);
+                    }
+                    float w6[6];
+                    for (int c6 = 0; c6 < 6; ++c6) w6[c6] = (float)sh.w[c6][j];
+                    for (int q = 0; q < PX; ++q)
+                        for (int ch = 0; ch < 3; ++ch) {
+                            const float t = il[q] * w6[ch] + th[q] * w6[3 + ch];
+                            acc[q][ch] -= slow[q] ? 0.0 : (double)t;
+                        }
+                    if (any_slow) {
+                        const int e = pid < 0 ? -1 - pid : pid;
+                        for (int q = 0; q < PX; ++q) {
+                            if (!(slow[q] && act[q])) continue;
+                            double dil, dth;
+                            chord_log_theta<double>(pv.x0[e] - x[q], pv.y0[e] - y[q], pv.tx[e],
+                                                    pv.ty[e], pv.len[e], dil, dth);
+                            for (int ch = 0; ch < 3; ++ch)
+                                acc[q][ch] -= dil * pv.w64[(size_t)ch * pv.n + e] +
+                                              dth * pv.w64[(size_t)(3 + ch) * pv.n + e];
+                            if (a.stats) atomicAdd(a.stats + kStatP2P64, 1ULL);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (!more) break;
+        }
+        for (int q = 0; q < PX; ++q) {
+            if (!act[q]) continue;
+            for (int ch = 0; ch < 3; ++ch) {
+                const double u = acc[q][ch] / kTwoPi;
+                if (a.out_f64)
+                    static_cast<double*>(a.out)[(size_t)out_idx[q] * 3 + ch] = u;
+                else
+                    static_cast<float*>(a.out)[(size_t)out_idx[q] * 3 + ch] = (float)u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Self-segment correction at the nodes: the FMM summed every piece of the
 // node's own segment with the regular closed form; replace that by the
 // singular rule (App. C.1, D.3, D.4):
@@ -1044,12 +1339,13 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     a.vleaf = d_leaf;
     a.nvleaf = pl.n;
     if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
+    // tiles of up to 9 x 9 pixels: one pixel per thread; up to 17 x 17: two
     if (o.tile_px <= 8)
-        hipLaunchKernelGGL((k_leaf<T, 64>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv, pv, a, p,
-                           M, TL, nset);
-    else
-        hipLaunchKernelGGL((k_leaf<T, 256>), dim3(pl.leaf_blocks), dim3(256), 0, st, tv, pv, a,
+        hipLaunchKernelGGL((k_tile<T, 64, 1>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv, pv, a,
                            p, M, TL, nset);
+    else
+        hipLaunchKernelGGL((k_tile<T, 128, 2>), dim3(pl.leaf_blocks), dim3(128), 0, st, tv, pv,
+                           a, p, M, TL, nset);
     DC_HIP(hipGetLastError());
     if (timed) {
         DC_HIP(hipEventRecord(f.ev[3], st));
