@@ -2,6 +2,7 @@
 // on the scene quadtree.  Host-side driver interface.
 #pragma once
 
+#include <map>
 #include <memory>
 #include <vector>
 
@@ -99,6 +100,9 @@ struct FmmState {
     // Multipole and local coefficients of the source tree (FP64 in both
     // precision modes), and near sets.
     DevBuf<double> M64, L64;
+    // Tabulated incoming-from-outgoing operators per expansion order
+    // (see m2l_table in fmm.hip).
+    std::map<int, std::unique_ptr<DevBuf<double>>> m2l_tab;
     DevBuf<int> nsetS;
     // Upward pass of the resident densities (render reuses it).
     bool up_valid = false;

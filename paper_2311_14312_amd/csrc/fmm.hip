@@ -24,6 +24,7 @@
 // exactly Alg. 8; for a render the target tree is the complete quadtree over
 // the viewport down to pixel tiles.
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "scene.h"
@@ -253,28 +254,15 @@ struct DownLevel {
     unsigned long long* stats;  // optional work counters (see kStat*)
 };
 
-// Incoming-from-outgoing (Eq. i-f-o), scaled, lane k = output index:
-//   Lt_k += (-1)^k sum_m c(k,m) w^{k+m} Mt_m,  c(k,m) = (k+m-1)!/(k! m!),
-//   w = r / (c_target - c_source); the k = m = 0 term is -log(c_t - c_s).
-template <typename T>
-__device__ inline void m2l_lane(cpx<T> acc[3], const cpx<T>* __restrict__ src, int p, int k,
-                                cpx<T> w, cpx<T> logd) {
-    cpx<T> pw = cpow(w, k);
-    const T sign = (k & 1) ? T(-1) : T(1);
-    T coef = k == 0 ? T(0) : recip<T>(k);
-    for (int m = 0; m <= p; ++m) {
-        cpx<T> t;
-        if (k == 0 && m == 0) {
-            t = {-logd.re, -logd.im};
-            coef = T(1);
-        } else {
-            t = cscale(pw, sign * coef);
-            coef = coef * (T)(k + m) * recip<T>(m + 1);
-        }
-        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(t, src[m * 3 + ch]));
-        pw = cmul(pw, w);
-    }
-}
+// Incoming-from-outgoing (Eq. i-f-o), scaled:
+//   Lt_k += sum_m T[o][k][m] Mt_m,  T[o][k][m] = (-1)^k c(k,m) w^{k+m},
+//   c(k,m) = (k+m-1)!/(k! m!),  w = r / (c_target - c_source),
+// and for k = m = 0 the term -log(c_target - c_source) Mt_0.  With source
+// and target boxes of one level, w and the log's argument depend only on
+// the offset (dx, dy) of the source box in box widths, so T is tabulated
+// once per order for the 7 x 7 offsets (m2l_table); the kernel adds the
+// level part -log(2r) Mt_0 of the k = 0 term.
+// Layout: [o][k][m] complex, o = (dy + 3) * 7 + (dx + 3).
 
 // Incoming-from-source (App. E.10, E.11), scaled.  For a piece with ends
 // A, B relative to the box centre in units of r, zA = 1/A, zB = 1/B and
@@ -283,130 +271,34 @@ __device__ inline void m2l_lane(cpx<T> acc[3], const cpx<T>* __restrict__ src, i
 //   k = 0: -qs [|a| (log r + log A) + wbar r B Lam - |a|]  - i qm Lam
 //   k = 1:  qs wbar r Lam                               + i qm (zB - zA)
 //   k > 1:  qs wbar r (zA^{k-1} - zB^{k-1})/(k(k-1))    + i qm (zB^k - zA^k)/k
-// The wave splits the pieces over its 64 lanes and walks k in blocks of KB
-// with running powers; block partial sums are reduced across the wave and
-// handed to the lane that owns coefficient k.
 template <typename T>
 __device__ inline T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// Per-lane piece data of the incoming-from-source pass, kept in LDS so the
-// coefficient blocks reuse it without holding it in registers.
-struct P2LPiece {
+// Per-piece data of the incoming-from-source pass, one piece per lane.
+struct P2LStage {
     double zAr[kWave], zAi[kWave], zBr[kWave], zBi[kWave];  // 1/A, 1/B
-    double par[kWave], pai[kWave], pbr[kWave], pbi[kWave];  // running zA^(k-1), zB^(k-1)
     double wr[kWave], wi[kWave];                             // wbar
     double qs[3][kWave], qm[3][kWave];
 };
 
-template <typename T>
-__device__ void p2l_wave(cpx<T> acc[3], const PieceView& pv, const TreeView& tv, const int* l4,
-                         const int* pre, int nl4, double cx, double cy, double r, int p,
-                         int lane, P2LPiece& sp) {
-    constexpr int KB = 4;
-    const int total = pre[nl4];
-    const double inv_r = 1.0 / r;
-    const T rr = (T)r, logr = (T)log(r);
-    const T* w = weights<T>(pv);
-    for (int base = 0; base < total; base += kWave) {
-        const int g = base + lane;
-        const bool valid = g < total;
-        // k = 0 and k = 1 terms of this lane's piece open the first block
-        cpx<T> c01[2][3];
-        for (int ch = 0; ch < 3; ++ch) c01[0][ch] = c01[1][ch] = {0, 0};
-        if (valid) {
-            int u = 0;
-            while (u + 1 < nl4 && pre[u + 1] <= g) ++u;
-            const int e = tv.pbeg[l4[u]] + (g - pre[u]);
-            const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
-            const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
-            const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
-            const T len = (T)pv.len[e];
-            const cpx<T> zA = cinv(A), zB = cinv(B);
-            const cpx<T> BA = cmul(B, cpx<T>{A.re, -A.im});
-            const T nA = A.re * A.re + A.im * A.im, nB = B.re * B.re + B.im * B.im;
-            const cpx<T> Lam = {T(0.5) * log(nB / nA), atan2(BA.im, BA.re)};
-            const cpx<T> lA = clog(A);
-            const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
-            const cpx<T> sv0 = {-(len * (logr + lA.re) + t2.re - len), -(len * lA.im + t2.im)};
-            const cpx<T> mv0 = {Lam.im, -Lam.re};
-            const cpx<T> sv1 = cmul(wbar, cscale(Lam, rr));
-            const cpx<T> d1 = csub(zB, zA);
-            const cpx<T> mv1 = {-d1.im, d1.re};
-            sp.zAr[lane] = zA.re;
-            sp.zAi[lane] = zA.im;
-            sp.zBr[lane] = zB.re;
-            sp.zBi[lane] = zB.im;
-            sp.par[lane] = zA.re;
-            sp.pai[lane] = zA.im;
-            sp.pbr[lane] = zB.re;
-            sp.pbi[lane] = zB.im;
-            sp.wr[lane] = wbar.re;
-            sp.wi[lane] = wbar.im;
-            for (int ch = 0; ch < 3; ++ch) {
-                const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
-                sp.qs[ch][lane] = qs;
-                sp.qm[ch][lane] = qm;
-                c01[0][ch] = cadd(cscale(sv0, qs), cscale(mv0, qm));
-                c01[1][ch] = cadd(cscale(sv1, qs), cscale(mv1, qm));
-            }
-        }
-        // coefficients in blocks of KB; the running powers live in LDS
-        for (int kb = 0; kb <= p; kb += KB) {
-            cpx<T> part[3][KB];
-#pragma unroll
-            for (int j = 0; j < KB; ++j)
-                for (int ch = 0; ch < 3; ++ch) part[ch][j] = {0, 0};
-            if (valid) {
-                const cpx<T> zA = {sp.zAr[lane], sp.zAi[lane]}, zB = {sp.zBr[lane], sp.zBi[lane]};
-                const cpx<T> wbar = {sp.wr[lane], sp.wi[lane]};
-                cpx<T> pa = {sp.par[lane], sp.pai[lane]}, pb = {sp.pbr[lane], sp.pbi[lane]};
-#pragma unroll
-                for (int j = 0; j < KB; ++j) {
-                    const int k = kb + j;
-                    if (k > p) break;
-                    if (k <= 1) {
-                        for (int ch = 0; ch < 3; ++ch) part[ch][j] = c01[k][ch];
-                        continue;
-                    }
-                    // pa = zA^{k-1}, pb = zB^{k-1}
-                    const cpx<T> sv =
-                        cmul(wbar, cscale(csub(pa, pb), rr * recip<T>(k) * recip<T>(k - 1)));
-                    const cpx<T> na = cmul(pa, zA), nb = cmul(pb, zB);
-                    const cpx<T> d = cscale(csub(nb, na), recip<T>(k));
-                    const cpx<T> mv = {-d.im, d.re};
-                    pa = na;
-                    pb = nb;
-                    for (int ch = 0; ch < 3; ++ch)
-                        part[ch][j] = cadd(cscale(sv, sp.qs[ch][lane]),
-                                           cscale(mv, sp.qm[ch][lane]));
-                }
-                sp.par[lane] = pa.re;
-                sp.pai[lane] = pa.im;
-                sp.pbr[lane] = pb.re;
-                sp.pbi[lane] = pb.im;
-            }
-#pragma unroll
-            for (int j = 0; j < KB; ++j) {
-                for (int ch = 0; ch < 3; ++ch) {
-                    const cpx<T> v = {wave_sum(part[ch][j].re), wave_sum(part[ch][j].im)};
-                    if (lane == kb + j) acc[ch] = cadd(acc[ch], v);
-                }
-            }
-        }
-    }
-}
-
+// Downward pass at one level, one wave per target box: near set from the
+// parent's, incoming-from-incoming (L2L) from the parent, incoming-from-
+// outgoing (M2L) over the interaction list and incoming-from-source (P2L)
+// over the pieces of coarser separated leaves.  Lane layout: ngrp groups of
+// p+1 lanes; lane k of a group owns coefficient k.  M2L entries and P2L
+// pieces are dealt round-robin to the groups, whose sums are reduced into
+// group 0 at the end.
 template <typename T>
 __global__ void __launch_bounds__(kWave, 4)
 k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
-       cpx<T>* __restrict__ L, int* __restrict__ nset) {
+       cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab) {
     __shared__ int sPN[9];
-    // LDS shared by the interaction-list reduction and incoming-from-source
-    constexpr size_t kScratch = sizeof(P2LPiece) > sizeof(cpx<T>) * kWave * 3
-                                    ? sizeof(P2LPiece) : sizeof(cpx<T>) * kWave * 3;
+    // LDS shared by the M2L staging, the P2L staging and the group reduction
+    constexpr size_t kStageM2L = 2 * 3 * kWave * sizeof(cpx<T>);
+    constexpr size_t kScratch = sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
     __shared__ __align__(16) unsigned char sScratch[kScratch];
     const int lane = threadIdx.x;
     const int l = dl.l;
@@ -428,6 +320,28 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
     }
     if (lane < 9) sPN[lane] = nset[(size_t)par * 9 + lane];
     __syncthreads();
+    // Metadata of the parent's near set, loaded once by lanes 0..8; it
+    // serves the near set, the interaction list and the separated leaves.
+    __shared__ int sPL[9], sPC[9], sPN2[9], sPcnt[9], sPT[9];
+    if (lane < 9) {
+        const int c = sPN[lane];
+        int lv = -1, ch = -1, np = 0, pc = 0, tch = 1;
+        if (c >= 0) {
+            lv = tv.lvl[c];
+            ch = tv.child[c];
+            np = tv.npc[c];
+            pc = tv.pend[c] - tv.pbeg[c];
+            tch = touches(tv, c, l, ti, tj) ? 1 : 0;
+        }
+        sPL[lane] = lv;
+        sPC[lane] = ch;
+        sPN2[lane] = np;
+        sPcnt[lane] = pc;
+        sPT[lane] = tch;
+    }
+    __syncthreads();
+    // near set N(own): the 3 x 3 positions around own at level l, each the
+    // deepest source box at level <= l covering it
     if (lane < 9) {
         const long long px = ti + (lane % 3) - 1, py = tj + (lane / 3) - 1;
         int c = -1;
@@ -435,24 +349,22 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         if (px >= 0 && py >= 0 && px < lim && py < lim) {
             const int slot = (int)((px >> 1) - (ti >> 1) + 1) + 3 * (int)((py >> 1) - (tj >> 1) + 1);
             c = sPN[slot];
-            if (c >= 0 && tv.lvl[c] == l - 1 && tv.child[c] >= 0)
-                c = tv.child[c] + (int)(px & 1) + 2 * (int)(py & 1);
+            if (c >= 0 && sPL[slot] == l - 1 && sPC[slot] >= 0)
+                c = sPC[slot] + (int)(px & 1) + 2 * (int)(py & 1);
         }
         nset[(size_t)own * 9 + lane] = c;
     }
-    // Lane layout: the wave holds ngrp groups of p+1 lanes; lane k of group g
-    // owns coefficient k for the interaction-list entries g, g + ngrp, ...
-    // Group 0 owns the result (L2L, P2L and the final sum).
     const int P1 = p + 1;
     const int ngrp = kWave / P1;
     const int grp = lane / P1;
     const int k = lane - grp * P1;
     const bool klane = grp == 0;           // owns coefficient k of the result
-    const bool glane = grp < ngrp;         // takes part in the interaction list
+    const bool glane = grp < ngrp;         // member of a group
     const double r = half_width(tv, l);
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
-    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};   // group 0: the result
+    cpx<T> gacc[3] = {{0, 0}, {0, 0}, {0, 0}};  // every group: its share
     // incoming-from-incoming from the parent (Eq. i-f-i), scaled:
     //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
     if (klane) {
@@ -469,21 +381,20 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         }
     }
     // interaction list: 36 candidates (children of the parent's 9 near-set
-    // boxes), compacted with a ballot so every group gets one entry per round
+    // boxes), compacted with a ballot
     __shared__ int sIL[36];
-    __shared__ signed char sDx[36], sDy[36];
+    __shared__ signed char sTo[36];
+    const T log2r = (T)log(2.0 * r);
     {
         bool valid = false;
-        int d = -1;
-        long long dx = 0, dy = 0;
+        int d = -1, o = 0;
         if (lane < 36) {
             const int sl = lane >> 2, q = lane & 3;
-            const int c = sPN[sl];
-            if (c >= 0 && tv.lvl[c] == l - 1 && tv.child[c] >= 0) {
+            if (sPN[sl] >= 0 && sPL[sl] == l - 1 && sPC[sl] >= 0) {
                 const long long ppx = (ti >> 1) + (sl % 3) - 1, ppy = (tj >> 1) + (sl / 3) - 1;
-                d = tv.child[c] + q;
-                dx = 2 * ppx + (q & 1) - ti;
-                dy = 2 * ppy + (q >> 1) - tj;
+                d = sPC[sl] + q;
+                const int dx = (int)(2 * ppx + (q & 1) - ti), dy = (int)(2 * ppy + (q >> 1) - tj);
+                o = (dy + 3) * 7 + (dx + 3);
                 valid = !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) && tv.npc[d] > 0;
             }
         }
@@ -491,72 +402,160 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         if (valid) {
             const int at = __popcll(mask & ((1ULL << lane) - 1ULL));
             sIL[at] = d;
-            sDx[at] = (signed char)dx;
-            sDy[at] = (signed char)dy;
+            sTo[at] = (signed char)o;
         }
         __syncthreads();
         const int nIL = __popcll(mask);
-        const double log2r = log(2.0 * r);
-        cpx<T> gacc[3] = {{0, 0}, {0, 0}, {0, 0}};
+        // Source coefficients of each round's ngrp entries are staged in LDS
+        // by the whole wave (coalesced), double-buffered: the loads of round
+        // b+1 are in flight while round b is computed.
+        const int per_round = ngrp * P1 * 3;  // complex values, <= 3 * kWave
+        cpx<T>* stage = reinterpret_cast<cpx<T>*>(sScratch);
+        constexpr int kPer = 3;
+        cpx<T> pre[kPer];
+        auto fetch = [&](int base) {
+            for (int t = 0; t < kPer; ++t) {
+                const int i = lane + t * kWave;
+                if (i < per_round) {
+                    const int g = i / (P1 * 3), off = i - g * (P1 * 3);
+                    const int e = base + g;
+                    pre[t] = e < nIL ? M[(size_t)sIL[e] * P1 * 3 + off] : cpx<T>{0, 0};
+                }
+            }
+        };
+        auto put = [&](int buf) {
+            for (int t = 0; t < kPer; ++t) {
+                const int i = lane + t * kWave;
+                if (i < per_round) stage[buf * per_round + i] = pre[t];
+            }
+        };
+        if (nIL > 0) {
+            fetch(0);
+            put(0);
+        }
+        int buf = 0;
         for (int base = 0; base < nIL; base += ngrp) {
+            __syncthreads();
+            const bool next = base + ngrp < nIL;
+            if (next) fetch(base + ngrp);
             const int e = base + grp;
-            if (!glane || e >= nIL) continue;
-            // c_target - c_source = -(dx, dy) * 2r
-            const double ddx = -(double)sDx[e], ddy = -(double)sDy[e];
-            const double n2 = ddx * ddx + ddy * ddy;
-            const double inv = 0.5 / n2;
-            const cpx<T> w = {(T)(ddx * inv), (T)(-ddy * inv)};  // r / d
-            const cpx<T> logd = {(T)(log2r + 0.5 * log(n2)), (T)atan2(ddy, ddx)};
-            m2l_lane<T>(gacc, M + (size_t)sIL[e] * P1 * 3, p, k, w, logd);
+            if (glane && e < nIL) {
+                const cpx<T>* src = stage + buf * per_round + grp * P1 * 3;
+                const cpx<T>* Tk = Ttab + ((size_t)sTo[e] * P1 + k) * P1;
+                for (int m = 0; m <= p; ++m) {
+                    const cpx<T> t = Tk[m];
+                    for (int ch = 0; ch < 3; ++ch)
+                        gacc[ch] = cadd(gacc[ch], cmul(t, src[m * 3 + ch]));
+                }
+                if (k == 0)
+                    for (int ch = 0; ch < 3; ++ch)
+                        gacc[ch] = csub(gacc[ch], cscale(src[ch], log2r));
+            }
+            if (next) put(buf ^ 1);
+            buf ^= 1;
         }
         if (dl.stats && lane == 0) atomicAdd(dl.stats + kStatM2L, (unsigned long long)nIL);
-        // reduce the groups into group 0 (through the LDS the incoming-from-
-        // source pass reuses below)
-        cpx<T>(*sRed)[3] = reinterpret_cast<cpx<T>(*)[3]>(sScratch);
-        if (glane)
-            for (int ch = 0; ch < 3; ++ch) sRed[lane][ch] = gacc[ch];
-        __syncthreads();
-        if (klane)
-            for (int g = 0; g < ngrp; ++g)
-                for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], sRed[g * P1 + k][ch]);
         __syncthreads();
     }
-    // bigger separated list: coarser source leaves that do not touch us;
-    // their pieces are flattened into one list shared by the wave
+    // bigger separated list: coarser source leaves that do not touch us
     __shared__ int sL4[9], sPre[10], sNl4;
-    P2LPiece& sP2L = *reinterpret_cast<P2LPiece*>(sScratch);
     if (lane == 0) {
         int nl4 = 0;
         sPre[0] = 0;
         for (int s = 0; s < 9; ++s) {
             const int c = sPN[s];
-            if (c < 0 || (tv.lvl[c] == l - 1 && tv.child[c] >= 0)) continue;
+            if (c < 0 || (sPL[s] == l - 1 && sPC[s] >= 0)) continue;
             bool dup = false;
             for (int s2 = 0; s2 < s; ++s2) dup |= (sPN[s2] == c);
-            if (dup || tv.npc[c] == 0 || touches(tv, c, l, ti, tj)) continue;
+            if (dup || sPN2[s] == 0 || sPT[s]) continue;
             sL4[nl4] = c;
-            sPre[nl4 + 1] = sPre[nl4] + (tv.pend[c] - tv.pbeg[c]);
+            sPre[nl4 + 1] = sPre[nl4] + sPcnt[s];
             ++nl4;
         }
         sNl4 = nl4;
     }
     __syncthreads();
-    const int nl4 = sNl4;
-    if (nl4 > 0) {
-        // always in FP64: pieces of one leaf can carry large charges of both
-        // signs whose sum cancels (near-cusps), beyond FP32's reach
-        cpx<double> accd[3] = {{0, 0}, {0, 0}, {0, 0}};
-        p2l_wave<double>(accd, pv, tv, sL4, sPre, nl4, cx, cy, r, p, lane, sP2L);
-        for (int ch = 0; ch < 3; ++ch) {
-            acc[ch].re += (T)accd[ch].re;
-            acc[ch].im += (T)accd[ch].im;
+    const int nl4 = sNl4, total = sPre[nl4];
+    if (total > 0) {
+        P2LStage& sp = *reinterpret_cast<P2LStage*>(sScratch);
+        const double inv_r = 1.0 / r;
+        const T rr = (T)r, logr = (T)log(r);
+        const T* w = weights<T>(pv);
+        cpx<T> c01[2][3];  // this lane's k = 0, 1 terms, summed over its pieces
+        for (int ch = 0; ch < 3; ++ch) c01[0][ch] = c01[1][ch] = {0, 0};
+        for (int base = 0; base < total; base += kWave) {
+            // stage: one piece per lane
+            const int g = base + lane;
+            if (g < total) {
+                int u = 0;
+                while (u + 1 < nl4 && sPre[u + 1] <= g) ++u;
+                const int e = tv.pbeg[sL4[u]] + (g - sPre[u]);
+                const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
+                const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
+                const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
+                const T len = (T)pv.len[e];
+                const cpx<T> zA = cinv(A), zB = cinv(B);
+                const cpx<T> BA = cmul(B, cpx<T>{A.re, -A.im});
+                const T nA = A.re * A.re + A.im * A.im, nB = B.re * B.re + B.im * B.im;
+                const cpx<T> Lam = {T(0.5) * log(nB / nA), atan2(BA.im, BA.re)};
+                const cpx<T> lA = clog(A);
+                const cpx<T> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
+                const cpx<T> sv0 = {-(len * (logr + lA.re) + t2.re - len), -(len * lA.im + t2.im)};
+                const cpx<T> mv0 = {Lam.im, -Lam.re};
+                const cpx<T> sv1 = cmul(wbar, cscale(Lam, rr));
+                const cpx<T> d1 = csub(zB, zA);
+                const cpx<T> mv1 = {-d1.im, d1.re};
+                sp.zAr[lane] = zA.re;
+                sp.zAi[lane] = zA.im;
+                sp.zBr[lane] = zB.re;
+                sp.zBi[lane] = zB.im;
+                sp.wr[lane] = wbar.re;
+                sp.wi[lane] = wbar.im;
+                for (int ch = 0; ch < 3; ++ch) {
+                    const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
+                    sp.qs[ch][lane] = qs;
+                    sp.qm[ch][lane] = qm;
+                    c01[0][ch] = cadd(c01[0][ch], cadd(cscale(sv0, qs), cscale(mv0, qm)));
+                    c01[1][ch] = cadd(c01[1][ch], cadd(cscale(sv1, qs), cscale(mv1, qm)));
+                }
+            }
+            __syncthreads();
+            // k >= 2: the groups deal the staged pieces round-robin
+            const int n = min(kWave, total - base);
+            if (glane && k >= 2) {
+                const T sck = rr * recip<T>(k) * recip<T>(k - 1), rk = recip<T>(k);
+                for (int j = grp; j < n; j += ngrp) {
+                    const cpx<T> zA = {sp.zAr[j], sp.zAi[j]}, zB = {sp.zBr[j], sp.zBi[j]};
+                    const cpx<T> pa = cpow(zA, k - 1), pb = cpow(zB, k - 1);
+                    const cpx<T> sv = cmul(cpx<T>{sp.wr[j], sp.wi[j]}, cscale(csub(pa, pb), sck));
+                    const cpx<T> dd = cscale(csub(cmul(pb, zB), cmul(pa, zA)), rk);
+                    const cpx<T> mv = {-dd.im, dd.re};
+                    for (int ch = 0; ch < 3; ++ch)
+                        gacc[ch] = cadd(gacc[ch], cadd(cscale(sv, sp.qs[ch][j]),
+                                                       cscale(mv, sp.qm[ch][j])));
+                }
+            }
+            __syncthreads();
         }
+        // k = 0, 1 terms: summed over the wave
+        for (int kk = 0; kk < 2; ++kk)
+            for (int ch = 0; ch < 3; ++ch) {
+                const cpx<T> v = {wave_sum(c01[kk][ch].re), wave_sum(c01[kk][ch].im)};
+                if (klane && k == kk) acc[ch] = cadd(acc[ch], v);
+            }
     }
-    if (dl.stats && k == 0) {
-        atomicAdd(dl.stats + kStatP2L, (unsigned long long)sPre[nl4]);
+    if (dl.stats && lane == 0) {
+        atomicAdd(dl.stats + kStatP2L, (unsigned long long)total);
         atomicAdd(dl.stats + kStatL2L, 1ULL);
     }
+    // reduce the groups' shares into group 0
+    cpx<T>(*sRed)[3] = reinterpret_cast<cpx<T>(*)[3]>(sScratch);
+    if (glane)
+        for (int ch = 0; ch < 3; ++ch) sRed[lane][ch] = gacc[ch];
+    __syncthreads();
     if (!klane) return;
+    for (int g = 0; g < ngrp; ++g)
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], sRed[g * P1 + k][ch]);
     cpx<T>* out = L + ((size_t)own * P1 + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
 }
@@ -864,6 +863,93 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a0, int p, const cpx<double>* __restr
     }
 }
 
+// Exclusive prefix sum over the 64 lanes of a wave, and the wave total.
+__device__ inline int wave_excl_scan(int v, int lane, int& total) {
+    int x = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    total = __shfl(x, kWave - 1, kWave);
+    return x - v;
+}
+
+constexpr int kQCap = 512;   // traversal stack of the render leaf pass
+constexpr int kMaxLevels = 64;
+
+template <typename T, int NT>
+struct TileShared {
+    T px[NT], py[NT], tx[NT], ty[NT], len[NT];
+    T w[6][NT];
+    int pid[NT];
+    int U[kUCap], Upre[kUCap + 1], W[kWCap], Q[kQCap];
+    int nU, nW, nQ;
+};
+
+// Near-set traversal of a target tile by one wave (lane = lane of wave 0),
+// one round: pops boxes from the stack top in chunks of up to 64, sends
+// leaves to U (target-from-source), non-touching children of internal
+// boxes to W (target-from-outgoing) and pushes touching children.  Chunks
+// shrink to one box when the stack nears its capacity, so it never
+// overflows: from then on every push is a child of the box just popped,
+// which bounds the growth by 3 per level.  The round ends when the stack is
+// empty or U or W is full; the order is fixed by the tree alone.
+template <typename T, int NT>
+__device__ void tile_round(TileShared<T, NT>& sh, const TreeView& tv, int l, long long ti,
+                           long long tj, int lane) {
+    int size = sh.nQ, nU = 0, nW = 0;
+    for (;;) {
+        int chunk = size + 3 * kWave + 3 * kMaxLevels <= kQCap ? min(kWave, size) : min(1, size);
+        chunk = min(chunk, min(kUCap - nU, (kWCap - nW) / 4));
+        if (chunk <= 0) break;
+        const int b0 = size - chunk;
+        int c = -1, ch0 = -1, isU = 0, wm = 0, fm = 0;
+        if (lane < chunk) {
+            c = sh.Q[b0 + lane];
+            ch0 = tv.child[c];
+            if (ch0 < 0) {
+                isU = 1;
+            } else {
+                for (int q = 0; q < 4; ++q) {
+                    const int d = ch0 + q;
+                    if (tv.npc[d] == 0) continue;
+                    if (touches(tv, d, l, ti, tj)) fm |= 1 << q; else wm |= 1 << q;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long um = __ballot(isU);
+        if (isU) sh.U[nU + __popcll(um & ((1ULL << lane) - 1ULL))] = c;
+        int wtot, ftot;
+        int wp = nW + wave_excl_scan(__popc(wm), lane, wtot);
+        int fp = b0 + wave_excl_scan(__popc(fm), lane, ftot);
+        for (int q = 0; q < 4; ++q) {
+            if ((wm >> q) & 1) sh.W[wp++] = ch0 + q;
+            if ((fm >> q) & 1) sh.Q[fp++] = ch0 + q;
+        }
+        nU += __popcll(um);
+        nW += wtot;
+        size = b0 + ftot;
+        __builtin_amdgcn_wave_barrier();
+    }
+    // piece offsets of the U leaves
+    int run = 0;
+    for (int b = 0; b < nU; b += kWave) {
+        const int u = b + lane;
+        const int cnt = u < nU ? tv.pend[sh.U[u]] - tv.pbeg[sh.U[u]] : 0;
+        int tot;
+        const int ex = wave_excl_scan(cnt, lane, tot);
+        if (u < nU) sh.Upre[u] = run + ex;
+        run += tot;
+    }
+    if (lane == 0) {
+        sh.Upre[nU] = run;
+        sh.nU = nU;
+        sh.nW = nW;
+        sh.nQ = size;
+    }
+}
+
 // Hardware dispatch places block b on XCD b % 8; renumber blocks so that
 // each XCD receives one contiguous run of tiles (neighbouring tiles share
 // their near pieces, which then stay in that XCD's L2).
@@ -896,7 +982,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     a.W = v.W;
     a.H = v.H;
     a.out = v.out;
-    __shared__ LeafShared<T, NT> sh;
+    __shared__ TileShared<T, NT> sh;
     const int tid = threadIdx.x;
     const int l = a.L;
     const long long ti = a.i0 + blk % a.wl, tj = a.j0 + blk / a.wl;
@@ -952,48 +1038,27 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             if (l >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
             if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
         }
-        // near-set traversal, in rounds bounded by the list capacities
-        if (tid == 0) {
-            sh.nS = 0;
-            for (int s = 0; s < 9; ++s) {
-                const int c = nset[(size_t)own * 9 + s];
-                bool dup = c < 0;
-                for (int s2 = 0; s2 < s && !dup; ++s2) dup = nset[(size_t)own * 9 + s2] == c;
-                if (!dup && tv.npc[c] > 0) sh.stack[sh.nS++] = c;
+        // near-set traversal by wave 0, in rounds bounded by the list
+        // capacities; the stack starts with the distinct nonempty boxes of
+        // the near set
+        if (tid < kWave) {
+            int c = -1;
+            bool ok = false;
+            if (tid < 9) {
+                c = nset[(size_t)own * 9 + tid];
+                ok = c >= 0;
+                for (int s2 = 0; s2 < tid && ok; ++s2) ok = nset[(size_t)own * 9 + s2] != c;
+                ok = ok && tv.npc[c] > 0;
             }
+            const unsigned long long m = __ballot(ok);
+            if (ok) sh.Q[__popcll(m & ((1ULL << tid) - 1ULL))] = c;
+            if (tid == 0) sh.nQ = __popcll(m);
         }
         __syncthreads();
         for (;;) {
-            if (tid == 0) {
-                int nU = 0, nW = 0;
-                while (sh.nS > 0 && nU < kUCap && nW + 4 <= kWCap) {
-                    const int c = sh.stack[--sh.nS];
-                    if (tv.child[c] < 0) {
-                        sh.U[nU++] = c;
-                        continue;
-                    }
-                    for (int q = 0; q < 4; ++q) {
-                        const int d = tv.child[c] + q;
-                        if (tv.npc[d] == 0) continue;
-                        if (touches(tv, d, l, ti, tj)) {
-                            if (sh.nS < kSCap) sh.stack[sh.nS++] = d;
-                        } else {
-                            sh.W[nW++] = d;
-                        }
-                    }
-                }
-                int cum = 0;
-                for (int u = 0; u < nU; ++u) {
-                    sh.Upre[u] = cum;
-                    cum += tv.pend[sh.U[u]] - tv.pbeg[sh.U[u]];
-                }
-                sh.Upre[nU] = cum;
-                sh.nU = nU;
-                sh.nW = nW;
-                sh.more = sh.nS > 0;
-            }
+            if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
             __syncthreads();
-            const int nU = sh.nU, nW = sh.nW, more = sh.more;
+            const int nU = sh.nU, nW = sh.nW, more = sh.nQ > 0;
             if (a.stats && tid == 0) {
                 atomicAdd(a.stats + kStatM2P, (unsigned long long)n_here * nW);
                 atomicAdd(a.stats + kStatP2P, (unsigned long long)n_here * sh.Upre[nU]);
@@ -1182,6 +1247,50 @@ k_heavy_flags(int n, const double* __restrict__ len, const double* __restrict__ 
 // FP32 path (their FP32 rounding alone would approach the error budget).
 constexpr double kHeavyTau = 1.0;
 
+// Incoming-from-outgoing operators of the 7 x 7 box offsets (see k_down):
+// [o][k][m] complex, o = (dy + 3) * 7 + (dx + 3), (dx, dy) the source box's
+// offset in box widths, w = -1 / (2 (dx + i dy)).  Offsets inside the 3 x 3
+// neighbourhood are never used and stay zero.
+std::vector<double> m2l_table(int p) {
+    const int P1 = p + 1;
+    std::vector<double> t((size_t)49 * P1 * P1 * 2, 0.0);
+    for (int dy = -3; dy <= 3; ++dy)
+        for (int dx = -3; dx <= 3; ++dx) {
+            if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+            const std::complex<double> z(dx, dy);
+            const std::complex<double> w = -1.0 / (2.0 * z);
+            std::vector<std::complex<double>> pw(2 * P1);
+            pw[0] = 1.0;
+            for (int n = 1; n < 2 * P1; ++n) pw[n] = pw[n - 1] * w;
+            double* o = t.data() + (size_t)((dy + 3) * 7 + (dx + 3)) * P1 * P1 * 2;
+            for (int k = 0; k <= p; ++k) {
+                double coef = k == 0 ? 1.0 : 1.0 / k;  // c(k, m) for m = 0 (k > 0) or 1 (k = 0)
+                for (int m = 0; m <= p; ++m) {
+                    std::complex<double> v;
+                    if (k == 0 && m == 0) {
+                        v = -std::log(-z);
+                    } else {
+                        v = ((k & 1) ? -coef : coef) * pw[k + m];
+                        coef = coef * (double)(k + m) / (double)(m + 1);
+                    }
+                    o[((size_t)k * P1 + m) * 2] = v.real();
+                    o[((size_t)k * P1 + m) * 2 + 1] = v.imag();
+                }
+            }
+        }
+    return t;
+}
+
+const cpx<double>* m2l_table_dev(FmmState& f, int p) {
+    auto it = f.m2l_tab.find(p);
+    if (it == f.m2l_tab.end()) {
+        auto buf = std::make_unique<DevBuf<double>>();
+        buf->upload(m2l_table(p));
+        it = f.m2l_tab.emplace(p, std::move(buf)).first;
+    }
+    return reinterpret_cast<const cpx<double>*>(it->second->p);
+}
+
 // Piece weights and the upward pass for the given densities.  Expansions are
 // FP64 in both precision modes: on this hardware an FP64 FMA issues at the
 // rate of an unpacked FP32 one, and a leaf's coefficients are sums of charges
@@ -1231,6 +1340,7 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
     DevBuf<double>& M = f.M64;
+    const cpx<double>* Ttab = m2l_table_dev(f, p);
     hipLaunchKernelGGL(k_init_root<double>, dim3(1), dim3(kWave), 0, st, p, as_cpx(L), f.nsetS.p);
     DC_HIP(hipGetLastError());
     for (int l = 1; l <= f.depth; ++l) {
@@ -1241,7 +1351,7 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
         const int cnt = f.level_start[l + 1] - dl.first;
         if (cnt <= 0) continue;
         hipLaunchKernelGGL(k_down<double>, dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p, as_cpx(M),
-                           as_cpx(L), f.nsetS.p);
+                           as_cpx(L), f.nsetS.p, Ttab);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
@@ -1315,6 +1425,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
     const cpx<double>* M = as_cpx(f.M64);
+    const cpx<double>* Ttab = m2l_table_dev(f, p);
     if (timed) DC_HIP(hipEventRecord(f.ev[1], st));
     const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
     hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
@@ -1328,7 +1439,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         dl.vl = d_lev + pl.lev_begin[l];
         dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
         hipLaunchKernelGGL(k_down<double>, dim3(pl.lev_blocks[l]), dim3(kWave), 0, st, tv, pv,
-                           dl, p, M, TL, nset);
+                           dl, p, M, TL, nset, Ttab);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
@@ -1590,6 +1701,7 @@ void fmm_launch_render(dc_scene_s& s, const RenderPlan& pl, const dc_eval_opts& 
 
 void fmm_prepare(dc_scene_s& s, const dc_eval_opts& o, hipStream_t st) {
     FmmState& f = *s.fmm;
+    (void)m2l_table_dev(f, o.p);
     const int prec = o.precision == DC_PREC_F32 ? 4 : 8;
     if (!f.up_valid || f.up_p != o.p || f.up_prec != prec) {
         upward(s, f, s.d_sigma.p, s.d_mu.p, o.p, prec == 4, st);
