@@ -27,7 +27,11 @@ struct VpLeaf {
     long long i0, j0;
     double vcx, vcy, vw, vh;
     void* out;
-    int L, wl, off, W, H, first_block, pad;
+    int L, wl, off, W, H, first_block;
+    // offsets into the plan's edge table: pixel columns [E[col_at + i],
+    // E[col_at + i + 1]) lie in tile column i0 + i; pixel rows
+    // [E[row_at + j + 1], E[row_at + j]) in tile row j0 + j
+    int col_at, row_at;
 };
 
 // Pinned host staging for descriptor uploads: reused once the copy that
@@ -67,15 +71,17 @@ struct PinnedStage {
 
 // Host plan of one render of n viewports: per (viewport, level) rectangles
 // of target boxes, launch sizes and the layout of the render's device
-// scratch, [level table | leaf table | local coefficients | near sets].
+// scratch, [level table | leaf table | edge table | local coefficients |
+// near sets].
 struct RenderPlan {
     int n = 0, p = 0, tile_px = 0, maxL = 0;
     std::vector<VpLevel> lev;
     std::vector<int> lev_begin, lev_blocks;
     std::vector<VpLeaf> leaf;
+    std::vector<int> edges;  // pixel index ranges of tile columns and rows
     int leaf_blocks = 0;
     long long total_boxes = 0;
-    size_t leaf_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0, scratch_bytes = 0;
+    size_t leaf_at = 0, edges_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0, scratch_bytes = 0;
     // Write both descriptor tables (desc_bytes) to host, with output
     // pointers outs[v].
     void write_tables(void* host, void* const* outs) const;

@@ -569,24 +569,18 @@ __global__ void k_init_root(int p, cpx<T>* __restrict__ L, int* __restrict__ nse
 
 // -------------------------------------------------------------- leaf pass
 struct LeafArgs {
-    int solve;
-    int L;                   // target leaf level
-    // render
-    long long i0, j0;
-    int wl, off;
-    double vcx, vcy, vw, vh;
-    int W, H;
-    int out_f64;
-    void* out;
-    // solve
+    // render (k_tile)
+    const VpLeaf* vleaf;     // one entry per viewport
+    int nvleaf;
+    const int* edges;        // pixel ranges of tile columns and rows
+    int out_f64;             // images in FP64 (else FP32)
+    // solve (k_leaf)
     const int* target_leaves;
     const double *node_x, *node_y;
     double* y;
     int N;
     double near2;            // (near_fp64)^2, FP32 only
     unsigned long long* stats;  // optional work counters
-    const VpLeaf* vleaf;     // render: one entry per viewport
-    int nvleaf;
 };
 
 template <typename T, int NT>
@@ -598,72 +592,20 @@ struct LeafShared {
     int nU, nW, nS, more;
 };
 
-__device__ inline int first_true_col(const LeafArgs& a, double X0, double sideL, long long ti) {
-    int lo = 0, hi = a.W;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cell_coord(pixel_x(a.vcx, a.vw, a.W, mid), X0, sideL) >= ti) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
-__device__ inline int first_true_row(const LeafArgs& a, double Y0, double sideL, long long tj) {
-    int lo = 0, hi = a.H;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cell_coord(pixel_y(a.vcy, a.vh, a.H, mid), Y0, sideL) <= tj) hi = mid; else lo = mid + 1;
-    }
-    return lo;
-}
-
+// Solve leaf pass (Alg. 8 at the source leaves): targets are the
+// collocation nodes of each leaf holding nodes; y[3][N] receives the
+// representation at the nodes (before the self-segment correction).
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
-k_leaf(TreeView tv, PieceView pv, LeafArgs a0, int p, const cpx<double>* __restrict__ M,
+k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
-    LeafArgs a = a0;
-    int blk = (int)blockIdx.x;
-    if (!a.solve) {  // take this block's viewport from the batch table
-        const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
-        blk -= v.first_block;
-        a.L = v.L;
-        a.i0 = v.i0;
-        a.j0 = v.j0;
-        a.wl = v.wl;
-        a.off = v.off;
-        a.vcx = v.vcx;
-        a.vcy = v.vcy;
-        a.vw = v.vw;
-        a.vh = v.vh;
-        a.W = v.W;
-        a.H = v.H;
-        a.out = v.out;
-    }
     __shared__ LeafShared<T, NT> sh;
     const int tid = threadIdx.x;
-    long long ti, tj;
-    int own;
-    int n_targets, base_pos = 0;
-    int k_lo = 0, nx = 1, r_lo = 0;
-    const int Lv = a.L;
-    if (a.solve) {
-        own = a.target_leaves[blockIdx.x];
-        ti = tv.ix[own];
-        tj = tv.iy[own];
-        base_pos = tv.nbeg[own];
-        n_targets = tv.nend[own] - base_pos;
-    } else {
-        const int b = blk;
-        ti = a.i0 + b % a.wl;
-        tj = a.j0 + b / a.wl;
-        own = a.off + b;
-        const double sideL = ldexp(tv.side, -Lv);
-        k_lo = first_true_col(a, tv.X0, sideL, ti);
-        const int k_hi = first_true_col(a, tv.X0, sideL, ti + 1);
-        r_lo = first_true_row(a, tv.Y0, sideL, tj);
-        const int r_hi = first_true_row(a, tv.Y0, sideL, tj - 1);
-        nx = k_hi - k_lo;
-        n_targets = nx > 0 ? nx * max(r_hi - r_lo, 0) : 0;
-    }
-    const int l = a.solve ? tv.lvl[own] : Lv;
+    const int own = a.target_leaves[blockIdx.x];
+    const long long ti = tv.ix[own], tj = tv.iy[own];
+    const int base_pos = tv.nbeg[own];
+    const int n_targets = tv.nend[own] - base_pos;
+    const int l = tv.lvl[own];
     const double r = half_width(tv, l);
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
@@ -676,17 +618,10 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a0, int p, const cpx<double>* __restr
         double x = cx, y = cy;
         int out_idx = 0;
         if (active) {
-            if (a.solve) {
-                const int node = tv.node_perm[base_pos + tgt];
-                x = a.node_x[node];
-                y = a.node_y[node];
-                out_idx = node;
-            } else {
-                const int col = k_lo + tgt % nx, row = r_lo + tgt / nx;
-                x = pixel_x(a.vcx, a.vw, a.W, col);
-                y = pixel_y(a.vcy, a.vh, a.H, row);
-                out_idx = row * a.W + col;
-            }
+            const int node = tv.node_perm[base_pos + tgt];
+            x = a.node_x[node];
+            y = a.node_y[node];
+            out_idx = node;
         }
         const T xr = (T)(x - cx), yr = (T)(y - cy);
         double accE[3] = {0, 0, 0};
@@ -849,14 +784,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a0, int p, const cpx<double>* __restr
         }
         if (active) {
             for (int ch = 0; ch < 3; ++ch) {
-                const double u = (accE[ch] - accP[ch] - acc64[ch]) / kTwoPi;
-                if (a.solve) {
-                    a.y[(size_t)ch * a.N + out_idx] = u;
-                } else if (a.out_f64) {
-                    static_cast<double*>(a.out)[(size_t)out_idx * 3 + ch] = u;
-                } else {
-                    static_cast<float*>(a.out)[(size_t)out_idx * 3 + ch] = (float)u;
-                }
+                a.y[(size_t)ch * a.N + out_idx] = (accE[ch] - accP[ch] - acc64[ch]) / kTwoPi;
             }
         }
         __syncthreads();
@@ -964,34 +892,22 @@ __device__ inline int xcd_block(int b, int nb) {
 // gives every lane PX independent chains of the closed forms.  Same
 // arithmetic per (pixel, source) pair as k_leaf; targets are pixels only.
 template <typename T, int NT, int PX>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, 4)
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
     int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
     blk -= v.first_block;
-    a.L = v.L;
-    a.i0 = v.i0;
-    a.j0 = v.j0;
-    a.wl = v.wl;
-    a.off = v.off;
-    a.vcx = v.vcx;
-    a.vcy = v.vcy;
-    a.vw = v.vw;
-    a.vh = v.vh;
-    a.W = v.W;
-    a.H = v.H;
-    a.out = v.out;
     __shared__ TileShared<T, NT> sh;
     const int tid = threadIdx.x;
-    const int l = a.L;
-    const long long ti = a.i0 + blk % a.wl, tj = a.j0 + blk / a.wl;
-    const int own = a.off + blk;
-    const double sideL = ldexp(tv.side, -l);
-    const int k_lo = first_true_col(a, tv.X0, sideL, ti);
-    const int nx = first_true_col(a, tv.X0, sideL, ti + 1) - k_lo;
-    const int r_lo = first_true_row(a, tv.Y0, sideL, tj);
-    const int ny = max(first_true_row(a, tv.Y0, sideL, tj - 1) - r_lo, 0);
+    const int l = v.L;
+    const long long ti = v.i0 + blk % v.wl, tj = v.j0 + blk / v.wl;
+    const int own = v.off + blk;
+    const int ci = (int)(ti - v.i0), cj = (int)(tj - v.j0);
+    const int k_lo = a.edges[v.col_at + ci];
+    const int nx = a.edges[v.col_at + ci + 1] - k_lo;
+    const int r_lo = a.edges[v.row_at + cj + 1];
+    const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
     const int n_targets = nx > 0 ? nx * ny : 0;
     const double r = half_width(tv, l);
     double cx, cy;
@@ -1014,9 +930,9 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             out_idx[q] = 0;
             if (act[q]) {
                 const int col = k_lo + tgt % nx, row = r_lo + tgt / nx;
-                x[q] = pixel_x(a.vcx, a.vw, a.W, col);
-                y[q] = pixel_y(a.vcy, a.vh, a.H, row);
-                out_idx[q] = row * a.W + col;
+                x[q] = pixel_x(v.vcx, v.vw, v.W, col);
+                y[q] = pixel_y(v.vcy, v.vh, v.H, row);
+                out_idx[q] = row * v.W + col;
             }
             xr[q] = (T)(x[q] - cx);
             yr[q] = (T)(y[q] - cy);
@@ -1172,9 +1088,9 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             for (int ch = 0; ch < 3; ++ch) {
                 const double u = acc[q][ch] / kTwoPi;
                 if (a.out_f64)
-                    static_cast<double*>(a.out)[(size_t)out_idx[q] * 3 + ch] = u;
+                    static_cast<double*>(v.out)[(size_t)out_idx[q] * 3 + ch] = u;
                 else
-                    static_cast<float*>(a.out)[(size_t)out_idx[q] * 3 + ch] = (float)u;
+                    static_cast<float*>(v.out)[(size_t)out_idx[q] * 3 + ch] = (float)u;
             }
         }
         __syncthreads();
@@ -1355,7 +1271,6 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
-    a.solve = 1;
     a.target_leaves = f.target_leaves.p;
     a.node_x = s.node_x.p;
     a.node_y = s.node_y.p;
@@ -1443,12 +1358,12 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
-    a.solve = 0;
     a.out_f64 = out_dtype == DC_OUT_F64;
     a.near2 = o.near_fp64 * o.near_fp64;
     a.stats = stats;
     a.vleaf = d_leaf;
     a.nvleaf = pl.n;
+    a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
     if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
     // tiles of up to 9 x 9 pixels: one pixel per thread; up to 17 x 17: two
     if (o.tile_px <= 8)
@@ -1650,10 +1565,41 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.lev_begin[maxL + 1] = (int)pl.lev.size();
     pl.total_boxes = total;
     pl.leaf.assign(n, VpLeaf{});
+    pl.edges.clear();
     long long leaf_blocks = 0;
     for (int v = 0; v < n; ++v) {
         VpLeaf& e = pl.leaf[v];
         const int L = Lt[v];
+        // pixel ranges of the tile columns and rows, with the same pixel
+        // centres and cell rule as the rectangles above: each boundary is
+        // guessed from the geometry and settled by the exact rule (cells
+        // are monotone in the pixel index)
+        {
+            const dc_viewport& vp = vps[v];
+            const double sl = std::ldexp(f.side, -L);
+            const long long i0 = ri0[v][L], i1 = ri1[v][L], j0 = rj0[v][L], j1 = rj1[v][L];
+            auto ccol = [&](int k) { return cell_coord(pixel_x(vp.cx, vp.width, vp.W, k), f.X0, sl); };
+            auto crow = [&](int r) { return cell_coord(pixel_y(vp.cy, vp.height, vp.H, r), f.Y0, sl); };
+            const double px = vp.width / vp.W, py = vp.height / vp.H;
+            e.col_at = (int)pl.edges.size();
+            for (long long t = i0; t <= i1 + 1; ++t) {
+                // first column whose cell is >= t
+                double g = std::ceil((f.X0 + (double)t * sl - (vp.cx - 0.5 * vp.width)) / px - 0.5);
+                int k = (int)std::min<double>(std::max<double>(g, 0.0), (double)vp.W);
+                while (k > 0 && ccol(k - 1) >= t) --k;
+                while (k < vp.W && ccol(k) < t) ++k;
+                pl.edges.push_back(k);
+            }
+            e.row_at = (int)pl.edges.size();
+            for (long long t = j0 - 1; t <= j1; ++t) {
+                // first row whose cell is <= t (rows are numbered downwards)
+                double g = std::ceil(((vp.cy + 0.5 * vp.height) - (f.Y0 + (double)(t + 1) * sl)) / py - 0.5);
+                int r = (int)std::min<double>(std::max<double>(g, 0.0), (double)vp.H);
+                while (r > 0 && crow(r - 1) <= t) --r;
+                while (r < vp.H && crow(r) > t) ++r;
+                pl.edges.push_back(r);
+            }
+        }
         e.L = L;
         e.i0 = ri0[v][L];
         e.j0 = rj0[v][L];
@@ -1670,10 +1616,12 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
         leaf_blocks += (long long)e.wl * (rj1[v][L] - rj0[v][L] + 1);
     }
     pl.leaf_blocks = (int)leaf_blocks;
-    // scratch layout: [level table | leaf table | local coefficients | near sets]
+    // scratch layout: [level table | leaf table | edge table | local
+    // coefficients | near sets]
     auto up256 = [](size_t x) { return (x + 255) & ~size_t(255); };
     pl.leaf_at = up256(pl.lev.size() * sizeof(VpLevel));
-    pl.desc_bytes = pl.leaf_at + pl.leaf.size() * sizeof(VpLeaf);
+    pl.edges_at = up256(pl.leaf_at + pl.leaf.size() * sizeof(VpLeaf));
+    pl.desc_bytes = pl.edges_at + pl.edges.size() * sizeof(int);
     pl.tl_at = up256(pl.desc_bytes);
     pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
     pl.scratch_bytes = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
@@ -1687,6 +1635,7 @@ void RenderPlan::write_tables(void* host, void* const* outs) const {
         lf[v] = leaf[v];
         lf[v].out = outs[v];
     }
+    std::memcpy(h + edges_at, edges.data(), edges.size() * sizeof(int));
 }
 
 void fmm_launch_render(dc_scene_s& s, const RenderPlan& pl, const dc_eval_opts& o,
