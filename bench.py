@@ -34,6 +34,26 @@ PEAK_FP64 = 78.6e12
 FLOP_P2P = 117.0
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it covers another kernel or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_tile_c2_2048_traffic.txt")
+    src = os.path.join(ROOT, "paper_2311_14312_amd", "csrc", "fmm.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != sha:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def flops_l2p(p):
     return 6 * p + 12 * (p + 1)
 
@@ -427,6 +447,8 @@ def main():
 
     px = W * H
     err32, err64 = sample_err(img32), sample_err(img64)
+    kernel_name = ("k_tile<float, 64, 1, false>" if tile <= 8
+                   else "k_tile<float, 128, 2, false>")
     line = {
         "metric": METRIC,
         "value": px / (ms32 * 1e-3),
@@ -455,8 +477,9 @@ def main():
                                   "frac": achieved64 / PEAK_FP64}},
         "speedup_fp32_vs_fp64": ms64 / ms32,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_tile<float,64,1>" if tile <= 8 else "k_tile<float,128,2>",
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": measured_traffic(kernel_name), "traffic_unit": "bytes/launch",
+                     "kernel": kernel_name,
                      "kernel_ms": leaf_ms,
                      "flop_eq_per_launch": fl},
         "phases_ms": {k: v / max(1, tm["calls"]) for k, v in tm.items() if k.endswith("_ms")},

@@ -169,7 +169,9 @@ int dc_apply_operator(dc_scene s, const double* x_dev, double* y_dev,
 /* Alg. 4: u = FMM_G(Pi sigma) + FMM_F(Pi mu) at every pixel centre of vp,
  * written to out_dev ([H][W][3], FP32 or FP64 per out_dtype).  Needs
  * densities.  Every pixel centre must lie inside the quadtree root.
- * Asynchronous on stream. */
+ * Asynchronous on stream.  Renders of one scene share its device scratch:
+ * when they are issued on different streams the caller orders them (the
+ * server below has scratch of its own). */
 int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
               int out_dtype, void* out_dev, void* stream);
 

@@ -115,8 +115,12 @@ struct FmmState {
     int up_p = -1, up_prec = -1;
     // Render of the dc_render / dc_render_batch calls: plan, descriptor
     // staging and device scratch (see RenderPlan).
+    // The staging is a ring, so the host can plan the next render while the
+    // device still runs the previous ones.
     RenderPlan plan;
-    PinnedStage stage;
+    static constexpr int kStages = 3;
+    PinnedStage stage[kStages];
+    int stage_next = 0;
     DevBuf<char> scratch;
     // Optional device work counters (counting runs only) and phase timing.
     unsigned long long* stats = nullptr;

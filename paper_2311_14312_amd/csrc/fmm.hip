@@ -132,6 +132,26 @@ __device__ inline float atan2_poly(float y, float x) {
     return copysignf(r, y);
 }
 
+// The same without the guards for zero arguments, for the render's hot
+// loop: a zero argument occurs only for a target at a chord end point,
+// a near-singular pair whose result is discarded there.
+__device__ inline float atan2_poly_nz(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float t = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+    const float u = t * t;
+    float q = 8.00683815e-03f;
+    q = q * u - 3.74428146e-02f;
+    q = q * u + 8.43539238e-02f;
+    q = q * u - 1.35121688e-01f;
+    q = q * u + 1.98873192e-01f;
+    q = q * u - 3.33270133e-01f;
+    q = q * u + 9.99999404e-01f;
+    float r = t * q;
+    r = ay > ax ? 1.57079632679f - r : r;
+    r = x < 0.f ? 3.14159265359f - r : r;
+    return copysignf(r, y);
+}
+
 // Natural logarithm from the hardware log2 (v_log_f32).
 __device__ inline float fast_ln(float x) {
     return __builtin_amdgcn_logf(x) * 0.69314718056f;
@@ -164,6 +184,26 @@ __device__ inline void chord_fast(float xi1, float h, float xi2, float la, float
     const float l1p = fast_log1p(arg);
     const float tail = xo == 0.f ? 0.f : xo * 0.5f * l1p;
     il = la * 0.5f * fast_ln(big) + tail - la + h * th;
+}
+
+// chord_fast without its guards (see atan2_poly_nz): valid for pairs that
+// are neither near-singular nor heavy; other pairs may yield inf or NaN and
+// must be discarded by the caller.
+__device__ inline void chord_fast_nz(float xi1, float h, float xi2, float la, float& il,
+                                     float& th) {
+    const float hh = h * h;
+    const float r1 = xi1 * xi1 + hh;
+    const float r2 = xi2 * xi2 + hh;
+    th = atan2_poly_nz(h * la, hh + xi1 * xi2);
+    const float sm = la * (xi1 + xi2);  // r2^2 - r1^2
+    const bool one = r1 >= r2;
+    const float big = one ? r1 : r2;
+    const float xo = one ? xi2 : -xi1;
+    const float arg = (one ? sm : -sm) * __builtin_amdgcn_rcpf(big);
+    const float u = 1.0f + arg;
+    const float d = u - 1.0f;
+    const float l1p = d == 0.0f ? arg : fast_ln(u) * (arg * __builtin_amdgcn_rcpf(d));
+    il = la * 0.5f * fast_ln(big) + xo * 0.5f * l1p - la + h * th;
 }
 
 // ------------------------------------------------------------------ upward
@@ -291,7 +331,7 @@ struct P2LStage {
 // p+1 lanes; lane k of a group owns coefficient k.  M2L entries and P2L
 // pieces are dealt round-robin to the groups, whose sums are reduced into
 // group 0 at the end.
-template <typename T>
+template <typename T, bool Count>
 __global__ void __launch_bounds__(kWave, 4)
 k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
        cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab) {
@@ -454,7 +494,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             if (next) put(buf ^ 1);
             buf ^= 1;
         }
-        if (dl.stats && lane == 0) atomicAdd(dl.stats + kStatM2L, (unsigned long long)nIL);
+        if (Count && lane == 0) atomicAdd(dl.stats + kStatM2L, (unsigned long long)nIL);
         __syncthreads();
     }
     // bigger separated list: coarser source leaves that do not touch us
@@ -544,7 +584,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
                 if (klane && k == kk) acc[ch] = cadd(acc[ch], v);
             }
     }
-    if (dl.stats && lane == 0) {
+    if (Count && lane == 0) {
         atomicAdd(dl.stats + kStatP2L, (unsigned long long)total);
         atomicAdd(dl.stats + kStatL2L, 1ULL);
     }
@@ -891,7 +931,9 @@ __device__ inline int xcd_block(int b, int nb) {
 // piece staged in LDS is read once and evaluated against PX pixels, which
 // gives every lane PX independent chains of the closed forms.  Same
 // arithmetic per (pixel, source) pair as k_leaf; targets are pixels only.
-template <typename T, int NT, int PX>
+// Count: a counting instance (work counters on; a distinct kernel, so that
+// timed launches carry no counter code).
+template <typename T, int NT, int PX, bool Count>
 __global__ void __launch_bounds__(NT, 4)
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
@@ -950,7 +992,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             }
         }
         const int n_here = min(NT * PX, n_targets - tbase);
-        if (a.stats && tid == 0) {
+        if (Count && tid == 0) {
             if (l >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
             if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
         }
@@ -975,7 +1017,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
             __syncthreads();
             const int nU = sh.nU, nW = sh.nW, more = sh.nQ > 0;
-            if (a.stats && tid == 0) {
+            if (Count && tid == 0) {
                 atomicAdd(a.stats + kStatM2P, (unsigned long long)n_here * nW);
                 atomicAdd(a.stats + kStatP2P, (unsigned long long)n_here * sh.Upre[nU]);
             }
@@ -1056,14 +1098,14 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                         const float along = fmaxf(xi1, 0.f) + fmaxf(-xi2, 0.f);
                         slow[q] = along * along + h * h < lim || pid < 0;
                         any_slow |= slow[q] && act[q];
-                        chord_fast(xi1, h, xi2, fla, il[q], th[q]);
+                        chord_fast_nz(xi1, h, xi2, fla, il[q], th[q]);
                     }
                     float w6[6];
                     for (int c6 = 0; c6 < 6; ++c6) w6[c6] = (float)sh.w[c6][j];
                     for (int q = 0; q < PX; ++q)
                         for (int ch = 0; ch < 3; ++ch) {
                             const float t = il[q] * w6[ch] + th[q] * w6[3 + ch];
-                            acc[q][ch] -= slow[q] ? 0.0 : (double)t;
+                            acc[q][ch] -= (double)(slow[q] ? 0.f : t);
                         }
                     if (any_slow) {
                         const int e = pid < 0 ? -1 - pid : pid;
@@ -1075,7 +1117,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                             for (int ch = 0; ch < 3; ++ch)
                                 acc[q][ch] -= dil * pv.w64[(size_t)ch * pv.n + e] +
                                               dth * pv.w64[(size_t)(3 + ch) * pv.n + e];
-                            if (a.stats) atomicAdd(a.stats + kStatP2P64, 1ULL);
+                            if (Count) atomicAdd(a.stats + kStatP2P64, 1ULL);
                         }
                     }
                 }
@@ -1266,8 +1308,8 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
         dl.first = f.level_start[l];
         const int cnt = f.level_start[l + 1] - dl.first;
         if (cnt <= 0) continue;
-        hipLaunchKernelGGL(k_down<double>, dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p, as_cpx(M),
-                           as_cpx(L), f.nsetS.p, Ttab);
+        hipLaunchKernelGGL((k_down<double, false>), dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p,
+                           as_cpx(M), as_cpx(L), f.nsetS.p, Ttab);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
@@ -1353,8 +1395,12 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         dl.l = l;
         dl.vl = d_lev + pl.lev_begin[l];
         dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
-        hipLaunchKernelGGL(k_down<double>, dim3(pl.lev_blocks[l]), dim3(kWave), 0, st, tv, pv,
-                           dl, p, M, TL, nset, Ttab);
+        if (stats)
+            hipLaunchKernelGGL((k_down<double, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
+                               tv, pv, dl, p, M, TL, nset, Ttab);
+        else
+            hipLaunchKernelGGL((k_down<double, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
+                               tv, pv, dl, p, M, TL, nset, Ttab);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
@@ -1366,12 +1412,21 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
     if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
     // tiles of up to 9 x 9 pixels: one pixel per thread; up to 17 x 17: two
-    if (o.tile_px <= 8)
-        hipLaunchKernelGGL((k_tile<T, 64, 1>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv, pv, a,
-                           p, M, TL, nset);
-    else
-        hipLaunchKernelGGL((k_tile<T, 128, 2>), dim3(pl.leaf_blocks), dim3(128), 0, st, tv, pv,
-                           a, p, M, TL, nset);
+    if (o.tile_px <= 8) {
+        if (stats)
+            hipLaunchKernelGGL((k_tile<T, 64, 1, true>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv,
+                               pv, a, p, M, TL, nset);
+        else
+            hipLaunchKernelGGL((k_tile<T, 64, 1, false>), dim3(pl.leaf_blocks), dim3(64), 0, st,
+                               tv, pv, a, p, M, TL, nset);
+    } else {
+        if (stats)
+            hipLaunchKernelGGL((k_tile<T, 128, 2, true>), dim3(pl.leaf_blocks), dim3(128), 0, st,
+                               tv, pv, a, p, M, TL, nset);
+        else
+            hipLaunchKernelGGL((k_tile<T, 128, 2, false>), dim3(pl.leaf_blocks), dim3(128), 0, st,
+                               tv, pv, a, p, M, TL, nset);
+    }
     DC_HIP(hipGetLastError());
     if (timed) {
         DC_HIP(hipEventRecord(f.ev[3], st));
@@ -1671,7 +1726,9 @@ void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eva
     FmmState& f = *s.fmm;
     RenderPlan& pl = f.plan;
     plan_render(f, vps, n, o.tile_px, o.p, pl);
-    void* stage = f.stage.acquire(pl.desc_bytes);
+    PinnedStage& ps = f.stage[f.stage_next];
+    f.stage_next = (f.stage_next + 1) % FmmState::kStages;
+    void* stage = ps.acquire(pl.desc_bytes);
     pl.write_tables(stage, outs);
     if (f.scratch.n < pl.scratch_bytes) f.scratch.alloc(pl.scratch_bytes);
     if (o.precision == DC_PREC_F32)
@@ -1680,7 +1737,7 @@ void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eva
     else
         launch_render_t<double>(s, f, pl, o, out_dtype, f.scratch.p, stage, f.timing, f.stats,
                                 st);
-    f.stage.mark_used(st);
+    ps.mark_used(st);
 }
 
 }  // namespace dc

@@ -6,6 +6,7 @@ whatever else shares its batch), equal to dc_render of its viewport, and
 within the FP32 bar of the FP64 oracle.  Admission by device footprint is
 exercised with a budget that holds only a few images at once."""
 import threading
+import time
 
 import numpy as np
 import pytest
@@ -109,6 +110,25 @@ def test_admission_by_footprint(gpu_lib, scenes):
             srv.submit(ss[0], (0.5, 0.5, 1.0, 1.0, 2048, 2048))   # 48 MiB alone
         assert e.value.code == gpu_lib.DC_ERR_OOM
         vp = [(0.5, 0.5, 1.0, 1.0, 256, 256), (0.4, 0.6, 0.3, 0.3, 256, 256)]
+        # all submitted before any fetch: 16 images do not fit, so later
+        # requests must wait for fetched images to free the arena
+        tickets = [(srv.submit(ss[k % 3], vp[k % 2]), k) for k in range(16)]
+        # nothing is fetched yet: images accumulate until the arena is full
+        # and the oldest queued request has to wait
+        deadline = time.time() + 60
+        while srv.stats()["admission_waits"] == 0 and time.time() < deadline:
+            time.sleep(0.01)
+        st0 = srv.stats()
+        print("server stats (arena full)", st0, flush=True)
+        assert st0["admission_waits"] >= 1 and st0["completed"] < 16
+        for t, k in tickets:
+            info = srv.wait(t, timeout=120)
+            assert info is not None and info["status"] == 0
+            img = srv.fetch(t)
+            assert torch.equal(img, ss[k % 3].render(vp[k % 2], method="fmm", **EV))
+        st = srv.stats()
+        print("server stats (one client)", st, flush=True)
+        assert st["bytes_peak"] <= budget and st["bytes_in_use"] == 0
         results = {}
 
         def client(k):
@@ -124,10 +144,9 @@ def test_admission_by_footprint(gpu_lib, scenes):
         for x in th:
             x.join()
         st = srv.stats()
-        print("server stats", st, flush=True)
-        assert st["completed"] == 16 and st["fetched"] == 16
+        print("server stats (16 client threads)", st, flush=True)
+        assert st["completed"] == 32 and st["fetched"] == 32
         assert st["bytes_peak"] <= budget and st["bytes_in_use"] == 0
-        assert st["admission_waits"] >= 1
         for info, img, s, v in results.values():
             assert info["status"] == 0
             assert torch.equal(img, s.render(v, method="fmm", **EV))
