@@ -34,10 +34,10 @@ PEAK_FP64 = 78.6e12
 FLOP_P2P = 117.0
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, config):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when it covers another kernel or the kernel source has
-    changed since the counters were taken."""
+    summary, or None when it covers another kernel or configuration, or the
+    kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_tile_c2_2048_traffic.txt")
     src = os.path.join(ROOT, "paper_2311_14312_amd", "csrc", "fmm.hip")
@@ -49,7 +49,8 @@ def measured_traffic(kernel):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("kernel") != kernel or kv.get("source_sha256") != sha:
+    if kv.get("kernel") != kernel or kv.get("config") != config or \
+            kv.get("source_sha256") != sha:
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -313,11 +314,11 @@ def main():
                     help="expansion orders tried for the FP32 path (smallest meeting 5e-5)")
     ap.add_argument("--p64", type=int, default=20, help="expansion order, FP64 path")
     ap.add_argument("--tiles", default="8,16")
-    ap.add_argument("--leaves", default="16,32,64")
+    ap.add_argument("--leaves", default="4,8,16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-viewport batch")
     ap.add_argument("--batch-orders", default="10,12,14,16,18,20,24")
-    ap.add_argument("--batch-leaves", default="16,32")
+    ap.add_argument("--batch-leaves", default="4,8")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (reference "
@@ -478,7 +479,8 @@ def main():
         "speedup_fp32_vs_fp64": ms64 / ms32,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": measured_traffic(kernel_name), "traffic_unit": "bytes/launch",
+                     "traffic": measured_traffic(kernel_name, f"leaf {leaf}, tile {tile}, p {p32}"),
+                     "traffic_unit": "bytes/launch",
                      "kernel": kernel_name,
                      "kernel_ms": leaf_ms,
                      "flop_eq_per_launch": fl},

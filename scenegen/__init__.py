@@ -25,6 +25,7 @@ __all__ = [
     "Scene", "uniform_scene", "sized_scene", "clustered_scene",
     "zoom_viewports", "serving_scenes", "polygon_ctrl", "circle_ctrl",
     "bernstein_point", "batch_scene", "serving_requests", "poisson_arrivals",
+    "synthetic_densities",
     "TINY", "FMM", "PRECISION", "BATCH", "SERVING",
 ]
 
@@ -167,6 +168,15 @@ def serving_requests(scenes, n, seed=7, sides=(256, 512, 1024, 2048), zoom=(1.0,
         cx, cy = bernstein_point(ctrl[c], rng.uniform(0.0, 1.0))
         out.append((k, (float(cx), float(cy), 1.0 / z, 1.0 / z, side, side)))
     return out
+
+
+def synthetic_densities(n_nodes, phase=0.0):
+    """Smooth synthetic nodal densities [3][n_nodes] given by the node index
+    alone (nodes are numbered curve, panel, GL node): 0.5 cos(0.37 i + 1.3 c
+    + phase) for channel c.  Inputs for render and operator parity where a
+    dense solve is out of reach."""
+    i = np.arange(n_nodes, dtype=float)
+    return np.stack([0.5 * np.cos(0.37 * i + 1.3 * c + phase) for c in range(3)])
 
 
 def poisson_arrivals(n, rate, seed=11):
