@@ -106,6 +106,7 @@ struct FmmState {
     // Multipole and local coefficients of the source tree (FP64 in both
     // precision modes), and near sets.
     DevBuf<double> M64, L64;
+    DevBuf<double> Ms64;  // M64 with coefficient k divided by k (render M2P)
     // Tabulated incoming-from-outgoing operators per expansion order
     // (see m2l_table in fmm.hip).
     std::map<int, std::unique_ptr<DevBuf<double>>> m2l_tab;

@@ -935,7 +935,7 @@ __device__ inline int xcd_block(int b, int nb) {
 // timed launches carry no counter code).
 template <typename T, int NT, int PX, bool Count>
 __global__ void __launch_bounds__(NT, 4)
-k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
+k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
     int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
@@ -982,8 +982,9 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
         }
         // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
         if (l >= 2) {
+            const double ir = 1.0 / r;
             for (int q = 0; q < PX; ++q) {
-                const cpx<double> z = {(x[q] - cx) / r, (y[q] - cy) / r};
+                const cpx<double> z = {(x[q] - cx) * ir, (y[q] - cy) * ir};
                 for (int ch = 0; ch < 3; ++ch) {
                     cpx<double> s = loc[p * 3 + ch];
                     for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
@@ -1023,26 +1024,28 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             }
             // target-from-outgoing (Eq. t-f-o), scaled:
             //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
+            // with Ms_k = Mt_k / k precomputed; Mt_0 (the total charge times
+            // length) is real, so only log|x - c| is needed
             for (int u = 0; u < nW; ++u) {
                 const int d = sh.W[u];
                 const int ld = tv.lvl[d];
-                const double rd = half_width(tv, ld);
+                const double rd = half_width(tv, ld), ird = 1.0 / rd;
                 double dcx, dcy;
                 center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
                 const double lr = log(rd);
-                const cpx<double>* src = M + (size_t)d * (p + 1) * 3;
+                const cpx<double>* src = Ms + (size_t)d * (p + 1) * 3;
                 for (int q = 0; q < PX; ++q) {
                     if (!act[q]) continue;
-                    const cpx<double> rel = {(x[q] - dcx) / rd, (y[q] - dcy) / rd};
-                    const cpx<double> z = cinv(rel);
-                    const cpx<double> lg = clog(rel);
+                    const cpx<double> rel = {(x[q] - dcx) * ird, (y[q] - dcy) * ird};
+                    const double n2 = rel.re * rel.re + rel.im * rel.im;
+                    const double in2 = 1.0 / n2;
+                    const cpx<double> z = {rel.re * in2, -rel.im * in2};
+                    const double lgr = lr + 0.5 * log(n2);
                     for (int ch = 0; ch < 3; ++ch) {
-                        cpx<double> s = cscale(src[p * 3 + ch], recip<double>(p));
-                        for (int kk = p - 1; kk >= 1; --kk)
-                            s = cadd(cmul(s, z), cscale(src[kk * 3 + ch], recip<double>(kk)));
+                        cpx<double> s = src[p * 3 + ch];
+                        for (int kk = p - 1; kk >= 1; --kk) s = cadd(cmul(s, z), src[kk * 3 + ch]);
                         s = cmul(s, z);
-                        const cpx<double> m0 = src[ch];
-                        acc[q][ch] += s.re - ((lr + lg.re) * m0.re - lg.im * m0.im);
+                        acc[q][ch] += s.re - lgr * src[ch].re;
                     }
                 }
             }
@@ -1191,6 +1194,17 @@ cpx<T>* as_cpx(DevBuf<T>& b) {
     return reinterpret_cast<cpx<T>*>(b.p);
 }
 
+// Ms_k = Mt_k / k (k >= 1), Ms_0 = Mt_0: the multipoles as the render's
+// target-from-outgoing evaluation uses them.
+__global__ void __launch_bounds__(256)
+k_m2p_scale(int n, int P1, const cpx<double>* __restrict__ M, cpx<double>* __restrict__ Ms) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = (i / 3) % P1;
+    const cpx<double> m = M[i];
+    Ms[i] = k == 0 ? m : cscale(m, recip<double>(k));
+}
+
 __global__ void __launch_bounds__(256)
 k_heavy_flags(int n, const double* __restrict__ len, const double* __restrict__ w, double tau,
               int* __restrict__ heavy) {
@@ -1279,6 +1293,10 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
                            as_cpx(f.M64));
         DC_HIP(hipGetLastError());
     }
+    f.Ms64.alloc(nm);
+    hipLaunchKernelGGL(k_m2p_scale, dim3((unsigned)((nm / 2 + 255) / 256)), dim3(256), 0, st,
+                       (int)(nm / 2), p + 1, as_cpx(f.M64), as_cpx(f.Ms64));
+    DC_HIP(hipGetLastError());
     if (want32) {
         hipLaunchKernelGGL(k_heavy_flags, dim3((f.n_pieces + 255) / 256), dim3(256), 0, st,
                            f.n_pieces, f.plen.p, f.w64.p, kHeavyTau, f.heavy.p);
@@ -1382,6 +1400,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
     const cpx<double>* M = as_cpx(f.M64);
+    const cpx<double>* Ms = as_cpx(f.Ms64);
     const cpx<double>* Ttab = m2l_table_dev(f, p);
     if (timed) DC_HIP(hipEventRecord(f.ev[1], st));
     const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
@@ -1415,17 +1434,17 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     if (o.tile_px <= 8) {
         if (stats)
             hipLaunchKernelGGL((k_tile<T, 64, 1, true>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv,
-                               pv, a, p, M, TL, nset);
+                               pv, a, p, Ms, TL, nset);
         else
             hipLaunchKernelGGL((k_tile<T, 64, 1, false>), dim3(pl.leaf_blocks), dim3(64), 0, st,
-                               tv, pv, a, p, M, TL, nset);
+                               tv, pv, a, p, Ms, TL, nset);
     } else {
         if (stats)
             hipLaunchKernelGGL((k_tile<T, 128, 2, true>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                               tv, pv, a, p, M, TL, nset);
+                               tv, pv, a, p, Ms, TL, nset);
         else
             hipLaunchKernelGGL((k_tile<T, 128, 2, false>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                               tv, pv, a, p, M, TL, nset);
+                               tv, pv, a, p, Ms, TL, nset);
     }
     DC_HIP(hipGetLastError());
     if (timed) {
