@@ -204,6 +204,70 @@ def batch_bench(args, torch, dcfmm):
     }
 
 
+def precision_bench(args, torch, dcfmm):
+    """The precision workload: 2,000 blob curves plus 20 long curves, 32
+    panels x 16 GL nodes (N = 1,034,240), 4096 x 4096 render, FP32 path vs
+    plain FP64 FMM, max and RMS error against stored oracle values at 5,120
+    sampled pixels (synthetic densities: no dense solve exists at this
+    size)."""
+    cfg = scenegen.PRECISION
+    gold_path = os.path.join(ROOT, "tests", "golden", "c3_golden.npz")
+    gold = np.load(gold_path) if os.path.exists(gold_path) else None
+    sc = scenegen.clustered_scene(seed=cfg["seed"], panels=cfg["panels"], gl=cfg["gl"],
+                                  segs=cfg["segs"])
+    t0 = time.time()
+    scn = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"], gl=cfg["gl"],
+                      segs=cfg["segs"], leaf_max=args.precision_leaf)
+    t_create = time.time() - t0
+    scn.set_densities(scenegen.synthetic_densities(scn.N))
+    vp = cfg["viewport"]
+    W, H = vp[4], vp[5]
+
+    def timed(ev, dtype, steps):
+        out = torch.empty((H, W, 3), device="cuda", dtype=dtype)
+        scn.render(vp, out=out, **ev)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            scn.render(vp, out=out, **ev)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps, out
+
+    def errs(img):
+        if gold is None:
+            return None, None
+        d = img.cpu().numpy()[gold["rows"], gold["cols"]] - gold["vals"]
+        return float(np.abs(d).max()), float(np.sqrt(np.mean(d * d)))
+
+    res = {}
+    for name, ev, dtype in (
+            ("fp32", dict(method="fmm", precision="f32", p=args.precision_p32, tile_px=8),
+             torch.float32),
+            ("fp64", dict(method="fmm", precision="f64", p=args.p64, tile_px=8), torch.float64)):
+        ms, img = timed(ev, dtype, 3)
+        mx, rms = errs(img)
+        del img
+        res[name] = {"value": W * H / (ms * 1e-3), "unit": "RGB pixels/s", "ms": ms,
+                     "p": ev["p"], "max_err_vs_oracle": mx, "rms_err_vs_oracle": rms}
+        print("precision", name, res[name], flush=True)
+    info = scn.info()
+    scn.close()
+    return {
+        "workload": "2,000 curves in 5 Gaussian blobs (sigma 0.05, lengths 0.005-0.1) + 20 "
+                    "long curves, 32 panels x 16 GL nodes (1,034,240 nodes, 5,171,200 "
+                    "segments), 4096x4096 render of [0,1]^2, synthetic densities",
+        "leaf_max": args.precision_leaf, "tile_px": 8, "scene_create_s": t_create,
+        "n_pieces": info["n_pieces"], "n_cells": info["n_cells"],
+        "err_sample": None if gold is None else f"{len(gold['vals'])} oracle pixels (64x64 "
+                                                "stride-64 grid + 1,024 near-chord)",
+        **res,
+        "speedup_fp32_vs_fp64": res["fp64"]["ms"] / res["fp32"]["ms"],
+    }
+
+
 def serving_bench(args, torch, dcfmm):
     """16 resident scenes of 10..5000 curves; requests of 256..2048 px a side
     at zoom 1..1e6 on curve points.  Capacity is measured with a burst of
@@ -320,6 +384,10 @@ def main():
     ap.add_argument("--batch-orders", default="10,12,14,16,18,20,24")
     ap.add_argument("--batch-leaves", default="4,8")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 1M-node 4096^2 precision workload")
+    ap.add_argument("--precision-leaf", type=int, default=8)
+    ap.add_argument("--precision-p32", type=int, default=12)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (reference "
                          "for hardware byte counters)")
@@ -499,6 +567,8 @@ def main():
         scn.close()
     if not args.no_batch:
         line["batch"] = batch_bench(args, torch, dcfmm)
+    if not args.no_precision:
+        line["precision"] = precision_bench(args, torch, dcfmm)
     if not args.no_serving:
         line["serving"] = serving_bench(args, torch, dcfmm)
     print(json.dumps(line), flush=True)

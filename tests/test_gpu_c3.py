@@ -1,0 +1,71 @@
+"""Full-size parity on the precision workload: 2,000 curves in five
+Gaussian blobs plus 20 long curves, 32 panels x 16 GL nodes per curve
+(N = 1,034,240 nodes, S = 5,171,200 segments), 4096 x 4096 render.
+
+A dense solve of this size is out of reach for the oracle, so the render is
+checked with the synthetic densities of scenegen.synthetic_densities (and
+mu from the scene's colours) at 5,120 sampled pixels, and the solve's
+operator at 256 sampled nodes; both against stored FP64 oracle values
+(tests/golden/make_c3_golden.py, which calls only the oracle).  Max and RMS
+errors are printed for the FP32 and FP64 paths."""
+import os
+
+import numpy as np
+import pytest
+
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CFG = scenegen.PRECISION
+
+
+@pytest.fixture(scope="module")
+def c3(gpu_lib):
+    g = np.load(os.path.join(HERE, "golden", "c3_golden.npz"))
+    sc = scenegen.clustered_scene(seed=CFG["seed"], panels=CFG["panels"], gl=CFG["gl"],
+                                  segs=CFG["segs"])
+    s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=CFG["panels"],
+                      gl=CFG["gl"], segs=CFG["segs"], leaf_max=8)
+    print("C3 scene", s.info(), flush=True)
+    yield dict(s=s, g=g)
+    s.close()
+
+
+def _errs(img, g):
+    d = img[g["rows"], g["cols"]] - g["vals"]
+    return float(np.abs(d).max()), float(np.sqrt(np.mean(d * d)))
+
+
+def test_c3_operator_rows(c3):
+    import torch
+    s, g = c3["s"], c3["g"]
+    N = s.N
+    x = torch.tensor(scenegen.synthetic_densities(N, phase=0.7), device="cuda")
+    idx = torch.tensor(g["node_idx"], device="cuda")
+    y = s.apply_operator(x, method="fmm", p=24)[:, idx].cpu().numpy()
+    scale = np.abs(g["yG"]).max()
+    eG = np.abs(y - g["yG"]).max() / scale
+    zero = torch.zeros_like(x)
+    yf = s.apply_operator(zero, c_mu=1, method="fmm", p=24)[:, idx].cpu().numpy()
+    eF = np.abs(yf - g["yF"]).max() / max(1.0, np.abs(g["yF"]).max())
+    print(f"C3 operator rows: G rel {eG:.3e}  F {eF:.3e}", flush=True)
+    assert eG <= 1e-8
+    assert eF <= 1e-8
+
+
+def test_c3_render_fp32_and_fp64(c3):
+    import torch
+    s, g = c3["s"], c3["g"]
+    s.set_densities(scenegen.synthetic_densities(s.N))
+    vp = CFG["viewport"]
+    img32 = s.render(vp, method="fmm", precision="f32", p=12, tile_px=8).cpu().numpy()
+    m32, r32 = _errs(img32, g)
+    del img32
+    img64 = s.render(vp, out_dtype=torch.float64, method="fmm", p=30, tile_px=8).cpu().numpy()
+    m64, r64 = _errs(img64, g)
+    print(f"C3 render vs oracle: FP32 max {m32:.3e} rms {r32:.3e}; FP64 p=30 max {m64:.3e} "
+          f"rms {r64:.3e}", flush=True)
+    assert m32 <= 1e-4
+    assert m64 <= 1e-8
