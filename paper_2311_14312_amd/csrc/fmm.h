@@ -72,7 +72,7 @@ struct PinnedStage {
 // Host plan of one render of n viewports: per (viewport, level) rectangles
 // of target boxes, launch sizes and the layout of the render's device
 // scratch, [level table | leaf table | edge table | local coefficients |
-// near sets].
+// near sets | expansion owners].
 struct RenderPlan {
     int n = 0, p = 0, tile_px = 0, maxL = 0;
     std::vector<VpLevel> lev;
@@ -81,7 +81,8 @@ struct RenderPlan {
     std::vector<int> edges;  // pixel index ranges of tile columns and rows
     int leaf_blocks = 0;
     long long total_boxes = 0;
-    size_t leaf_at = 0, edges_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0, scratch_bytes = 0;
+    size_t leaf_at = 0, edges_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0, owner_at = 0;
+    size_t scratch_bytes = 0;
     // Write both descriptor tables (desc_bytes) to host, with output
     // pointers outs[v].
     void write_tables(void* host, void* const* outs) const;

@@ -334,7 +334,8 @@ struct P2LStage {
 template <typename T, bool Count>
 __global__ void __launch_bounds__(kWave, 4)
 k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
-       cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab) {
+       cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
+       int2* __restrict__ owner) {
     __shared__ int sPN[9];
     // LDS shared by the M2L staging, the P2L staging and the group reduction
     constexpr size_t kStageM2L = 2 * 3 * kWave * sizeof(cpx<T>);
@@ -393,6 +394,21 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
                 c = sPC[slot] + (int)(px & 1) + 2 * (int)(py & 1);
         }
         nset[(size_t)own * 9 + lane] = c;
+    }
+    // Render: a box whose parent's near set holds no pieces is quiet: it has
+    // no interaction list, no separated leaves and no near field, and so do
+    // its descendants; its local expansion is the nearest non-quiet
+    // ancestor's, which it records instead of translating it (the L2L
+    // translation of a truncated expansion is exact, so evaluating the
+    // ancestor's expansion at a pixel gives the same value).
+    if (owner != nullptr) {
+        bool quiet = true;
+        for (int s = 0; s < 9; ++s) quiet = quiet && (sPN[s] < 0 || sPN2[s] == 0);
+        if (quiet) {
+            if (lane == 0) owner[own] = owner[par];
+            return;
+        }
+        if (lane == 0) owner[own] = make_int2(own, l);
     }
     const int P1 = p + 1;
     const int ngrp = kWave / P1;
@@ -936,7 +952,8 @@ __device__ inline int xcd_block(int b, int nb) {
 template <typename T, int NT, int PX, bool Count>
 __global__ void __launch_bounds__(NT, 4)
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
-       const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
+       const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
+       const int2* __restrict__ owner) {
     int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
     blk -= v.first_block;
@@ -955,7 +972,15 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
     const T* wts = weights<T>(pv);
-    const cpx<double>* loc = Lc + (size_t)own * (p + 1) * 3;
+    // a quiet tile (see k_down) evaluates its owner's expansion and has no
+    // near field
+    const int2 ow = owner[own];
+    const bool quiet = ow.x != own;
+    const cpx<double>* loc = Lc + (size_t)ow.x * (p + 1) * 3;
+    const int lo = ow.y;
+    const double ro = half_width(tv, lo);
+    double ocx, ocy;
+    center_of(tv, lo, ti >> (l - lo), tj >> (l - lo), ocx, ocy);
 
     for (int tbase = 0; tbase < n_targets; tbase += NT * PX) {
         double x[PX], y[PX];
@@ -981,10 +1006,10 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
         }
         // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
-        if (l >= 2) {
-            const double ir = 1.0 / r;
+        if (lo >= 2) {
+            const double ir = 1.0 / ro;
             for (int q = 0; q < PX; ++q) {
-                const cpx<double> z = {(x[q] - cx) * ir, (y[q] - cy) * ir};
+                const cpx<double> z = {(x[q] - ocx) * ir, (y[q] - ocy) * ir};
                 for (int ch = 0; ch < 3; ++ch) {
                     cpx<double> s = loc[p * 3 + ch];
                     for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
@@ -994,9 +1019,10 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
         }
         const int n_here = min(NT * PX, n_targets - tbase);
         if (Count && tid == 0) {
-            if (l >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
+            if (lo >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
             if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
         }
+        if (quiet) goto store;
         // near-set traversal by wave 0, in rounds bounded by the list
         // capacities; the stack starts with the distinct nonempty boxes of
         // the near set
@@ -1128,6 +1154,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             __syncthreads();
             if (!more) break;
         }
+    store:
         for (int q = 0; q < PX; ++q) {
             if (!act[q]) continue;
             for (int ch = 0; ch < 3; ++ch) {
@@ -1327,7 +1354,7 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
         const int cnt = f.level_start[l + 1] - dl.first;
         if (cnt <= 0) continue;
         hipLaunchKernelGGL((k_down<double, false>), dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p,
-                           as_cpx(M), as_cpx(L), f.nsetS.p, Ttab);
+                           as_cpx(M), as_cpx(L), f.nsetS.p, Ttab, (int2*)nullptr);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
@@ -1365,11 +1392,13 @@ int tile_level(double side, const dc_viewport& vp, int tile_px) {
 }
 
 __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
-                             cpx<double>* __restrict__ L, int* __restrict__ nset) {
+                             cpx<double>* __restrict__ L, int* __restrict__ nset,
+                             int2* __restrict__ owner) {
     const int v = blockIdx.x;
     if (v >= n) return;
     const int own = roots[v].off;
     const int t = threadIdx.x;
+    if (t == 0) owner[own] = make_int2(own, 0);
     if (t < 9) nset[(size_t)own * 9 + t] = (t == 4) ? 0 : -1;
     for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[(size_t)own * (p + 1) * 3 + i] = {0, 0};
 }
@@ -1390,6 +1419,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     const VpLeaf* d_leaf = reinterpret_cast<const VpLeaf*>(scratch + pl.leaf_at);
     cpx<double>* TL = reinterpret_cast<cpx<double>*>(scratch + pl.tl_at);
     int* nset = reinterpret_cast<int*>(scratch + pl.nset_at);
+    int2* owner = reinterpret_cast<int2*>(scratch + pl.owner_at);
     if (timed) DC_HIP(hipEventRecord(f.ev[0], st));
     if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
         upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st);
@@ -1405,7 +1435,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     if (timed) DC_HIP(hipEventRecord(f.ev[1], st));
     const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
     hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
-                       nset);
+                       nset, owner);
     DC_HIP(hipGetLastError());
     for (int l = 1; l <= pl.maxL; ++l) {
         DownLevel dl{};
@@ -1416,10 +1446,10 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
         if (stats)
             hipLaunchKernelGGL((k_down<double, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
-                               tv, pv, dl, p, M, TL, nset, Ttab);
+                               tv, pv, dl, p, M, TL, nset, Ttab, owner);
         else
             hipLaunchKernelGGL((k_down<double, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
-                               tv, pv, dl, p, M, TL, nset, Ttab);
+                               tv, pv, dl, p, M, TL, nset, Ttab, owner);
         DC_HIP(hipGetLastError());
     }
     LeafArgs a{};
@@ -1434,17 +1464,17 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     if (o.tile_px <= 8) {
         if (stats)
             hipLaunchKernelGGL((k_tile<T, 64, 1, true>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv,
-                               pv, a, p, Ms, TL, nset);
+                               pv, a, p, Ms, TL, nset, owner);
         else
             hipLaunchKernelGGL((k_tile<T, 64, 1, false>), dim3(pl.leaf_blocks), dim3(64), 0, st,
-                               tv, pv, a, p, Ms, TL, nset);
+                               tv, pv, a, p, Ms, TL, nset, owner);
     } else {
         if (stats)
             hipLaunchKernelGGL((k_tile<T, 128, 2, true>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                               tv, pv, a, p, Ms, TL, nset);
+                               tv, pv, a, p, Ms, TL, nset, owner);
         else
             hipLaunchKernelGGL((k_tile<T, 128, 2, false>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                               tv, pv, a, p, Ms, TL, nset);
+                               tv, pv, a, p, Ms, TL, nset, owner);
     }
     DC_HIP(hipGetLastError());
     if (timed) {
@@ -1698,7 +1728,8 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.desc_bytes = pl.edges_at + pl.edges.size() * sizeof(int);
     pl.tl_at = up256(pl.desc_bytes);
     pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
-    pl.scratch_bytes = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
+    pl.owner_at = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
+    pl.scratch_bytes = up256(pl.owner_at + (size_t)total * sizeof(int2));
 }
 
 void RenderPlan::write_tables(void* host, void* const* outs) const {
