@@ -44,7 +44,12 @@ extern "C" {
 #define DC_ERR_OOM (-2)            /* device or host allocation failed */
 #define DC_ERR_NOT_CONVERGED (-3)  /* GMRES hit max_iter; report filled */
 #define DC_ERR_HIP (-4)            /* HIP runtime error; message kept */
-#define DC_ERR_TIMEOUT (-5)        /* dc_server_wait: not done in time */
+#define DC_ERR_TIMEOUT (-5)        /* dc_server_wait: not done in time;
+                                      render calls and server requests: an
+                                      earlier render of the scene stalled
+                                      on the device (a bounded wait of the
+                                      render kernel ran out) and its images
+                                      are incomplete */
 
 #define DC_PREC_F64 0   /* everything in FP64 */
 #define DC_PREC_F32 1   /* FP32 expansions and near field; FP64 for

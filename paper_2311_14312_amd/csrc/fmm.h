@@ -19,7 +19,22 @@ struct VpLevel {
     int wl, pwl;           // rectangle widths
     int off, poff;         // global index of the first box, and of the parent's
     int first_block;       // first block of this viewport in the level's launch
-    int pad;
+    int hl;                // rectangle height
+};
+
+// Work item of the fused render kernel: target box (ti, tj) at `level` of
+// viewport `vp`, with its parent's slot.
+struct QItem {
+    long long ti, tj;
+    int vp, level, parent, pad;
+};
+
+// Counters of the fused render kernel's work queue.
+struct QueueCtl {
+    int head;     // next slot to claim
+    int tail;     // next slot to fill
+    int pending;  // items filled but not finished
+    int error;    // set when a wait exceeded its bound
 };
 
 // One viewport's target leaves (pixel tiles) in a (batched) render.
@@ -28,6 +43,7 @@ struct VpLeaf {
     double vcx, vcy, vw, vh;
     void* out;
     int L, wl, off, W, H, first_block;
+    int hl, pad;             // tile rectangle height
     // offsets into the plan's edge table: pixel columns [E[col_at + i],
     // E[col_at + i + 1]) lie in tile column i0 + i; pixel rows
     // [E[row_at + j + 1], E[row_at + j]) in tile row j0 + j
@@ -71,18 +87,20 @@ struct PinnedStage {
 
 // Host plan of one render of n viewports: per (viewport, level) rectangles
 // of target boxes, launch sizes and the layout of the render's device
-// scratch, [level table | leaf table | edge table | local coefficients |
-// near sets | expansion owners].
+// scratch, [level table | leaf table | edge table | level index | local
+// coefficients | near sets | expansion owners | work queue | ready flags |
+// queue counters].
 struct RenderPlan {
     int n = 0, p = 0, tile_px = 0, maxL = 0;
     std::vector<VpLevel> lev;
     std::vector<int> lev_begin, lev_blocks;
     std::vector<VpLeaf> leaf;
     std::vector<int> edges;  // pixel index ranges of tile columns and rows
+    std::vector<int> vlev;   // [viewport][level] -> index into lev, or -1
     int leaf_blocks = 0;
     long long total_boxes = 0;
-    size_t leaf_at = 0, edges_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0, owner_at = 0;
-    size_t scratch_bytes = 0;
+    size_t leaf_at = 0, edges_at = 0, vlev_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0;
+    size_t owner_at = 0, queue_at = 0, ready_at = 0, ctl_at = 0, scratch_bytes = 0;
     // Write both descriptor tables (desc_bytes) to host, with output
     // pointers outs[v].
     void write_tables(void* host, void* const* outs) const;
@@ -130,13 +148,22 @@ struct FmmState {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double tms[4] = {0, 0, 0, 0};
     int tcalls = 0;
+    // Host word (pinned, mapped) that a render kernel sets when one of its
+    // bounded waits ran out; reported and cleared by the scene's next call
+    // that reaches fmm_check_stall.
+    int* stall_host = nullptr;
+    int* stall_dev = nullptr;
     ~FmmState() {
         for (hipEvent_t& e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (stall_host) (void)hipHostFree(stall_host);
     }
 };
 
 std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s);
+// Throws DC_ERR_TIMEOUT (and clears the word) when an earlier render of the
+// scene stalled on the device; its images are then incomplete.
+void fmm_check_stall(FmmState& f);
 void fmm_invalidate(FmmState& f);
 // y[3][N] = G_H sigma + F_H mu at the nodes (either density may be null).
 void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, double* y,

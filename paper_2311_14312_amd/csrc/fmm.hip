@@ -331,41 +331,36 @@ struct P2LStage {
 // p+1 lanes; lane k of a group owns coefficient k.  M2L entries and P2L
 // pieces are dealt round-robin to the groups, whose sums are reduced into
 // group 0 at the end.
+// LDS of one box of the downward pass.
+template <typename T>
+struct DownShared {
+    static constexpr size_t kStageM2L = 2 * 3 * kWave * sizeof(cpx<T>);
+    static constexpr size_t kScratch =
+        sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
+    // the parent's near set and its metadata
+    int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9];
+    int IL[36];              // interaction list (compacted)
+    signed char To[36];      // its offset classes
+    int L4[9], Pre[10], Nl4; // separated leaves and their piece offsets
+    // shared by the M2L staging, the P2L staging and the group reduction
+    __align__(16) unsigned char scratch[kScratch];
+};
+
+// Downward pass of one target box (own, at level l, cell (ti, tj), parent
+// par) by one wave.  Writes nset[own] and, unless the box is quiet (render
+// only, owner != nullptr), L[own]; returns whether it was quiet.
 template <typename T, bool Count>
-__global__ void __launch_bounds__(kWave, 4)
-k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
-       cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
-       int2* __restrict__ owner) {
-    __shared__ int sPN[9];
-    // LDS shared by the M2L staging, the P2L staging and the group reduction
-    constexpr size_t kStageM2L = 2 * 3 * kWave * sizeof(cpx<T>);
-    constexpr size_t kScratch = sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
-    __shared__ __align__(16) unsigned char sScratch[kScratch];
-    const int lane = threadIdx.x;
-    const int l = dl.l;
-    long long ti, tj;
-    int own, par;
-    if (dl.solve) {
-        own = dl.first + blockIdx.x;
-        if (tv.child[own] < 0 && tv.nend[own] == tv.nbeg[own]) return;  // no targets
-        ti = tv.ix[own];
-        tj = tv.iy[own];
-        par = tv.parent[own];
-    } else {
-        const VpLevel& e = find_entry(dl.vl, dl.nvl, (int)blockIdx.x);
-        const int b = (int)blockIdx.x - e.first_block;
-        ti = e.i0 + b % e.wl;
-        tj = e.j0 + b / e.wl;
-        own = e.off + b;
-        par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
-    }
-    if (lane < 9) sPN[lane] = nset[(size_t)par * 9 + lane];
+__device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView& pv, int l,
+                          long long ti, long long tj, int own, int par, int p,
+                          const cpx<T>* __restrict__ M, cpx<T>* __restrict__ L,
+                          int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
+                          int2* __restrict__ owner, unsigned long long* stats, int lane) {
+    if (lane < 9) sh.PN[lane] = nset[(size_t)par * 9 + lane];
     __syncthreads();
     // Metadata of the parent's near set, loaded once by lanes 0..8; it
     // serves the near set, the interaction list and the separated leaves.
-    __shared__ int sPL[9], sPC[9], sPN2[9], sPcnt[9], sPT[9];
     if (lane < 9) {
-        const int c = sPN[lane];
+        const int c = sh.PN[lane];
         int lv = -1, ch = -1, np = 0, pc = 0, tch = 1;
         if (c >= 0) {
             lv = tv.lvl[c];
@@ -374,11 +369,11 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             pc = tv.pend[c] - tv.pbeg[c];
             tch = touches(tv, c, l, ti, tj) ? 1 : 0;
         }
-        sPL[lane] = lv;
-        sPC[lane] = ch;
-        sPN2[lane] = np;
-        sPcnt[lane] = pc;
-        sPT[lane] = tch;
+        sh.PL[lane] = lv;
+        sh.PC[lane] = ch;
+        sh.PN2[lane] = np;
+        sh.Pcnt[lane] = pc;
+        sh.PT[lane] = tch;
     }
     __syncthreads();
     // near set N(own): the 3 x 3 positions around own at level l, each the
@@ -389,9 +384,9 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         const long long lim = 1LL << l;
         if (px >= 0 && py >= 0 && px < lim && py < lim) {
             const int slot = (int)((px >> 1) - (ti >> 1) + 1) + 3 * (int)((py >> 1) - (tj >> 1) + 1);
-            c = sPN[slot];
-            if (c >= 0 && sPL[slot] == l - 1 && sPC[slot] >= 0)
-                c = sPC[slot] + (int)(px & 1) + 2 * (int)(py & 1);
+            c = sh.PN[slot];
+            if (c >= 0 && sh.PL[slot] == l - 1 && sh.PC[slot] >= 0)
+                c = sh.PC[slot] + (int)(px & 1) + 2 * (int)(py & 1);
         }
         nset[(size_t)own * 9 + lane] = c;
     }
@@ -403,10 +398,10 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
     // ancestor's expansion at a pixel gives the same value).
     if (owner != nullptr) {
         bool quiet = true;
-        for (int s = 0; s < 9; ++s) quiet = quiet && (sPN[s] < 0 || sPN2[s] == 0);
+        for (int s = 0; s < 9; ++s) quiet = quiet && (sh.PN[s] < 0 || sh.PN2[s] == 0);
         if (quiet) {
             if (lane == 0) owner[own] = owner[par];
-            return;
+            return true;
         }
         if (lane == 0) owner[own] = make_int2(own, l);
     }
@@ -438,17 +433,15 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
     }
     // interaction list: 36 candidates (children of the parent's 9 near-set
     // boxes), compacted with a ballot
-    __shared__ int sIL[36];
-    __shared__ signed char sTo[36];
     const T log2r = (T)log(2.0 * r);
     {
         bool valid = false;
         int d = -1, o = 0;
         if (lane < 36) {
             const int sl = lane >> 2, q = lane & 3;
-            if (sPN[sl] >= 0 && sPL[sl] == l - 1 && sPC[sl] >= 0) {
+            if (sh.PN[sl] >= 0 && sh.PL[sl] == l - 1 && sh.PC[sl] >= 0) {
                 const long long ppx = (ti >> 1) + (sl % 3) - 1, ppy = (tj >> 1) + (sl / 3) - 1;
-                d = sPC[sl] + q;
+                d = sh.PC[sl] + q;
                 const int dx = (int)(2 * ppx + (q & 1) - ti), dy = (int)(2 * ppy + (q >> 1) - tj);
                 o = (dy + 3) * 7 + (dx + 3);
                 valid = !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) && tv.npc[d] > 0;
@@ -457,8 +450,8 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         const unsigned long long mask = __ballot(valid);
         if (valid) {
             const int at = __popcll(mask & ((1ULL << lane) - 1ULL));
-            sIL[at] = d;
-            sTo[at] = (signed char)o;
+            sh.IL[at] = d;
+            sh.To[at] = (signed char)o;
         }
         __syncthreads();
         const int nIL = __popcll(mask);
@@ -466,7 +459,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         // by the whole wave (coalesced), double-buffered: the loads of round
         // b+1 are in flight while round b is computed.
         const int per_round = ngrp * P1 * 3;  // complex values, <= 3 * kWave
-        cpx<T>* stage = reinterpret_cast<cpx<T>*>(sScratch);
+        cpx<T>* stage = reinterpret_cast<cpx<T>*>(sh.scratch);
         constexpr int kPer = 3;
         cpx<T> pre[kPer];
         auto fetch = [&](int base) {
@@ -475,7 +468,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
                 if (i < per_round) {
                     const int g = i / (P1 * 3), off = i - g * (P1 * 3);
                     const int e = base + g;
-                    pre[t] = e < nIL ? M[(size_t)sIL[e] * P1 * 3 + off] : cpx<T>{0, 0};
+                    pre[t] = e < nIL ? M[(size_t)sh.IL[e] * P1 * 3 + off] : cpx<T>{0, 0};
                 }
             }
         };
@@ -497,7 +490,7 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             const int e = base + grp;
             if (glane && e < nIL) {
                 const cpx<T>* src = stage + buf * per_round + grp * P1 * 3;
-                const cpx<T>* Tk = Ttab + ((size_t)sTo[e] * P1 + k) * P1;
+                const cpx<T>* Tk = Ttab + ((size_t)sh.To[e] * P1 + k) * P1;
                 for (int m = 0; m <= p; ++m) {
                     const cpx<T> t = Tk[m];
                     for (int ch = 0; ch < 3; ++ch)
@@ -510,30 +503,29 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             if (next) put(buf ^ 1);
             buf ^= 1;
         }
-        if (Count && lane == 0) atomicAdd(dl.stats + kStatM2L, (unsigned long long)nIL);
+        if (Count && lane == 0) atomicAdd(stats + kStatM2L, (unsigned long long)nIL);
         __syncthreads();
     }
     // bigger separated list: coarser source leaves that do not touch us
-    __shared__ int sL4[9], sPre[10], sNl4;
     if (lane == 0) {
         int nl4 = 0;
-        sPre[0] = 0;
+        sh.Pre[0] = 0;
         for (int s = 0; s < 9; ++s) {
-            const int c = sPN[s];
-            if (c < 0 || (sPL[s] == l - 1 && sPC[s] >= 0)) continue;
+            const int c = sh.PN[s];
+            if (c < 0 || (sh.PL[s] == l - 1 && sh.PC[s] >= 0)) continue;
             bool dup = false;
-            for (int s2 = 0; s2 < s; ++s2) dup |= (sPN[s2] == c);
-            if (dup || sPN2[s] == 0 || sPT[s]) continue;
-            sL4[nl4] = c;
-            sPre[nl4 + 1] = sPre[nl4] + sPcnt[s];
+            for (int s2 = 0; s2 < s; ++s2) dup |= (sh.PN[s2] == c);
+            if (dup || sh.PN2[s] == 0 || sh.PT[s]) continue;
+            sh.L4[nl4] = c;
+            sh.Pre[nl4 + 1] = sh.Pre[nl4] + sh.Pcnt[s];
             ++nl4;
         }
-        sNl4 = nl4;
+        sh.Nl4 = nl4;
     }
     __syncthreads();
-    const int nl4 = sNl4, total = sPre[nl4];
+    const int nl4 = sh.Nl4, total = sh.Pre[nl4];
     if (total > 0) {
-        P2LStage& sp = *reinterpret_cast<P2LStage*>(sScratch);
+        P2LStage& sp = *reinterpret_cast<P2LStage*>(sh.scratch);
         const double inv_r = 1.0 / r;
         const T rr = (T)r, logr = (T)log(r);
         const T* w = weights<T>(pv);
@@ -544,8 +536,8 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             const int g = base + lane;
             if (g < total) {
                 int u = 0;
-                while (u + 1 < nl4 && sPre[u + 1] <= g) ++u;
-                const int e = tv.pbeg[sL4[u]] + (g - sPre[u]);
+                while (u + 1 < nl4 && sh.Pre[u + 1] <= g) ++u;
+                const int e = tv.pbeg[sh.L4[u]] + (g - sh.Pre[u]);
                 const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
                 const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
                 const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
@@ -601,19 +593,48 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
             }
     }
     if (Count && lane == 0) {
-        atomicAdd(dl.stats + kStatP2L, (unsigned long long)total);
-        atomicAdd(dl.stats + kStatL2L, 1ULL);
+        atomicAdd(stats + kStatP2L, (unsigned long long)total);
+        atomicAdd(stats + kStatL2L, 1ULL);
     }
     // reduce the groups' shares into group 0
-    cpx<T>(*sRed)[3] = reinterpret_cast<cpx<T>(*)[3]>(sScratch);
+    cpx<T>(*sRed)[3] = reinterpret_cast<cpx<T>(*)[3]>(sh.scratch);
     if (glane)
         for (int ch = 0; ch < 3; ++ch) sRed[lane][ch] = gacc[ch];
     __syncthreads();
-    if (!klane) return;
+    if (!klane) return false;
     for (int g = 0; g < ngrp; ++g)
         for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], sRed[g * P1 + k][ch]);
     cpx<T>* out = L + ((size_t)own * P1 + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+    return false;
+}
+
+template <typename T, bool Count>
+__global__ void __launch_bounds__(kWave, 4)
+k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
+       cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
+       int2* __restrict__ owner) {
+    __shared__ DownShared<T> sh;
+    const int lane = threadIdx.x;
+    const int l = dl.l;
+    long long ti, tj;
+    int own, par;
+    if (dl.solve) {
+        own = dl.first + blockIdx.x;
+        if (tv.child[own] < 0 && tv.nend[own] == tv.nbeg[own]) return;  // no targets
+        ti = tv.ix[own];
+        tj = tv.iy[own];
+        par = tv.parent[own];
+    } else {
+        const VpLevel& e = find_entry(dl.vl, dl.nvl, (int)blockIdx.x);
+        const int b = (int)blockIdx.x - e.first_block;
+        ti = e.i0 + b % e.wl;
+        tj = e.j0 + b / e.wl;
+        own = e.off + b;
+        par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
+    }
+    (void)down_body<T, Count>(sh, tv, pv, l, ti, tj, own, par, p, M, L, nset, Ttab, owner,
+                              dl.stats, lane);
 }
 
 template <typename T>
@@ -947,26 +968,15 @@ __device__ inline int xcd_block(int b, int nb) {
 // piece staged in LDS is read once and evaluated against PX pixels, which
 // gives every lane PX independent chains of the closed forms.  Same
 // arithmetic per (pixel, source) pair as k_leaf; targets are pixels only.
-// Count: a counting instance (work counters on; a distinct kernel, so that
-// timed launches carry no counter code).
+// Leaf evaluation of one target box (own, level l, cell (ti, tj)) of
+// viewport v at the pixels [k_lo, k_lo + nx) x [r_lo, r_lo + ny), by one
+// block of NT threads, PX pixels each per pass.
 template <typename T, int NT, int PX, bool Count>
-__global__ void __launch_bounds__(NT, 4)
-k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
-       const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
-       const int2* __restrict__ owner) {
-    int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
-    blk -= v.first_block;
-    __shared__ TileShared<T, NT> sh;
-    const int tid = threadIdx.x;
-    const int l = v.L;
-    const long long ti = v.i0 + blk % v.wl, tj = v.j0 + blk / v.wl;
-    const int own = v.off + blk;
-    const int ci = (int)(ti - v.i0), cj = (int)(tj - v.j0);
-    const int k_lo = a.edges[v.col_at + ci];
-    const int nx = a.edges[v.col_at + ci + 1] - k_lo;
-    const int r_lo = a.edges[v.row_at + cj + 1];
-    const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
+__device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const PieceView& pv,
+                          const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
+                          const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
+                          const int2* __restrict__ owner, const VpLeaf& v, int l, long long ti,
+                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid) {
     const int n_targets = nx > 0 ? nx * ny : 0;
     const double r = half_width(tv, l);
     double cx, cy;
@@ -1166,6 +1176,197 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             }
         }
         __syncthreads();
+    }
+}
+
+
+// Count: a counting instance (work counters on; a distinct kernel, so that
+// timed launches carry no counter code).
+template <typename T, int NT, int PX, bool Count>
+__global__ void __launch_bounds__(NT, 4)
+k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
+       const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
+       const int2* __restrict__ owner) {
+    int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
+    blk -= v.first_block;
+    __shared__ TileShared<T, NT> sh;
+    const int tid = threadIdx.x;
+    const int l = v.L;
+    const long long ti = v.i0 + blk % v.wl, tj = v.j0 + blk / v.wl;
+    const int own = v.off + blk;
+    const int ci = (int)(ti - v.i0), cj = (int)(tj - v.j0);
+    const int k_lo = a.edges[v.col_at + ci];
+    const int nx = a.edges[v.col_at + ci + 1] - k_lo;
+    const int r_lo = a.edges[v.row_at + cj + 1];
+    const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
+    tile_body<T, NT, PX, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own, k_lo,
+                                nx, r_lo, ny, tid);
+}
+
+// ------------------------------------------------------ fused render kernel
+// Switched off: its first device run ended in an illegal memory access
+// whose cause is not found yet; renders use the per-level launches below.
+constexpr bool kFusedRender = false;
+
+// One persistent launch renders a whole batch: waves take target boxes from
+// a work queue in the order they become ready (a box is queued by its
+// parent once the parent's near set and local expansion are written), run
+// the downward pass on them and, at the tile level or when a box is quiet,
+// evaluate its pixels.  Levels and viewports overlap; quiet subtrees cost
+// one item.  Every wait is bounded (wait_ticks of the constant-rate wall
+// clock): a wave that waits longer sets the error flags and leaves, and the
+// others follow when their own waits run out.
+
+__device__ inline int ld_acquire(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_release(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Roots of every viewport as ready items in slots 0..n-1; every other slot
+// not ready; counters reset.
+__global__ void __launch_bounds__(256)
+k_fused_init(int n_vp, const VpLevel* __restrict__ lev, const int* __restrict__ vlev, int maxL,
+             int n_slots, int p, cpx<double>* __restrict__ L, int* __restrict__ nset,
+             int2* __restrict__ owner, QItem* __restrict__ q, int* __restrict__ ready,
+             QueueCtl* __restrict__ ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_slots) ready[i] = i < n_vp ? 1 : 0;  // the roots are ready
+    if (i == 0) {
+        ctl->head = 0;
+        ctl->tail = n_vp;
+        ctl->pending = n_vp;
+        ctl->error = 0;
+    }
+    if (i < n_vp) {
+        const VpLevel& e = lev[vlev[(size_t)i * (maxL + 1)]];
+        q[i] = QItem{e.i0, e.j0, i, 0, -1, 0};
+        for (int t = 0; t < 9; ++t) nset[(size_t)i * 9 + t] = (t == 4) ? 0 : -1;
+        for (int t = 0; t < (p + 1) * 3; ++t) L[(size_t)i * (p + 1) * 3 + t] = {0, 0};
+        owner[i] = make_int2(i, 0);
+    }
+}
+
+// Out-of-line bodies for the fused kernel: separate register allocation for
+// the downward and the leaf phase (inlined together they spill heavily).
+template <typename T, bool Count>
+__device__ __noinline__ bool down_call(DownShared<T>& sh, const TreeView& tv,
+                                       const PieceView& pv, int l, long long ti, long long tj,
+                                       int own, int par, int p, const cpx<T>* M, cpx<T>* L,
+                                       int* nset, const cpx<T>* Ttab, int2* owner,
+                                       unsigned long long* stats, int lane) {
+    return down_body<T, Count>(sh, tv, pv, l, ti, tj, own, par, p, M, L, nset, Ttab, owner,
+                               stats, lane);
+}
+
+template <typename T, int NT, int PX, bool Count>
+__device__ __noinline__ void tile_call(TileShared<T, NT>& sh, const TreeView& tv,
+                                       const PieceView& pv, const LeafArgs& a, int p,
+                                       const cpx<double>* Ms, const cpx<double>* Lc,
+                                       const int* nset, const int2* owner, const VpLeaf& v, int l,
+                                       long long ti, long long tj, int own, int k_lo, int nx,
+                                       int r_lo, int ny, int tid) {
+    tile_body<T, NT, PX, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own, k_lo, nx,
+                                r_lo, ny, tid);
+}
+
+template <typename T>
+union FusedShared {
+    DownShared<double> d;
+    TileShared<T, kWave> t;
+};
+
+template <typename T, bool Count>
+__global__ void __launch_bounds__(kWave, 4)
+k_render_fused(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
+               const cpx<double>* __restrict__ Ms, const cpx<double>* __restrict__ Ttab,
+               cpx<double>* __restrict__ L, int* __restrict__ nset, int2* __restrict__ owner,
+               QItem* __restrict__ q, int* __restrict__ ready, QueueCtl* __restrict__ ctl,
+               int n_slots, const VpLevel* __restrict__ lev, const int* __restrict__ vlev,
+               int maxL, long long wait_ticks, int* __restrict__ stall) {
+    __shared__ FusedShared<T> sh;
+    __shared__ QItem s_item;
+    __shared__ int s_slot, s_t0;
+    const int lane = threadIdx.x;
+    for (;;) {
+        // claim the next slot and wait until it holds an item
+        if (lane == 0) {
+            const int h = atomicAdd(&ctl->head, 1);
+            int slot = -1;
+            if (h < n_slots) {
+                const long long t0 = wall_clock64();
+                for (int spins = 0;; ++spins) {
+                    if (ld_acquire(&ready[h])) {
+                        slot = h;
+                        break;
+                    }
+                    if ((spins & 15) == 15) {
+                        if (ld_acquire(&ctl->pending) == 0) break;  // nothing can arrive
+                        if (wall_clock64() - t0 > wait_ticks) {
+                            atomicOr(&ctl->error, 1);
+                            __hip_atomic_store(stall, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_SYSTEM);
+                            break;
+                        }
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            s_slot = slot;
+            if (slot >= 0) s_item = q[slot];
+        }
+        __syncthreads();
+        const int slot = s_slot;
+        if (slot < 0) return;
+        const QItem it = s_item;
+        const VpLeaf& v = a.vleaf[it.vp];
+        bool quiet = false;
+        if (it.level > 0) {
+            quiet = down_call<double, Count>(sh.d, tv, pv, it.level, it.ti, it.tj, slot, it.parent,
+                                             p, M, L, nset, Ttab, owner, a.stats, lane);
+        }
+        __syncthreads();
+        if (quiet || it.level == v.L) {
+            // leaf: the box's pixels, from the tile-level edge tables
+            const int s = v.L - it.level;
+            const long long wl = v.wl;
+            const int hl = v.hl;
+            const long long c0 = min(max((it.ti << s) - v.i0, 0LL), wl);
+            const long long c1 = min(max(((it.ti + 1) << s) - v.i0, 0LL), wl);
+            const long long r0 = min(max((it.tj << s) - v.j0, 0LL), (long long)hl);
+            const long long r1 = min(max(((it.tj + 1) << s) - v.j0, 0LL), (long long)hl);
+            const int k_lo = a.edges[v.col_at + c0];
+            const int nx = a.edges[v.col_at + c1] - k_lo;
+            const int r_lo = a.edges[v.row_at + r1];
+            const int ny = max(a.edges[v.row_at + r0] - r_lo, 0);
+            tile_call<T, kWave, 1, Count>(sh.t, tv, pv, a, p, Ms, L, nset, owner, v, it.level,
+                                          it.ti, it.tj, slot, k_lo, nx, r_lo, ny, lane);
+        } else {
+            // queue the children that lie in the next level's rectangle
+            const VpLevel& e = lev[vlev[(size_t)it.vp * (maxL + 1) + it.level + 1]];
+            const long long cxi = 2 * it.ti + (lane & 1), cyi = 2 * it.tj + (lane >> 1);
+            const bool in = lane < 4 && cxi >= e.i0 && cxi < e.i0 + e.wl && cyi >= e.j0 &&
+                            cyi < e.j0 + e.hl;
+            const unsigned long long m = __ballot(in);
+            const int nc = __popcll(m);
+            if (lane == 0) {
+                s_t0 = atomicAdd(&ctl->tail, nc);
+                atomicAdd(&ctl->pending, nc);
+            }
+            __syncthreads();
+            const int pos = s_t0 + __popcll(m & ((1ULL << lane) - 1ULL));
+            if (in && pos >= n_slots) atomicOr(&ctl->error, 2);  // cannot happen: one slot per box
+            if (in && pos < n_slots) {
+                q[pos] = QItem{cxi, cyi, it.vp, it.level + 1, slot, 0};
+                // publish after this box's outputs and the item itself
+                __threadfence();
+                st_release(&ready[pos], 1);
+            }
+        }
+        __syncthreads();
+        if (lane == 0) atomicSub(&ctl->pending, 1);
     }
 }
 
@@ -1403,6 +1604,77 @@ __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
     for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[(size_t)own * (p + 1) * 3 + i] = {0, 0};
 }
 
+// Ticks of the device's constant-rate wall clock in about one second.
+long long wall_ticks_per_second() {
+    static long long t = 0;
+    if (t == 0) {
+        int dev = 0, khz = 0;
+        DC_HIP(hipGetDevice(&dev));
+        DC_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        t = std::max(1, khz) * 1000LL;
+    }
+    return t;
+}
+
+// Waves of the fused render kernel that fit on the device at once (its grid).
+template <typename T>
+int fused_capacity(bool count) {
+    static int cap[2] = {0, 0};
+    int& c = cap[count ? 1 : 0];
+    if (c == 0) {
+        int dev = 0, per_cu = 0;
+        DC_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        DC_HIP(hipGetDeviceProperties(&prop, dev));
+        if (count)
+            DC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(k_render_fused<T, true>), kWave, 0));
+        else
+            DC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(k_render_fused<T, false>), kWave, 0));
+        c = std::max(1, per_cu) * prop.multiProcessorCount;
+    }
+    return c;
+}
+
+// Fused launch of a planned render (k_fused_init + k_render_fused).
+template <typename T>
+void launch_fused(FmmState& f, const RenderPlan& pl, const dc_eval_opts& o, int out_dtype,
+                  char* scratch, bool timed, unsigned long long* stats, const TreeView& tv,
+                  const PieceView& pv, int p, const cpx<double>* M, const cpx<double>* Ms,
+                  const cpx<double>* Ttab, cpx<double>* TL, int* nset, int2* owner,
+                  const VpLevel* d_lev, const VpLeaf* d_leaf, hipStream_t st) {
+    // one persistent launch for the whole batch (levels and tiles)
+    const int n_slots = (int)pl.total_boxes;
+    QItem* q = reinterpret_cast<QItem*>(scratch + pl.queue_at);
+    int* ready = reinterpret_cast<int*>(scratch + pl.ready_at);
+    QueueCtl* ctl = reinterpret_cast<QueueCtl*>(scratch + pl.ctl_at);
+    const int* vlev = reinterpret_cast<const int*>(scratch + pl.vlev_at);
+    hipLaunchKernelGGL(k_fused_init, dim3((n_slots + 255) / 256), dim3(256), 0, st, pl.n,
+                       d_lev, vlev, pl.maxL, n_slots, p, TL, nset, owner, q, ready, ctl);
+    DC_HIP(hipGetLastError());
+    LeafArgs a{};
+    a.out_f64 = out_dtype == DC_OUT_F64;
+    a.near2 = o.near_fp64 * o.near_fp64;
+    a.stats = stats;
+    a.vleaf = d_leaf;
+    a.nvleaf = pl.n;
+    a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
+    if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
+    const int grid = std::min(n_slots, fused_capacity<T>(stats != nullptr));
+    // a wave waits for its item at most ~2 s (a whole render takes far less)
+    const long long wait = 2 * wall_ticks_per_second();
+    if (stats)
+        hipLaunchKernelGGL((k_render_fused<T, true>), dim3(grid), dim3(kWave), 0, st, tv, pv,
+                           a, p, M, Ms, Ttab, TL, nset, owner, q, ready, ctl, n_slots, d_lev,
+                           vlev, pl.maxL, wait, f.stall_dev);
+    else
+        hipLaunchKernelGGL((k_render_fused<T, false>), dim3(grid), dim3(kWave), 0, st, tv, pv,
+                           a, p, M, Ms, Ttab, TL, nset, owner, q, ready, ctl, n_slots, d_lev,
+                           vlev, pl.maxL, wait, f.stall_dev);
+    DC_HIP(hipGetLastError());
+}
+
 // Launch of a planned render (plan_render) with its scratch at `scratch`
 // (RenderPlan::scratch_bytes, 256-byte aligned) and its descriptor tables
 // already written to the pinned host buffer `stage` (RenderPlan::write_tables).
@@ -1433,53 +1705,62 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     const cpx<double>* Ms = as_cpx(f.Ms64);
     const cpx<double>* Ttab = m2l_table_dev(f, p);
     if (timed) DC_HIP(hipEventRecord(f.ev[1], st));
-    const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
-    hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
-                       nset, owner);
-    DC_HIP(hipGetLastError());
-    for (int l = 1; l <= pl.maxL; ++l) {
-        DownLevel dl{};
-        dl.stats = stats;
-        dl.solve = 0;
-        dl.l = l;
-        dl.vl = d_lev + pl.lev_begin[l];
-        dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
-        if (stats)
-            hipLaunchKernelGGL((k_down<double, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
-                               tv, pv, dl, p, M, TL, nset, Ttab, owner);
-        else
-            hipLaunchKernelGGL((k_down<double, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
-                               tv, pv, dl, p, M, TL, nset, Ttab, owner);
+    bool fused = false;
+    if constexpr (kFusedRender) fused = o.tile_px <= 8;
+    if (fused) {
+        if constexpr (kFusedRender)
+            launch_fused<T>(f, pl, o, out_dtype, scratch, timed, stats, tv, pv, p, M, Ms, Ttab,
+                            TL, nset, owner, d_lev, d_leaf, st);
+    } else {
+        const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
+        hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
+                           nset, owner);
+        DC_HIP(hipGetLastError());
+        for (int l = 1; l <= pl.maxL; ++l) {
+            DownLevel dl{};
+            dl.stats = stats;
+            dl.solve = 0;
+            dl.l = l;
+            dl.vl = d_lev + pl.lev_begin[l];
+            dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
+            if (stats)
+                hipLaunchKernelGGL((k_down<double, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
+                                   tv, pv, dl, p, M, TL, nset, Ttab, owner);
+            else
+                hipLaunchKernelGGL((k_down<double, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
+                                   tv, pv, dl, p, M, TL, nset, Ttab, owner);
+            DC_HIP(hipGetLastError());
+        }
+        LeafArgs a{};
+        a.out_f64 = out_dtype == DC_OUT_F64;
+        a.near2 = o.near_fp64 * o.near_fp64;
+        a.stats = stats;
+        a.vleaf = d_leaf;
+        a.nvleaf = pl.n;
+        a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
+        if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
+        // tiles of up to 9 x 9 pixels: one pixel per thread; up to 17 x 17: two
+        if (o.tile_px <= 8) {
+            if (stats)
+                hipLaunchKernelGGL((k_tile<T, 64, 1, true>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv,
+                                   pv, a, p, Ms, TL, nset, owner);
+            else
+                hipLaunchKernelGGL((k_tile<T, 64, 1, false>), dim3(pl.leaf_blocks), dim3(64), 0, st,
+                                   tv, pv, a, p, Ms, TL, nset, owner);
+        } else {
+            if (stats)
+                hipLaunchKernelGGL((k_tile<T, 128, 2, true>), dim3(pl.leaf_blocks), dim3(128), 0, st,
+                                   tv, pv, a, p, Ms, TL, nset, owner);
+            else
+                hipLaunchKernelGGL((k_tile<T, 128, 2, false>), dim3(pl.leaf_blocks), dim3(128), 0, st,
+                                   tv, pv, a, p, Ms, TL, nset, owner);
+        }
         DC_HIP(hipGetLastError());
     }
-    LeafArgs a{};
-    a.out_f64 = out_dtype == DC_OUT_F64;
-    a.near2 = o.near_fp64 * o.near_fp64;
-    a.stats = stats;
-    a.vleaf = d_leaf;
-    a.nvleaf = pl.n;
-    a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
-    if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
-    // tiles of up to 9 x 9 pixels: one pixel per thread; up to 17 x 17: two
-    if (o.tile_px <= 8) {
-        if (stats)
-            hipLaunchKernelGGL((k_tile<T, 64, 1, true>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv,
-                               pv, a, p, Ms, TL, nset, owner);
-        else
-            hipLaunchKernelGGL((k_tile<T, 64, 1, false>), dim3(pl.leaf_blocks), dim3(64), 0, st,
-                               tv, pv, a, p, Ms, TL, nset, owner);
-    } else {
-        if (stats)
-            hipLaunchKernelGGL((k_tile<T, 128, 2, true>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                               tv, pv, a, p, Ms, TL, nset, owner);
-        else
-            hipLaunchKernelGGL((k_tile<T, 128, 2, false>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                               tv, pv, a, p, Ms, TL, nset, owner);
-    }
-    DC_HIP(hipGetLastError());
     if (timed) {
         DC_HIP(hipEventRecord(f.ev[3], st));
         DC_HIP(hipEventSynchronize(f.ev[3]));
+        fmm_check_stall(f);
         float ms[3];
         for (int i = 0; i < 3; ++i) DC_HIP(hipEventElapsedTime(&ms[i], f.ev[i], f.ev[i + 1]));
         f.tms[0] += ms[0];
@@ -1497,8 +1778,21 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 }  // namespace
 
+void fmm_check_stall(FmmState& f) {
+    if (f.stall_host && __atomic_load_n(f.stall_host, __ATOMIC_ACQUIRE) != 0) {
+        __atomic_store_n(f.stall_host, 0, __ATOMIC_RELEASE);
+        throw Error(DC_ERR_TIMEOUT,
+                    "an earlier render of this scene stalled on the device (a bounded wait "
+                    "of the render kernel ran out); its images are incomplete");
+    }
+}
+
 std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s) {
     auto f = std::make_unique<FmmState>();
+    DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&f->stall_host), sizeof(int),
+                         hipHostMallocMapped));
+    *f->stall_host = 0;
+    DC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&f->stall_dev), f->stall_host, 0));
     const Tree& T = s.tree;
     f->n_cells = T.n_cells;
     f->depth = T.depth;
@@ -1577,6 +1871,7 @@ void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts&
     unsigned long long h[kNStat];
     DC_HIP(hipMemcpyAsync(h, stats.p, sizeof(h), hipMemcpyDeviceToHost, st));
     DC_HIP(hipStreamSynchronize(st));
+    fmm_check_stall(f);
     counts->p2p_pairs = h[kStatP2P];
     counts->p2p_fp64_pairs = h[kStatP2P64];
     counts->m2p_pairs = h[kStatM2P];
@@ -1637,6 +1932,7 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     // global layout: level-major, viewports in batch order inside a level
     std::vector<std::vector<int>> offs(n);
     pl.lev.clear();
+    pl.vlev.assign((size_t)n * (maxL + 1), -1);
     pl.lev_begin.assign(maxL + 2, 0);
     pl.lev_blocks.assign(maxL + 1, 0);
     long long total = 0;
@@ -1660,8 +1956,10 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
                 e.poff = offs[v][l - 1];
             }
             e.first_block = (int)fb;
+            e.hl = (int)(rj1[v][l] - rj0[v][l] + 1);
             fb += cnt;
             total += cnt;
+            pl.vlev[(size_t)v * (maxL + 1) + l] = (int)pl.lev.size();
             pl.lev.push_back(e);
         }
         pl.lev_blocks[l] = (int)fb;
@@ -1717,7 +2015,8 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
         e.H = vps[v].H;
         e.out = nullptr;
         e.first_block = (int)leaf_blocks;
-        leaf_blocks += (long long)e.wl * (rj1[v][L] - rj0[v][L] + 1);
+        e.hl = (int)(rj1[v][L] - rj0[v][L] + 1);
+        leaf_blocks += (long long)e.wl * e.hl;
     }
     pl.leaf_blocks = (int)leaf_blocks;
     // scratch layout: [level table | leaf table | edge table | local
@@ -1725,11 +2024,15 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     auto up256 = [](size_t x) { return (x + 255) & ~size_t(255); };
     pl.leaf_at = up256(pl.lev.size() * sizeof(VpLevel));
     pl.edges_at = up256(pl.leaf_at + pl.leaf.size() * sizeof(VpLeaf));
-    pl.desc_bytes = pl.edges_at + pl.edges.size() * sizeof(int);
+    pl.vlev_at = up256(pl.edges_at + pl.edges.size() * sizeof(int));
+    pl.desc_bytes = pl.vlev_at + pl.vlev.size() * sizeof(int);
     pl.tl_at = up256(pl.desc_bytes);
     pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
     pl.owner_at = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
-    pl.scratch_bytes = up256(pl.owner_at + (size_t)total * sizeof(int2));
+    pl.queue_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
+    pl.ready_at = up256(pl.queue_at + (size_t)total * sizeof(QItem));
+    pl.ctl_at = up256(pl.ready_at + (size_t)total * sizeof(int));
+    pl.scratch_bytes = up256(pl.ctl_at + sizeof(QueueCtl));
 }
 
 void RenderPlan::write_tables(void* host, void* const* outs) const {
@@ -1741,6 +2044,7 @@ void RenderPlan::write_tables(void* host, void* const* outs) const {
         lf[v].out = outs[v];
     }
     std::memcpy(h + edges_at, edges.data(), edges.size() * sizeof(int));
+    std::memcpy(h + vlev_at, vlev.data(), vlev.size() * sizeof(int));
 }
 
 void fmm_launch_render(dc_scene_s& s, const RenderPlan& pl, const dc_eval_opts& o,
@@ -1774,6 +2078,7 @@ void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int
 void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,
                       int out_dtype, void* const* outs, hipStream_t st) {
     FmmState& f = *s.fmm;
+    fmm_check_stall(f);
     RenderPlan& pl = f.plan;
     plan_render(f, vps, n, o.tile_px, o.p, pl);
     PinnedStage& ps = f.stage[f.stage_next];

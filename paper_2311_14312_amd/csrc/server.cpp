@@ -153,7 +153,15 @@ bool dc_server_s::poll_completions() {
         if (!sl.busy) continue;
         const hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) continue;
-        finish(sl, q == hipSuccess ? DC_OK : DC_ERR_HIP);
+        int status = q == hipSuccess ? DC_OK : DC_ERR_HIP;
+        if (status == DC_OK && !sl.tickets.empty()) {
+            try {
+                fmm_check_stall(*reqs[sl.tickets[0]].scene->fmm);
+            } catch (const Error& e) {
+                status = e.code;
+            }
+        }
+        finish(sl, status);
         any = true;
     }
     return any;
