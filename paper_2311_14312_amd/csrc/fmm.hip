@@ -25,6 +25,7 @@
 // the viewport down to pixel tiles.
 #include <cmath>
 #include <complex>
+#include <cstddef>
 #include <cstring>
 
 #include "scene.h"
@@ -881,10 +882,15 @@ __device__ inline int wave_excl_scan(int v, int lane, int& total) {
 
 constexpr int kQCap = 512;   // traversal stack of the render leaf pass
 constexpr int kMaxLevels = 64;
+// Waves that share one small (8 x 8 pixel) render tile's near field.
+constexpr int kSplit = 2;
 
 template <typename T, int NT>
 struct TileShared {
-    T px[NT], py[NT], tx[NT], ty[NT], len[NT];
+    // piece staging (also the partial sums of the near-field split at the
+    // end of a pass)
+    __align__(16) T px[NT];
+    T py[NT], tx[NT], ty[NT], len[NT];
     T w[6][NT];
     int pid[NT];
     int U[kUCap], Upre[kUCap + 1], W[kWCap], Q[kQCap];
@@ -964,19 +970,50 @@ __device__ inline int xcd_block(int b, int nb) {
     return x * q + min(x, rmd) + b / kXcd;
 }
 
+struct Rgb {
+    double v[3];
+};
+
+// One (pixel, piece) pair of the near field in FP64 (App. D), weighted for
+// the three channels.  Out of line: the FP32 render path calls it only for
+// the rare near-singular and heavy pairs, and inlined it would set the
+// register budget of the whole tile kernel.
+__device__ __noinline__ Rgb pair_fp64(const double* __restrict__ x0, const double* __restrict__ y0,
+                                      const double* __restrict__ tx, const double* __restrict__ ty,
+                                      const double* __restrict__ len,
+                                      const double* __restrict__ w64, int n, int e, double x,
+                                      double y) {
+    double il, th;
+    chord_log_theta<double>(x0[e] - x, y0[e] - y, tx[e], ty[e], len[e], il, th);
+    Rgb r;
+    for (int ch = 0; ch < 3; ++ch)
+        r.v[ch] = il * w64[(size_t)ch * n + e] + th * w64[(size_t)(3 + ch) * n + e];
+    return r;
+}
+
 // Render leaf pass (Alg. 4 at pixel tiles), PX pixels per thread: each
 // piece staged in LDS is read once and evaluated against PX pixels, which
 // gives every lane PX independent chains of the closed forms.  Same
 // arithmetic per (pixel, source) pair as k_leaf; targets are pixels only.
 // Leaf evaluation of one target box (own, level l, cell (ti, tj)) of
 // viewport v at the pixels [k_lo, k_lo + nx) x [r_lo, r_lo + ny), by one
-// block of NT threads, PX pixels each per pass.
-template <typename T, int NT, int PX, bool Count>
+// block of NT threads.  The block is S groups of G = NT / S threads; every
+// group evaluates the same G * PX pixels per pass against every S-th
+// separated box and staged piece, and the S partial sums are added in
+// group order at the end of the pass (so a tile near many pieces is spread
+// over S waves, with a fixed summation order).
+template <typename T, int NT, int PX, int S, bool Count>
 __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const PieceView& pv,
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
                           const int2* __restrict__ owner, const VpLeaf& v, int l, long long ti,
                           long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid) {
+    static_assert(NT % S == 0 && (S == 1 || (NT / S) % kWave == 0), "split groups are waves");
+    constexpr int G = NT / S;
+    using Sh = TileShared<T, NT>;
+    static_assert((S - 1) * PX * 3 * G * sizeof(double) <= offsetof(Sh, U) - offsetof(Sh, px),
+                  "partial sums fit the staging");
+    const int gid = tid / G, gt = tid - gid * G;
     const int n_targets = nx > 0 ? nx * ny : 0;
     const double r = half_width(tv, l);
     double cx, cy;
@@ -992,7 +1029,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
     double ocx, ocy;
     center_of(tv, lo, ti >> (l - lo), tj >> (l - lo), ocx, ocy);
 
-    for (int tbase = 0; tbase < n_targets; tbase += NT * PX) {
+    for (int tbase = 0; tbase < n_targets; tbase += G * PX) {
         double x[PX], y[PX];
         T xr[PX], yr[PX];
         bool act[PX];
@@ -1000,7 +1037,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         // u = (E - P) / 2pi: E from expansions, P the near field (FP64 sums)
         double acc[PX][3];
         for (int q = 0; q < PX; ++q) {
-            const int tgt = tbase + q * NT + tid;
+            const int tgt = tbase + q * G + gt;
             act[q] = tgt < n_targets;
             x[q] = cx;
             y[q] = cy;
@@ -1016,7 +1053,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
             for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
         }
         // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
-        if (lo >= 2) {
+        if (lo >= 2 && gid == 0) {
             const double ir = 1.0 / ro;
             for (int q = 0; q < PX; ++q) {
                 const cpx<double> z = {(x[q] - ocx) * ir, (y[q] - ocy) * ir};
@@ -1027,7 +1064,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                 }
             }
         }
-        const int n_here = min(NT * PX, n_targets - tbase);
+        const int n_here = min(G * PX, n_targets - tbase);
         if (Count && tid == 0) {
             if (lo >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
             if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
@@ -1062,7 +1099,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
             //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
             // with Ms_k = Mt_k / k precomputed; Mt_0 (the total charge times
             // length) is real, so only log|x - c| is needed
-            for (int u = 0; u < nW; ++u) {
+            for (int u = gid; u < nW; u += S) {
                 const int d = sh.W[u];
                 const int ld = tv.lvl[d];
                 const double rd = half_width(tv, ld), ird = 1.0 / rd;
@@ -1108,7 +1145,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                 __syncthreads();
                 const int m = min(NT, total - pbase);
                 const float near2f = (float)a.near2;
-                for (int j = 0; j < m; ++j) {
+                for (int j = gid; j < m; j += S) {
                     const T px0 = sh.px[j], py0 = sh.py[j];
                     const T tx = sh.tx[j], ty = sh.ty[j], la = sh.len[j];
                     const int pid = sh.pid[j];
@@ -1150,12 +1187,9 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                         const int e = pid < 0 ? -1 - pid : pid;
                         for (int q = 0; q < PX; ++q) {
                             if (!(slow[q] && act[q])) continue;
-                            double dil, dth;
-                            chord_log_theta<double>(pv.x0[e] - x[q], pv.y0[e] - y[q], pv.tx[e],
-                                                    pv.ty[e], pv.len[e], dil, dth);
-                            for (int ch = 0; ch < 3; ++ch)
-                                acc[q][ch] -= dil * pv.w64[(size_t)ch * pv.n + e] +
-                                              dth * pv.w64[(size_t)(3 + ch) * pv.n + e];
+                            const Rgb d = pair_fp64(pv.x0, pv.y0, pv.tx, pv.ty, pv.len, pv.w64,
+                                                    pv.n, e, x[q], y[q]);
+                            for (int ch = 0; ch < 3; ++ch) acc[q][ch] -= d.v[ch];
                             if (Count) atomicAdd(a.stats + kStatP2P64, 1ULL);
                         }
                     }
@@ -1165,8 +1199,22 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
             if (!more) break;
         }
     store:
+        if (S > 1) {
+            // partial sums of groups 1..S-1 through the staging arrays
+            double* red = reinterpret_cast<double*>(sh.px);
+            if (gid > 0)
+                for (int q = 0; q < PX; ++q)
+                    for (int ch = 0; ch < 3; ++ch)
+                        red[(((size_t)(gid - 1) * PX + q) * 3 + ch) * G + gt] = acc[q][ch];
+            __syncthreads();
+            if (gid == 0)
+                for (int g2 = 1; g2 < S; ++g2)
+                    for (int q = 0; q < PX; ++q)
+                        for (int ch = 0; ch < 3; ++ch)
+                            acc[q][ch] += red[(((size_t)(g2 - 1) * PX + q) * 3 + ch) * G + gt];
+        }
         for (int q = 0; q < PX; ++q) {
-            if (!act[q]) continue;
+            if (!act[q] || gid != 0) continue;
             for (int ch = 0; ch < 3; ++ch) {
                 const double u = acc[q][ch] / kTwoPi;
                 if (a.out_f64)
@@ -1182,8 +1230,8 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
 
 // Count: a counting instance (work counters on; a distinct kernel, so that
 // timed launches carry no counter code).
-template <typename T, int NT, int PX, bool Count>
-__global__ void __launch_bounds__(NT, 4)
+template <typename T, int NT, int PX, int S, bool Count>
+__global__ void __launch_bounds__(NT, 5)
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
@@ -1200,8 +1248,8 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     const int nx = a.edges[v.col_at + ci + 1] - k_lo;
     const int r_lo = a.edges[v.row_at + cj + 1];
     const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
-    tile_body<T, NT, PX, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own, k_lo,
-                                nx, r_lo, ny, tid);
+    tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
+                                   k_lo, nx, r_lo, ny, tid);
 }
 
 // ------------------------------------------------------ fused render kernel
@@ -1268,8 +1316,8 @@ __device__ __noinline__ void tile_call(TileShared<T, NT>& sh, const TreeView& tv
                                        const int* nset, const int2* owner, const VpLeaf& v, int l,
                                        long long ti, long long tj, int own, int k_lo, int nx,
                                        int r_lo, int ny, int tid) {
-    tile_body<T, NT, PX, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own, k_lo, nx,
-                                r_lo, ny, tid);
+    tile_body<T, NT, PX, 1, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own, k_lo,
+                                   nx, r_lo, ny, tid);
 }
 
 template <typename T>
@@ -1739,21 +1787,24 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         a.nvleaf = pl.n;
         a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
         if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
-        // tiles of up to 9 x 9 pixels: one pixel per thread; up to 17 x 17: two
+        // tiles of up to 8 x 8 pixels: one pixel per lane, the near field split
+        // over kSplit waves; up to 16 x 16: two pixels per thread
         if (o.tile_px <= 8) {
             if (stats)
-                hipLaunchKernelGGL((k_tile<T, 64, 1, true>), dim3(pl.leaf_blocks), dim3(64), 0, st, tv,
-                                   pv, a, p, Ms, TL, nset, owner);
+                hipLaunchKernelGGL((k_tile<T, kWave * kSplit, 1, kSplit, true>),
+                                   dim3(pl.leaf_blocks), dim3(kWave * kSplit), 0, st, tv, pv, a, p,
+                                   Ms, TL, nset, owner);
             else
-                hipLaunchKernelGGL((k_tile<T, 64, 1, false>), dim3(pl.leaf_blocks), dim3(64), 0, st,
-                                   tv, pv, a, p, Ms, TL, nset, owner);
+                hipLaunchKernelGGL((k_tile<T, kWave * kSplit, 1, kSplit, false>),
+                                   dim3(pl.leaf_blocks), dim3(kWave * kSplit), 0, st, tv, pv, a, p,
+                                   Ms, TL, nset, owner);
         } else {
             if (stats)
-                hipLaunchKernelGGL((k_tile<T, 128, 2, true>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                                   tv, pv, a, p, Ms, TL, nset, owner);
+                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128), 0,
+                                   st, tv, pv, a, p, Ms, TL, nset, owner);
             else
-                hipLaunchKernelGGL((k_tile<T, 128, 2, false>), dim3(pl.leaf_blocks), dim3(128), 0, st,
-                                   tv, pv, a, p, Ms, TL, nset, owner);
+                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128), 0,
+                                   st, tv, pv, a, p, Ms, TL, nset, owner);
         }
         DC_HIP(hipGetLastError());
     }
