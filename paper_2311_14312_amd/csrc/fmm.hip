@@ -348,15 +348,23 @@ struct DownShared {
 };
 
 // Downward pass of one target box (own, at level l, cell (ti, tj), parent
-// par) by one wave.  Writes nset[own] and, unless the box is quiet (render
-// only, owner != nullptr), L[own]; returns whether it was quiet.
+// par) by one wave.  Writes nset[own] (unless the parent is quiet) and,
+// unless the box is quiet (render only, owner != nullptr), L[own]; returns
+// whether it was quiet.
 template <typename T, bool Count>
 __device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView& pv, int l,
                           long long ti, long long tj, int own, int par, int p,
                           const cpx<T>* __restrict__ M, cpx<T>* __restrict__ L,
                           int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
                           int2* __restrict__ owner, unsigned long long* stats, int lane) {
+    // Render: the children of a quiet box are quiet (below); they record the
+    // owner and leave without loading the near set (which nothing reads).
+    const int2 po = owner != nullptr ? owner[par] : make_int2(par, 0);
     if (lane < 9) sh.PN[lane] = nset[(size_t)par * 9 + lane];
+    if (po.x != par) {
+        if (lane == 0) owner[own] = po;
+        return true;
+    }
     __syncthreads();
     // Metadata of the parent's near set, loaded once by lanes 0..8; it
     // serves the near set, the interaction list and the separated leaves.
@@ -401,7 +409,7 @@ __device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView
         bool quiet = true;
         for (int s = 0; s < 9; ++s) quiet = quiet && (sh.PN[s] < 0 || sh.PN2[s] == 0);
         if (quiet) {
-            if (lane == 0) owner[own] = owner[par];
+            if (lane == 0) owner[own] = po;
             return true;
         }
         if (lane == 0) owner[own] = make_int2(own, l);
@@ -659,6 +667,10 @@ struct LeafArgs {
     int N;
     double near2;            // (near_fp64)^2, FP32 only
     unsigned long long* stats;  // optional work counters
+    // heavy small render tiles left to k_tile_big; hv_list null: none
+    int* hv_ctl;             // [0] queued tiles, [1] next to take
+    int* hv_list;            // queued tiles (global leaf block), hv_list_cap entries
+    int hv_list_cap;
 };
 
 template <typename T, int NT>
@@ -883,7 +895,7 @@ __device__ inline int wave_excl_scan(int v, int lane, int& total) {
 constexpr int kQCap = 512;   // traversal stack of the render leaf pass
 constexpr int kMaxLevels = 64;
 // Waves that share one small (8 x 8 pixel) render tile's near field.
-constexpr int kSplit = 2;
+constexpr int kSplit = 1;
 
 template <typename T, int NT>
 struct TileShared {
@@ -894,7 +906,9 @@ struct TileShared {
     T w[6][NT];
     int pid[NT];
     int U[kUCap], Upre[kUCap + 1], W[kWCap], Q[kQCap];
-    int nU, nW, nQ;
+    int nU, nW, nQ, heavy;
+    // expansion coefficients staged per wave (L2P and M2P)
+    cpx<double> coef[NT / kWave][3 * (DC_P_MAX + 1)];
 };
 
 // Near-set traversal of a target tile by one wave (lane = lane of wave 0),
@@ -995,249 +1009,371 @@ __device__ __noinline__ Rgb pair_fp64(const double* __restrict__ x0, const doubl
 // piece staged in LDS is read once and evaluated against PX pixels, which
 // gives every lane PX independent chains of the closed forms.  Same
 // arithmetic per (pixel, source) pair as k_leaf; targets are pixels only.
-// Leaf evaluation of one target box (own, level l, cell (ti, tj)) of
-// viewport v at the pixels [k_lo, k_lo + nx) x [r_lo, r_lo + ny), by one
-// block of NT threads.  The block is S groups of G = NT / S threads; every
-// group evaluates the same G * PX pixels per pass against every S-th
-// separated box and staged piece, and the S partial sums are added in
-// group order at the end of the pass (so a tile near many pieces is spread
-// over S waves, with a fixed summation order).
+// A tile (target box own, level l, cell (ti, tj) of viewport v, pixels
+// [k_lo, k_lo + nx) x [r_lo, r_lo + ny)) is evaluated by one block of NT
+// threads: S groups of G = NT / S threads, each group on the same G * PX
+// pixels per pass.  The separated boxes are numbered in traversal order and
+// group g takes those with number % S == g, and every S-th piece of each
+// staged chunk; the value of a pixel is L2P plus the group partial sums,
+// added in group order.  A small tile whose first traversal round finds
+// more than kHeavyPieces<T> near pieces, or leaves more rounds to come, is
+// queued instead and evaluated by k_tile_big, whose blocks split one
+// tile's near field over kBigSplit<T> waves.
+// Waves per SIMD the tile kernels are compiled for (register budget).
+template <typename T>
+constexpr int kTileWaves = sizeof(T) == 4 ? 8 : 4;
+template <typename T>
+constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
+template <typename T>
+constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
+
+template <typename T, int PX>
+struct TileTargets {
+    double x[PX], y[PX];
+    T xr[PX], yr[PX];
+    bool act[PX];
+    int out_idx[PX];
+};
+
+// Pixels of one pass (targets tbase + q G + gt of the tile, row-major).
+template <typename T, int PX, int G>
+__device__ inline void tile_targets(TileTargets<T, PX>& tt, const VpLeaf& v, double cx,
+                                    double cy, int k_lo, int nx, int r_lo, int n_targets,
+                                    int tbase, int gt) {
+    for (int q = 0; q < PX; ++q) {
+        const int tgt = tbase + q * G + gt;
+        tt.act[q] = tgt < n_targets;
+        tt.x[q] = cx;
+        tt.y[q] = cy;
+        tt.out_idx[q] = 0;
+        if (tt.act[q]) {
+            const int col = k_lo + tgt % nx, row = r_lo + tgt / nx;
+            tt.x[q] = pixel_x(v.vcx, v.vw, v.W, col);
+            tt.y[q] = pixel_y(v.vcy, v.vh, v.H, row);
+            tt.out_idx[q] = row * v.W + col;
+        }
+        tt.xr[q] = (T)(tt.x[q] - cx);
+        tt.yr[q] = (T)(tt.y[q] - cy);
+    }
+}
+
+// Copy of n expansion coefficients into this wave's LDS buffer (one
+// coalesced load per lane; LDS accesses of one wave complete in order, so
+// the wave reads them back without a block barrier).
+__device__ inline void stage_coef(cpx<double>* __restrict__ buf, const cpx<double>* __restrict__ src,
+                                  int n, int lane) {
+    for (int i = lane; i < n; i += kWave) buf[i] = src[i];
+    __builtin_amdgcn_wave_barrier();
+}
+
+// target-from-incoming (Eq. t-f-i) at the pass's pixels: Re sum_k ((x-c)/r)^k Lt_k
+// of the owner's expansion (loc at level lo, centre (ocx, ocy)); adds into acc.
+// cbuf: this wave's coefficient buffer.
+template <typename T, int PX>
+__device__ inline void tile_l2p(const TileTargets<T, PX>& tt, const cpx<double>* loc, int p,
+                                int lo, double ro, double ocx, double ocy, cpx<double>* cbuf,
+                                int lane, double (&acc)[PX][3]) {
+    if (lo < 2) return;
+    stage_coef(cbuf, loc, (p + 1) * 3, lane);
+    const double ir = 1.0 / ro;
+    for (int q = 0; q < PX; ++q) {
+        const cpx<double> z = {(tt.x[q] - ocx) * ir, (tt.y[q] - ocy) * ir};
+        for (int ch = 0; ch < 3; ++ch) {
+            cpx<double> s = cbuf[p * 3 + ch];
+            for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), cbuf[kk * 3 + ch]);
+            acc[q][ch] += s.re;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Traversal stack of a tile: the distinct nonempty cells of its near set.
+template <typename T, int NT>
+__device__ inline void tile_near_init(TileShared<T, NT>& sh, const TreeView& tv,
+                                      const int* __restrict__ nset, int own, int tid) {
+    if (tid < kWave) {
+        int c = -1;
+        bool ok = false;
+        if (tid < 9) {
+            c = nset[(size_t)own * 9 + tid];
+            ok = c >= 0;
+            for (int s2 = 0; s2 < tid && ok; ++s2) ok = nset[(size_t)own * 9 + s2] != c;
+            ok = ok && tv.npc[c] > 0;
+        }
+        const unsigned long long m = __ballot(ok);
+        if (ok) sh.Q[__popcll(m & ((1ULL << tid) - 1ULL))] = c;
+        if (tid == 0) sh.nQ = __popcll(m);
+    }
+}
+
+// Near field of a tile pass (see above): near-set traversal by wave 0 in
+// rounds bounded by the list capacities (the stack starts with the
+// distinct nonempty cells of the near set; first_round_done: the first
+// round is already in sh), then the round's separated boxes
+// (target-from-outgoing) and near pieces (target-from-source) of this
+// thread's group.  Adds the group's terms into acc.
 template <typename T, int NT, int PX, int S, bool Count>
-__device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const PieceView& pv,
+__device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const PieceView& pv,
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
-                          const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
-                          const int2* __restrict__ owner, const VpLeaf& v, int l, long long ti,
-                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid) {
-    static_assert(NT % S == 0 && (S == 1 || (NT / S) % kWave == 0), "split groups are waves");
+                          const int* __restrict__ nset, int l, long long ti, long long tj,
+                          int own, double cx, double cy, const TileTargets<T, PX>& tt,
+                          int n_here, int tid, double (&acc)[PX][3],
+                          bool first_round_done = false) {
+    constexpr int G = NT / S;
+    const int gid = tid / G, gt = tid - gid * G;
+    const T* wts = weights<T>(pv);
+    if (!first_round_done) {
+        tile_near_init(sh, tv, nset, own, tid);
+        __syncthreads();
+    }
+    int u_run = 0;
+    for (bool first = true;; first = false) {
+        if (tid < kWave && !(first && first_round_done)) tile_round(sh, tv, l, ti, tj, tid);
+        __syncthreads();
+        const int nU = sh.nU, nW = sh.nW, more = sh.nQ > 0;
+        // target-from-outgoing (Eq. t-f-o), scaled:
+        //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
+        // with Ms_k = Mt_k / k precomputed; Mt_0 (the total charge times
+        // length) is real, so only log|x - c| is needed
+        cpx<double>* const src = sh.coef[tid / kWave];
+        for (int u = ((gid - u_run) % S + S) % S; u < nW; u += S) {
+            const int d = sh.W[u];
+            stage_coef(src, Ms + (size_t)d * (p + 1) * 3, (p + 1) * 3, tid % kWave);
+            const int ld = tv.lvl[d];
+            const double rd = half_width(tv, ld), ird = 1.0 / rd;
+            double dcx, dcy;
+            center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
+            const double lr = log(rd);
+            for (int q = 0; q < PX; ++q) {
+                if (!tt.act[q]) continue;
+                const cpx<double> rel = {(tt.x[q] - dcx) * ird, (tt.y[q] - dcy) * ird};
+                const double n2 = rel.re * rel.re + rel.im * rel.im;
+                const double in2 = 1.0 / n2;
+                const cpx<double> z = {rel.re * in2, -rel.im * in2};
+                const double lgr = lr + 0.5 * log(n2);
+                for (int ch = 0; ch < 3; ++ch) {
+                    cpx<double> s = src[p * 3 + ch];
+                    for (int kk = p - 1; kk >= 1; --kk) s = cadd(cmul(s, z), src[kk * 3 + ch]);
+                    s = cmul(s, z);
+                    acc[q][ch] += s.re - lgr * src[ch].re;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (Count && gt == 0) atomicAdd(a.stats + kStatM2P, (unsigned long long)n_here);
+        }
+        u_run += nW;
+        // target-from-source (App. D) over the pieces of the near leaves
+        const int total = sh.Upre[nU];
+        for (int pbase = 0; pbase < total; pbase += NT) {
+            __syncthreads();
+            const int g = pbase + tid;
+            if (g < total) {
+                int lo = 0, hi = nU - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sh.Upre[mid] <= g) lo = mid; else hi = mid - 1;
+                }
+                const int e = tv.pbeg[sh.U[lo]] + (g - sh.Upre[lo]);
+                sh.px[tid] = (T)(pv.x0[e] - cx);
+                sh.py[tid] = (T)(pv.y0[e] - cy);
+                sh.tx[tid] = (T)pv.tx[e];
+                sh.ty[tid] = (T)pv.ty[e];
+                sh.len[tid] = (T)pv.len[e];
+                for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
+                sh.pid[tid] = sizeof(T) == 4 && pv.heavy[e] ? -1 - e : e;
+            }
+            __syncthreads();
+            const int m = min(NT, total - pbase);
+            if (Count && tid == 0) atomicAdd(a.stats + kStatP2P, (unsigned long long)n_here * m);
+            const float near2f = (float)a.near2;
+            for (int j = gid; j < m; j += S) {
+                const T px0 = sh.px[j], py0 = sh.py[j];
+                const T tx = sh.tx[j], ty = sh.ty[j], la = sh.len[j];
+                const int pid = sh.pid[j];
+                if (sizeof(T) == 8) {
+                    for (int q = 0; q < PX; ++q) {
+                        T il, th;
+                        chord_log_theta<T>(px0 - tt.xr[q], py0 - tt.yr[q], tx, ty, la, il, th);
+                        for (int ch = 0; ch < 3; ++ch)
+                            acc[q][ch] -= il * sh.w[ch][j] + th * sh.w[3 + ch][j];
+                    }
+                    continue;
+                }
+                // FP32: the fast closed form for every pixel, straight-line
+                // so the PX chains interleave; near-singular pairs and heavy
+                // pieces are then redone in FP64 (rare, divergent)
+                float il[PX], th[PX];
+                bool slow[PX];
+                bool any_slow = false;
+                const float fla = (float)la, lim = near2f * fla * fla;
+                for (int q = 0; q < PX; ++q) {
+                    const float dx = (float)(px0 - tt.xr[q]), dy = (float)(py0 - tt.yr[q]);
+                    const float xi1 = dx * (float)tx + dy * (float)ty;
+                    const float h = dy * (float)tx - dx * (float)ty;
+                    const float xi2 = xi1 + fla;
+                    // squared distance to the chord, branch-free
+                    const float along = fmaxf(xi1, 0.f) + fmaxf(-xi2, 0.f);
+                    slow[q] = along * along + h * h < lim || pid < 0;
+                    any_slow |= slow[q] && tt.act[q];
+                    chord_fast_nz(xi1, h, xi2, fla, il[q], th[q]);
+                }
+                float w6[6];
+                for (int c6 = 0; c6 < 6; ++c6) w6[c6] = (float)sh.w[c6][j];
+                for (int q = 0; q < PX; ++q)
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const float t = il[q] * w6[ch] + th[q] * w6[3 + ch];
+                        acc[q][ch] -= (double)(slow[q] ? 0.f : t);
+                    }
+                if (any_slow) {
+                    const int e = pid < 0 ? -1 - pid : pid;
+                    for (int q = 0; q < PX; ++q) {
+                        if (!(slow[q] && tt.act[q])) continue;
+                        const Rgb d = pair_fp64(pv.x0, pv.y0, pv.tx, pv.ty, pv.len, pv.w64,
+                                                pv.n, e, tt.x[q], tt.y[q]);
+                        for (int ch = 0; ch < 3; ++ch) acc[q][ch] -= d.v[ch];
+                        if (Count) atomicAdd(a.stats + kStatP2P64, 1ULL);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (!more) break;
+    }
+}
+
+// Adds the partial sums of groups 1..S-1 to group 0's, in group order
+// (through the staging arrays; every thread of the block calls it).
+template <typename T, int NT, int PX, int S>
+__device__ inline void tile_group_sum(TileShared<T, NT>& sh, int tid, double (&acc)[PX][3]) {
+    if (S == 1) return;
     constexpr int G = NT / S;
     using Sh = TileShared<T, NT>;
     static_assert((S - 1) * PX * 3 * G * sizeof(double) <= offsetof(Sh, U) - offsetof(Sh, px),
                   "partial sums fit the staging");
     const int gid = tid / G, gt = tid - gid * G;
+    double* red = reinterpret_cast<double*>(sh.px);
+    __syncthreads();
+    if (gid > 0)
+        for (int q = 0; q < PX; ++q)
+            for (int ch = 0; ch < 3; ++ch)
+                red[(((size_t)(gid - 1) * PX + q) * 3 + ch) * G + gt] = acc[q][ch];
+    __syncthreads();
+    if (gid == 0)
+        for (int g2 = 1; g2 < S; ++g2)
+            for (int q = 0; q < PX; ++q)
+                for (int ch = 0; ch < 3; ++ch)
+                    acc[q][ch] += red[(((size_t)(g2 - 1) * PX + q) * 3 + ch) * G + gt];
+    __syncthreads();
+}
+
+// u / 2pi at the pass's pixels (group 0 holds the sums).
+template <typename T, int PX>
+__device__ inline void tile_store(const LeafArgs& a, const VpLeaf& v, const TileTargets<T, PX>& tt,
+                                  bool group0, const double (&acc)[PX][3]) {
+    for (int q = 0; q < PX; ++q) {
+        if (!tt.act[q] || !group0) continue;
+        for (int ch = 0; ch < 3; ++ch) {
+            const double u = acc[q][ch] / kTwoPi;
+            if (a.out_f64)
+                static_cast<double*>(v.out)[(size_t)tt.out_idx[q] * 3 + ch] = u;
+            else
+                static_cast<float*>(v.out)[(size_t)tt.out_idx[q] * 3 + ch] = (float)u;
+        }
+    }
+}
+
+// Geometry of a tile's owner expansion (quiet tiles evaluate an ancestor's).
+struct TileOwner {
+    const cpx<double>* loc;
+    int lo;
+    double ro, ocx, ocy;
+    bool quiet;
+};
+
+__device__ inline TileOwner tile_owner(const TreeView& tv, const cpx<double>* Lc,
+                                       const int2* owner, int p, int l, long long ti,
+                                       long long tj, int own) {
+    TileOwner o;
+    const int2 ow = owner[own];
+    o.quiet = ow.x != own;
+    o.loc = Lc + (size_t)ow.x * (p + 1) * 3;
+    o.lo = ow.y;
+    o.ro = half_width(tv, o.lo);
+    center_of(tv, o.lo, ti >> (l - o.lo), tj >> (l - o.lo), o.ocx, o.ocy);
+    return o;
+}
+
+// Leaf evaluation of one tile by one block.  With share set, a heavy tile
+// of at most G * PX pixels (see above) is queued for k_tile_big (as global
+// leaf block gb) and left to it.
+template <typename T, int NT, int PX, int S, bool Count>
+__device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const PieceView& pv,
+                          const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
+                          const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
+                          const int2* __restrict__ owner, const VpLeaf& v, int l, long long ti,
+                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid,
+                          bool share = false, int gb = -1) {
+    static_assert(NT % S == 0 && (S == 1 || (NT / S) % kWave == 0), "split groups are waves");
+    constexpr int G = NT / S;
+    const int gid = tid / G, gt = tid - gid * G;
     const int n_targets = nx > 0 ? nx * ny : 0;
-    const double r = half_width(tv, l);
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
-    const T* wts = weights<T>(pv);
-    // a quiet tile (see k_down) evaluates its owner's expansion and has no
-    // near field
-    const int2 ow = owner[own];
-    const bool quiet = ow.x != own;
-    const cpx<double>* loc = Lc + (size_t)ow.x * (p + 1) * 3;
-    const int lo = ow.y;
-    const double ro = half_width(tv, lo);
-    double ocx, ocy;
-    center_of(tv, lo, ti >> (l - lo), tj >> (l - lo), ocx, ocy);
-
-    for (int tbase = 0; tbase < n_targets; tbase += G * PX) {
-        double x[PX], y[PX];
-        T xr[PX], yr[PX];
-        bool act[PX];
-        int out_idx[PX];
-        // u = (E - P) / 2pi: E from expansions, P the near field (FP64 sums)
-        double acc[PX][3];
-        for (int q = 0; q < PX; ++q) {
-            const int tgt = tbase + q * G + gt;
-            act[q] = tgt < n_targets;
-            x[q] = cx;
-            y[q] = cy;
-            out_idx[q] = 0;
-            if (act[q]) {
-                const int col = k_lo + tgt % nx, row = r_lo + tgt / nx;
-                x[q] = pixel_x(v.vcx, v.vw, v.W, col);
-                y[q] = pixel_y(v.vcy, v.vh, v.H, row);
-                out_idx[q] = row * v.W + col;
+    const TileOwner o = tile_owner(tv, Lc, owner, p, l, ti, tj, own);
+    // A shared tile is decided after the first traversal round: more than
+    // kHeavyPieces near pieces, or more rounds to come.
+    bool round0 = false;
+    if (share && !o.quiet && n_targets > 0 && n_targets <= G * PX) {
+        tile_near_init(sh, tv, nset, own, tid);
+        __syncthreads();
+        if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
+        __syncthreads();
+        if (tid == 0) {
+            int queued = 0;
+            if (sh.Upre[sh.nU] > kHeavyPieces<T> || sh.nQ > 0) {
+                const int h = atomicAdd(&a.hv_ctl[0], 1);
+                queued = h < a.hv_list_cap;  // the list holds every tile
+                if (queued) a.hv_list[h] = gb;
             }
-            xr[q] = (T)(x[q] - cx);
-            yr[q] = (T)(y[q] - cy);
-            for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
-        }
-        // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
-        if (lo >= 2 && gid == 0) {
-            const double ir = 1.0 / ro;
-            for (int q = 0; q < PX; ++q) {
-                const cpx<double> z = {(x[q] - ocx) * ir, (y[q] - ocy) * ir};
-                for (int ch = 0; ch < 3; ++ch) {
-                    cpx<double> s = loc[p * 3 + ch];
-                    for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
-                    acc[q][ch] += s.re;
-                }
-            }
-        }
-        const int n_here = min(G * PX, n_targets - tbase);
-        if (Count && tid == 0) {
-            if (lo >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
-            if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
-        }
-        if (quiet) goto store;
-        // near-set traversal by wave 0, in rounds bounded by the list
-        // capacities; the stack starts with the distinct nonempty boxes of
-        // the near set
-        if (tid < kWave) {
-            int c = -1;
-            bool ok = false;
-            if (tid < 9) {
-                c = nset[(size_t)own * 9 + tid];
-                ok = c >= 0;
-                for (int s2 = 0; s2 < tid && ok; ++s2) ok = nset[(size_t)own * 9 + s2] != c;
-                ok = ok && tv.npc[c] > 0;
-            }
-            const unsigned long long m = __ballot(ok);
-            if (ok) sh.Q[__popcll(m & ((1ULL << tid) - 1ULL))] = c;
-            if (tid == 0) sh.nQ = __popcll(m);
+            sh.heavy = queued;
         }
         __syncthreads();
-        for (;;) {
-            if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
-            __syncthreads();
-            const int nU = sh.nU, nW = sh.nW, more = sh.nQ > 0;
-            if (Count && tid == 0) {
-                atomicAdd(a.stats + kStatM2P, (unsigned long long)n_here * nW);
-                atomicAdd(a.stats + kStatP2P, (unsigned long long)n_here * sh.Upre[nU]);
-            }
-            // target-from-outgoing (Eq. t-f-o), scaled:
-            //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
-            // with Ms_k = Mt_k / k precomputed; Mt_0 (the total charge times
-            // length) is real, so only log|x - c| is needed
-            for (int u = gid; u < nW; u += S) {
-                const int d = sh.W[u];
-                const int ld = tv.lvl[d];
-                const double rd = half_width(tv, ld), ird = 1.0 / rd;
-                double dcx, dcy;
-                center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
-                const double lr = log(rd);
-                const cpx<double>* src = Ms + (size_t)d * (p + 1) * 3;
-                for (int q = 0; q < PX; ++q) {
-                    if (!act[q]) continue;
-                    const cpx<double> rel = {(x[q] - dcx) * ird, (y[q] - dcy) * ird};
-                    const double n2 = rel.re * rel.re + rel.im * rel.im;
-                    const double in2 = 1.0 / n2;
-                    const cpx<double> z = {rel.re * in2, -rel.im * in2};
-                    const double lgr = lr + 0.5 * log(n2);
-                    for (int ch = 0; ch < 3; ++ch) {
-                        cpx<double> s = src[p * 3 + ch];
-                        for (int kk = p - 1; kk >= 1; --kk) s = cadd(cmul(s, z), src[kk * 3 + ch]);
-                        s = cmul(s, z);
-                        acc[q][ch] += s.re - lgr * src[ch].re;
-                    }
-                }
-            }
-            // target-from-source (App. D) over the pieces of the near leaves
-            const int total = sh.Upre[nU];
-            for (int pbase = 0; pbase < total; pbase += NT) {
-                __syncthreads();
-                const int g = pbase + tid;
-                if (g < total) {
-                    int lo = 0, hi = nU - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (sh.Upre[mid] <= g) lo = mid; else hi = mid - 1;
-                    }
-                    const int e = tv.pbeg[sh.U[lo]] + (g - sh.Upre[lo]);
-                    sh.px[tid] = (T)(pv.x0[e] - cx);
-                    sh.py[tid] = (T)(pv.y0[e] - cy);
-                    sh.tx[tid] = (T)pv.tx[e];
-                    sh.ty[tid] = (T)pv.ty[e];
-                    sh.len[tid] = (T)pv.len[e];
-                    for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
-                    sh.pid[tid] = sizeof(T) == 4 && pv.heavy[e] ? -1 - e : e;
-                }
-                __syncthreads();
-                const int m = min(NT, total - pbase);
-                const float near2f = (float)a.near2;
-                for (int j = gid; j < m; j += S) {
-                    const T px0 = sh.px[j], py0 = sh.py[j];
-                    const T tx = sh.tx[j], ty = sh.ty[j], la = sh.len[j];
-                    const int pid = sh.pid[j];
-                    if (sizeof(T) == 8) {
-                        for (int q = 0; q < PX; ++q) {
-                            T il, th;
-                            chord_log_theta<T>(px0 - xr[q], py0 - yr[q], tx, ty, la, il, th);
-                            for (int ch = 0; ch < 3; ++ch)
-                                acc[q][ch] -= il * sh.w[ch][j] + th * sh.w[3 + ch][j];
-                        }
-                        continue;
-                    }
-                    // FP32: the fast closed form for every pixel, straight-line
-                    // so the PX chains interleave; near-singular pairs and
-                    // heavy pieces are then redone in FP64 (rare, divergent)
-                    float il[PX], th[PX];
-                    bool slow[PX];
-                    bool any_slow = false;
-                    const float fla = (float)la, lim = near2f * fla * fla;
-                    for (int q = 0; q < PX; ++q) {
-                        const float dx = (float)(px0 - xr[q]), dy = (float)(py0 - yr[q]);
-                        const float xi1 = dx * (float)tx + dy * (float)ty;
-                        const float h = dy * (float)tx - dx * (float)ty;
-                        const float xi2 = xi1 + fla;
-                        // squared distance to the chord, branch-free
-                        const float along = fmaxf(xi1, 0.f) + fmaxf(-xi2, 0.f);
-                        slow[q] = along * along + h * h < lim || pid < 0;
-                        any_slow |= slow[q] && act[q];
-                        chord_fast_nz(xi1, h, xi2, fla, il[q], th[q]);
-                    }
-                    float w6[6];
-                    for (int c6 = 0; c6 < 6; ++c6) w6[c6] = (float)sh.w[c6][j];
-                    for (int q = 0; q < PX; ++q)
-                        for (int ch = 0; ch < 3; ++ch) {
-                            const float t = il[q] * w6[ch] + th[q] * w6[3 + ch];
-                            acc[q][ch] -= (double)(slow[q] ? 0.f : t);
-                        }
-                    if (any_slow) {
-                        const int e = pid < 0 ? -1 - pid : pid;
-                        for (int q = 0; q < PX; ++q) {
-                            if (!(slow[q] && act[q])) continue;
-                            const Rgb d = pair_fp64(pv.x0, pv.y0, pv.tx, pv.ty, pv.len, pv.w64,
-                                                    pv.n, e, x[q], y[q]);
-                            for (int ch = 0; ch < 3; ++ch) acc[q][ch] -= d.v[ch];
-                            if (Count) atomicAdd(a.stats + kStatP2P64, 1ULL);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            if (!more) break;
+        if (sh.heavy) return;
+        round0 = true;
+    }
+    for (int tbase = 0; tbase < n_targets; tbase += G * PX) {
+        TileTargets<T, PX> tt;
+        tile_targets<T, PX, G>(tt, v, cx, cy, k_lo, nx, r_lo, n_targets, tbase, gt);
+        // u = (E - P) / 2pi: E from expansions, P the near field (FP64 sums)
+        double acc[PX][3];
+        for (int q = 0; q < PX; ++q)
+            for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
+        if (gid == 0)
+            tile_l2p<T, PX>(tt, o.loc, p, o.lo, o.ro, o.ocx, o.ocy, sh.coef[tid / kWave],
+                            tid % kWave, acc);
+        const int n_here = min(G * PX, n_targets - tbase);
+        if (Count && tid == 0) {
+            if (o.lo >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
+            if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
         }
-    store:
-        if (S > 1) {
-            // partial sums of groups 1..S-1 through the staging arrays
-            double* red = reinterpret_cast<double*>(sh.px);
-            if (gid > 0)
-                for (int q = 0; q < PX; ++q)
-                    for (int ch = 0; ch < 3; ++ch)
-                        red[(((size_t)(gid - 1) * PX + q) * 3 + ch) * G + gt] = acc[q][ch];
-            __syncthreads();
-            if (gid == 0)
-                for (int g2 = 1; g2 < S; ++g2)
-                    for (int q = 0; q < PX; ++q)
-                        for (int ch = 0; ch < 3; ++ch)
-                            acc[q][ch] += red[(((size_t)(g2 - 1) * PX + q) * 3 + ch) * G + gt];
-        }
-        for (int q = 0; q < PX; ++q) {
-            if (!act[q] || gid != 0) continue;
-            for (int ch = 0; ch < 3; ++ch) {
-                const double u = acc[q][ch] / kTwoPi;
-                if (a.out_f64)
-                    static_cast<double*>(v.out)[(size_t)out_idx[q] * 3 + ch] = u;
-                else
-                    static_cast<float*>(v.out)[(size_t)out_idx[q] * 3 + ch] = (float)u;
-            }
-        }
+        if (!o.quiet)
+            tile_near<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, nset, l, ti, tj, own, cx, cy, tt,
+                                           n_here, tid, acc, round0 && tbase == 0);
+        tile_group_sum<T, NT, PX, S>(sh, tid, acc);
+        tile_store<T, PX>(a, v, tt, gid == 0, acc);
         __syncthreads();
     }
 }
 
-
-// Count: a counting instance (work counters on; a distinct kernel, so that
-// timed launches carry no counter code).
+// Hardware dispatch places block b on XCD b % 8 (see xcd_block).
 template <typename T, int NT, int PX, int S, bool Count>
-__global__ void __launch_bounds__(NT, 5)
+__global__ void __launch_bounds__(NT, kTileWaves<T>)
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
-    int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, blk);
-    blk -= v.first_block;
+    const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
+    const int blk = gb - v.first_block;
     __shared__ TileShared<T, NT> sh;
     const int tid = threadIdx.x;
     const int l = v.L;
@@ -1249,7 +1385,42 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     const int r_lo = a.edges[v.row_at + cj + 1];
     const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
     tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
-                                   k_lo, nx, r_lo, ny, tid);
+                                   k_lo, nx, r_lo, ny, tid, a.hv_list != nullptr, gb);
+}
+
+// Queued (heavy) small tiles, one per block at a time: blocks take tiles
+// from a counter until none is left; nothing waits.
+template <typename T, bool Count>
+__global__ void __launch_bounds__(kWave * kBigSplit<T>)
+k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
+           const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
+           const int2* __restrict__ owner) {
+    constexpr int S = kBigSplit<T>, NT = kWave * S;
+    __shared__ TileShared<T, NT> sh;
+    __shared__ int s_it;
+    const int tid = threadIdx.x;
+    const int nq = min(a.hv_ctl[0], a.hv_list_cap);  // final: set by k_tile
+    for (;;) {
+        if (tid == 0) s_it = atomicAdd(&a.hv_ctl[1], 1);
+        __syncthreads();
+        const int it = s_it;
+        __syncthreads();
+        if (it >= nq) return;
+        const int gb = a.hv_list[it];
+        const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
+        const int blk = gb - v.first_block;
+        const int l = v.L;
+        const long long ti = v.i0 + blk % v.wl, tj = v.j0 + blk / v.wl;
+        const int own = v.off + blk;
+        const int ci = (int)(ti - v.i0), cj = (int)(tj - v.j0);
+        const int k_lo = a.edges[v.col_at + ci];
+        const int nx = a.edges[v.col_at + ci + 1] - k_lo;
+        const int r_lo = a.edges[v.row_at + cj + 1];
+        const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
+        tile_body<T, NT, 1, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
+                                      k_lo, nx, r_lo, ny, tid);
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------ fused render kernel
@@ -1652,6 +1823,11 @@ __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
     for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[(size_t)own * (p + 1) * 3 + i] = {0, 0};
 }
 
+// Counters of the heavy-tile queue, cleared before each leaf pass.
+__global__ void k_heavy_init(int* __restrict__ ctl) {
+    if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
+}
+
 // Ticks of the device's constant-rate wall clock in about one second.
 long long wall_ticks_per_second() {
     static long long t = 0;
@@ -1788,16 +1964,30 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
         if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
         // tiles of up to 8 x 8 pixels: one pixel per lane, the near field split
-        // over kSplit waves; up to 16 x 16: two pixels per thread
+        // over kSplit waves, heavy tiles shared over the device; up to
+        // 16 x 16: two pixels per thread
         if (o.tile_px <= 8) {
-            if (stats)
-                hipLaunchKernelGGL((k_tile<T, kWave * kSplit, 1, kSplit, true>),
-                                   dim3(pl.leaf_blocks), dim3(kWave * kSplit), 0, st, tv, pv, a, p,
-                                   Ms, TL, nset, owner);
-            else
-                hipLaunchKernelGGL((k_tile<T, kWave * kSplit, 1, kSplit, false>),
-                                   dim3(pl.leaf_blocks), dim3(kWave * kSplit), 0, st, tv, pv, a, p,
-                                   Ms, TL, nset, owner);
+            DC_REQUIRE(pl.hv_list_at > 0, "render plan without the heavy-tile queue");
+            a.hv_ctl = reinterpret_cast<int*>(scratch + pl.hv_ctl_at);
+            a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
+            a.hv_list_cap = pl.leaf_blocks;
+            hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
+            DC_HIP(hipGetLastError());
+            constexpr int NT = kWave * kSplit, NB = kWave * kBigSplit<T>;
+            const int bgrid = std::min(512, pl.leaf_blocks);
+            if (stats) {
+                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks),
+                                   dim3(NT), 0, st, tv, pv, a, p, Ms, TL, nset, owner);
+                DC_HIP(hipGetLastError());
+                hipLaunchKernelGGL((k_tile_big<T, true>), dim3(bgrid), dim3(NB), 0, st, tv, pv, a,
+                                   p, Ms, TL, nset, owner);
+            } else {
+                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks),
+                                   dim3(NT), 0, st, tv, pv, a, p, Ms, TL, nset, owner);
+                DC_HIP(hipGetLastError());
+                hipLaunchKernelGGL((k_tile_big<T, false>), dim3(bgrid), dim3(NB), 0, st, tv, pv, a,
+                                   p, Ms, TL, nset, owner);
+            }
         } else {
             if (stats)
                 hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128), 0,
@@ -2080,10 +2270,15 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.tl_at = up256(pl.desc_bytes);
     pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
     pl.owner_at = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
+    const size_t nq = kFusedRender ? (size_t)total : 0;  // work queue of the fused kernel
     pl.queue_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
-    pl.ready_at = up256(pl.queue_at + (size_t)total * sizeof(QItem));
-    pl.ctl_at = up256(pl.ready_at + (size_t)total * sizeof(int));
-    pl.scratch_bytes = up256(pl.ctl_at + sizeof(QueueCtl));
+    pl.ready_at = up256(pl.queue_at + nq * sizeof(QItem));
+    pl.ctl_at = up256(pl.ready_at + nq * sizeof(int));
+    // queue of heavy small tiles (it can hold every tile)
+    const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;
+    pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
+    pl.hv_list_at = up256(pl.hv_ctl_at + 2 * sizeof(int));
+    pl.scratch_bytes = up256(pl.hv_list_at + nl * sizeof(int));
 }
 
 void RenderPlan::write_tables(void* host, void* const* outs) const {
