@@ -668,7 +668,7 @@ struct LeafArgs {
     double near2;            // (near_fp64)^2, FP32 only
     unsigned long long* stats;  // optional work counters
     // heavy small render tiles left to k_tile_big; hv_list null: none
-    int* hv_ctl;             // [0] queued tiles, [1] next to take
+    int* hv_ctl;             // [0] / [2] tiles queued at the front / back, [1] next to take
     int* hv_list;            // queued tiles (global leaf block), hv_list_cap entries
     int hv_list_cap;
 };
@@ -907,9 +907,17 @@ struct TileShared {
     int pid[NT];
     int U[kUCap], Upre[kUCap + 1], W[kWCap], Q[kQCap];
     int nU, nW, nQ, heavy;
-    // expansion coefficients staged per wave (L2P and M2P)
-    cpx<double> coef[NT / kWave][3 * (DC_P_MAX + 1)];
 };
+
+// Per-wave LDS buffers of 3 (p + 1) expansion coefficients (L2P and M2P),
+// in the dynamic shared memory of the tile kernels (tile_coef_bytes).
+__device__ inline cpx<double>* tile_coef(int p, int tid) {
+    extern __shared__ cpx<double> tile_dyn[];
+    return tile_dyn + (size_t)(tid / kWave) * 3 * (p + 1);
+}
+inline size_t tile_coef_bytes(int nt, int p) {
+    return (size_t)(nt / kWave) * 3 * (p + 1) * sizeof(cpx<double>);
+}
 
 // Near-set traversal of a target tile by one wave (lane = lane of wave 0),
 // one round: pops boxes from the stack top in chunks of up to 64, sends
@@ -1019,7 +1027,8 @@ __device__ __noinline__ Rgb pair_fp64(const double* __restrict__ x0, const doubl
 // more than kHeavyPieces<T> near pieces, or leaves more rounds to come, is
 // queued instead and evaluated by k_tile_big, whose blocks split one
 // tile's near field over kBigSplit<T> waves.
-// Waves per SIMD the tile kernels are compiled for (register budget).
+// Launch-bound occupancy argument of the one-wave tile kernel (register
+// budget; measured best).
 template <typename T>
 constexpr int kTileWaves = sizeof(T) == 4 ? 8 : 4;
 template <typename T>
@@ -1135,7 +1144,7 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
         // with Ms_k = Mt_k / k precomputed; Mt_0 (the total charge times
         // length) is real, so only log|x - c| is needed
-        cpx<double>* const src = sh.coef[tid / kWave];
+        cpx<double>* const src = tile_coef(p, tid);
         for (int u = ((gid - u_run) % S + S) % S; u < nW; u += S) {
             const int d = sh.W[u];
             stage_coef(src, Ms + (size_t)d * (p + 1) * 3, (p + 1) * 3, tid % kWave);
@@ -1330,10 +1339,15 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         __syncthreads();
         if (tid == 0) {
             int queued = 0;
-            if (sh.Upre[sh.nU] > kHeavyPieces<T> || sh.nQ > 0) {
-                const int h = atomicAdd(&a.hv_ctl[0], 1);
-                queued = h < a.hv_list_cap;  // the list holds every tile
-                if (queued) a.hv_list[h] = gb;
+            const int np = sh.Upre[sh.nU];
+            if (np > kHeavyPieces<T> || sh.nQ > 0) {
+                // the heaviest (more rounds, or 4x the pieces) from the front
+                // of the list, the others from the back; the list can hold
+                // every tile, so the two ends never meet
+                const bool front = sh.nQ > 0 || np > 4 * kHeavyPieces<T>;
+                const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
+                queued = h < a.hv_list_cap;
+                if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
             }
             sh.heavy = queued;
         }
@@ -1349,7 +1363,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         for (int q = 0; q < PX; ++q)
             for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
         if (gid == 0)
-            tile_l2p<T, PX>(tt, o.loc, p, o.lo, o.ro, o.ocx, o.ocy, sh.coef[tid / kWave],
+            tile_l2p<T, PX>(tt, o.loc, p, o.lo, o.ro, o.ocx, o.ocy, tile_coef(p, tid),
                             tid % kWave, acc);
         const int n_here = min(G * PX, n_targets - tbase);
         if (Count && tid == 0) {
@@ -1367,7 +1381,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
 
 // Hardware dispatch places block b on XCD b % 8 (see xcd_block).
 template <typename T, int NT, int PX, int S, bool Count>
-__global__ void __launch_bounds__(NT, kTileWaves<T>)
+__global__ void __launch_bounds__(NT, NT == kWave ? kTileWaves<T> : 4)
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
@@ -1399,14 +1413,16 @@ k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __re
     __shared__ TileShared<T, NT> sh;
     __shared__ int s_it;
     const int tid = threadIdx.x;
-    const int nq = min(a.hv_ctl[0], a.hv_list_cap);  // final: set by k_tile
+    // final counts, set by k_tile: the heaviest first
+    const int nf = min(a.hv_ctl[0], a.hv_list_cap);
+    const int nb = min(a.hv_ctl[2], a.hv_list_cap - nf);
     for (;;) {
         if (tid == 0) s_it = atomicAdd(&a.hv_ctl[1], 1);
         __syncthreads();
         const int it = s_it;
         __syncthreads();
-        if (it >= nq) return;
-        const int gb = a.hv_list[it];
+        if (it >= nf + nb) return;
+        const int gb = a.hv_list[it < nf ? it : a.hv_list_cap - 1 - (it - nf)];
         const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
         const int blk = gb - v.first_block;
         const int l = v.L;
@@ -1825,7 +1841,7 @@ __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
 
 // Counters of the heavy-tile queue, cleared before each leaf pass.
 __global__ void k_heavy_init(int* __restrict__ ctl) {
-    if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
+    if (threadIdx.x < 3) ctl[threadIdx.x] = 0;
 }
 
 // Ticks of the device's constant-rate wall clock in about one second.
@@ -1889,11 +1905,13 @@ void launch_fused(FmmState& f, const RenderPlan& pl, const dc_eval_opts& o, int 
     // a wave waits for its item at most ~2 s (a whole render takes far less)
     const long long wait = 2 * wall_ticks_per_second();
     if (stats)
-        hipLaunchKernelGGL((k_render_fused<T, true>), dim3(grid), dim3(kWave), 0, st, tv, pv,
+        hipLaunchKernelGGL((k_render_fused<T, true>), dim3(grid), dim3(kWave),
+                           tile_coef_bytes(kWave, p), st, tv, pv,
                            a, p, M, Ms, Ttab, TL, nset, owner, q, ready, ctl, n_slots, d_lev,
                            vlev, pl.maxL, wait, f.stall_dev);
     else
-        hipLaunchKernelGGL((k_render_fused<T, false>), dim3(grid), dim3(kWave), 0, st, tv, pv,
+        hipLaunchKernelGGL((k_render_fused<T, false>), dim3(grid), dim3(kWave),
+                           tile_coef_bytes(kWave, p), st, tv, pv,
                            a, p, M, Ms, Ttab, TL, nset, owner, q, ready, ctl, n_slots, d_lev,
                            vlev, pl.maxL, wait, f.stall_dev);
     DC_HIP(hipGetLastError());
@@ -1977,24 +1995,26 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             const int bgrid = std::min(512, pl.leaf_blocks);
             if (stats) {
                 hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks),
-                                   dim3(NT), 0, st, tv, pv, a, p, Ms, TL, nset, owner);
+                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
                 DC_HIP(hipGetLastError());
-                hipLaunchKernelGGL((k_tile_big<T, true>), dim3(bgrid), dim3(NB), 0, st, tv, pv, a,
+                hipLaunchKernelGGL((k_tile_big<T, true>), dim3(bgrid), dim3(NB),
+                                   tile_coef_bytes(NB, p), st, tv, pv, a,
                                    p, Ms, TL, nset, owner);
             } else {
                 hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks),
-                                   dim3(NT), 0, st, tv, pv, a, p, Ms, TL, nset, owner);
+                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
                 DC_HIP(hipGetLastError());
-                hipLaunchKernelGGL((k_tile_big<T, false>), dim3(bgrid), dim3(NB), 0, st, tv, pv, a,
+                hipLaunchKernelGGL((k_tile_big<T, false>), dim3(bgrid), dim3(NB),
+                                   tile_coef_bytes(NB, p), st, tv, pv, a,
                                    p, Ms, TL, nset, owner);
             }
         } else {
             if (stats)
-                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128), 0,
-                                   st, tv, pv, a, p, Ms, TL, nset, owner);
+                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128),
+                                   tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
             else
-                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128), 0,
-                                   st, tv, pv, a, p, Ms, TL, nset, owner);
+                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128),
+                                   tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
         }
         DC_HIP(hipGetLastError());
     }
@@ -2277,7 +2297,7 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     // queue of heavy small tiles (it can hold every tile)
     const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;
     pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
-    pl.hv_list_at = up256(pl.hv_ctl_at + 2 * sizeof(int));
+    pl.hv_list_at = up256(pl.hv_ctl_at + 3 * sizeof(int));
     pl.scratch_bytes = up256(pl.hv_list_at + nl * sizeof(int));
 }
 
