@@ -102,7 +102,7 @@ struct RenderPlan {
     size_t leaf_at = 0, edges_at = 0, vlev_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0;
     size_t owner_at = 0, queue_at = 0, ready_at = 0, ctl_at = 0, scratch_bytes = 0;
     // queue of heavy small tiles (8-pixel tiles only)
-    size_t hv_ctl_at = 0, hv_list_at = 0;
+    size_t hv_ctl_at = 0, hv_list_at = 0, hv_flag_at = 0;
     // Write both descriptor tables (desc_bytes) to host, with output
     // pointers outs[v].
     void write_tables(void* host, void* const* outs) const;
@@ -155,9 +155,26 @@ struct FmmState {
     // that reaches fmm_check_stall.
     int* stall_host = nullptr;
     int* stall_dev = nullptr;
+    // Second stream of the render leaf pass (queued heavy tiles run on it
+    // concurrently with the other tiles), ordered by two events against
+    // the caller's stream.  Renders of the scene on different caller
+    // streams share it, which only serialises their heavy-tile kernels.
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_scan = nullptr, ev_big = nullptr;
+    hipStream_t aux_stream() {
+        if (!aux) {
+            DC_HIP(hipEventCreateWithFlags(&ev_scan, hipEventDisableTiming));
+            DC_HIP(hipEventCreateWithFlags(&ev_big, hipEventDisableTiming));
+            DC_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+        }
+        return aux;
+    }
     ~FmmState() {
         for (hipEvent_t& e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (aux) (void)hipStreamSynchronize(aux), (void)hipStreamDestroy(aux);
+        if (ev_scan) (void)hipEventDestroy(ev_scan);
+        if (ev_big) (void)hipEventDestroy(ev_big);
         if (stall_host) (void)hipHostFree(stall_host);
     }
 };

@@ -671,6 +671,7 @@ struct LeafArgs {
     int* hv_ctl;             // [0] / [2] tiles queued at the front / back, [1] next to take
     int* hv_list;            // queued tiles (global leaf block), hv_list_cap entries
     int hv_list_cap;
+    unsigned char* hv_flag;  // per global leaf block: 1 if queued
 };
 
 template <typename T, int NT>
@@ -1025,8 +1026,9 @@ __device__ __noinline__ Rgb pair_fp64(const double* __restrict__ x0, const doubl
 // staged chunk; the value of a pixel is L2P plus the group partial sums,
 // added in group order.  A small tile whose first traversal round finds
 // more than kHeavyPieces<T> near pieces, or leaves more rounds to come, is
-// queued instead and evaluated by k_tile_big, whose blocks split one
-// tile's near field over kBigSplit<T> waves.
+// queued by k_tile_scan and evaluated by k_tile_big (on a second stream,
+// concurrently with k_tile), whose blocks split one tile's near field over
+// kBigSplit<T> waves.
 // Launch-bound occupancy argument of the one-wave tile kernel (register
 // budget; measured best).
 template <typename T>
@@ -1035,6 +1037,7 @@ template <typename T>
 constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
 template <typename T>
 constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
+constexpr int kBigBlocks = 512;  // grid of k_tile_big
 
 template <typename T, int PX>
 struct TileTargets {
@@ -1117,8 +1120,7 @@ __device__ inline void tile_near_init(TileShared<T, NT>& sh, const TreeView& tv,
 
 // Near field of a tile pass (see above): near-set traversal by wave 0 in
 // rounds bounded by the list capacities (the stack starts with the
-// distinct nonempty cells of the near set; first_round_done: the first
-// round is already in sh), then the round's separated boxes
+// distinct nonempty cells of the near set), then the round's separated boxes
 // (target-from-outgoing) and near pieces (target-from-source) of this
 // thread's group.  Adds the group's terms into acc.
 template <typename T, int NT, int PX, int S, bool Count>
@@ -1126,18 +1128,15 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const int* __restrict__ nset, int l, long long ti, long long tj,
                           int own, double cx, double cy, const TileTargets<T, PX>& tt,
-                          int n_here, int tid, double (&acc)[PX][3],
-                          bool first_round_done = false) {
+                          int n_here, int tid, double (&acc)[PX][3]) {
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
     const T* wts = weights<T>(pv);
-    if (!first_round_done) {
-        tile_near_init(sh, tv, nset, own, tid);
-        __syncthreads();
-    }
+    tile_near_init(sh, tv, nset, own, tid);
+    __syncthreads();
     int u_run = 0;
-    for (bool first = true;; first = false) {
-        if (tid < kWave && !(first && first_round_done)) tile_round(sh, tv, l, ti, tj, tid);
+    for (;;) {
+        if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
         __syncthreads();
         const int nU = sh.nU, nW = sh.nW, more = sh.nQ > 0;
         // target-from-outgoing (Eq. t-f-o), scaled:
@@ -1312,16 +1311,13 @@ __device__ inline TileOwner tile_owner(const TreeView& tv, const cpx<double>* Lc
     return o;
 }
 
-// Leaf evaluation of one tile by one block.  With share set, a heavy tile
-// of at most G * PX pixels (see above) is queued for k_tile_big (as global
-// leaf block gb) and left to it.
+// Leaf evaluation of one tile by one block.
 template <typename T, int NT, int PX, int S, bool Count>
 __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const PieceView& pv,
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
                           const int2* __restrict__ owner, const VpLeaf& v, int l, long long ti,
-                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid,
-                          bool share = false, int gb = -1) {
+                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid) {
     static_assert(NT % S == 0 && (S == 1 || (NT / S) % kWave == 0), "split groups are waves");
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
@@ -1329,32 +1325,6 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
     const TileOwner o = tile_owner(tv, Lc, owner, p, l, ti, tj, own);
-    // A shared tile is decided after the first traversal round: more than
-    // kHeavyPieces near pieces, or more rounds to come.
-    bool round0 = false;
-    if (share && !o.quiet && n_targets > 0 && n_targets <= G * PX) {
-        tile_near_init(sh, tv, nset, own, tid);
-        __syncthreads();
-        if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
-        __syncthreads();
-        if (tid == 0) {
-            int queued = 0;
-            const int np = sh.Upre[sh.nU];
-            if (np > kHeavyPieces<T> || sh.nQ > 0) {
-                // the heaviest (more rounds, or 4x the pieces) from the front
-                // of the list, the others from the back; the list can hold
-                // every tile, so the two ends never meet
-                const bool front = sh.nQ > 0 || np > 4 * kHeavyPieces<T>;
-                const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
-                queued = h < a.hv_list_cap;
-                if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
-            }
-            sh.heavy = queued;
-        }
-        __syncthreads();
-        if (sh.heavy) return;
-        round0 = true;
-    }
     for (int tbase = 0; tbase < n_targets; tbase += G * PX) {
         TileTargets<T, PX> tt;
         tile_targets<T, PX, G>(tt, v, cx, cy, k_lo, nx, r_lo, n_targets, tbase, gt);
@@ -1372,7 +1342,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         }
         if (!o.quiet)
             tile_near<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, nset, l, ti, tj, own, cx, cy, tt,
-                                           n_here, tid, acc, round0 && tbase == 0);
+                                           n_here, tid, acc);
         tile_group_sum<T, NT, PX, S>(sh, tid, acc);
         tile_store<T, PX>(a, v, tt, gid == 0, acc);
         __syncthreads();
@@ -1386,6 +1356,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
     const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    if (a.hv_flag != nullptr && a.hv_flag[gb]) return;  // queued for k_tile_big
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
     const int blk = gb - v.first_block;
     __shared__ TileShared<T, NT> sh;
@@ -1399,7 +1370,48 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     const int r_lo = a.edges[v.row_at + cj + 1];
     const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
     tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
-                                   k_lo, nx, r_lo, ny, tid, a.hv_list != nullptr, gb);
+                                   k_lo, nx, r_lo, ny, tid);
+}
+
+// First traversal round of every small tile: a heavy one (see above) is
+// queued for k_tile_big and flagged, so that k_tile leaves it.  Queuing
+// depends only on the tile's own traversal (every tile always takes the
+// same path); the two ends of the list never meet, since it can hold
+// every tile.
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
+            const int2* __restrict__ owner) {
+    __shared__ TileShared<float, kWave> sh;  // the traversal lists
+    const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
+    const int blk = gb - v.first_block;
+    const int tid = threadIdx.x;
+    const int l = v.L;
+    const long long ti = v.i0 + blk % v.wl, tj = v.j0 + blk / v.wl;
+    const int own = v.off + blk;
+    const int ci = (int)(ti - v.i0), cj = (int)(tj - v.j0);
+    const int nx = a.edges[v.col_at + ci + 1] - a.edges[v.col_at + ci];
+    const int ny = max(a.edges[v.row_at + cj] - a.edges[v.row_at + cj + 1], 0);
+    const int n_targets = nx > 0 ? nx * ny : 0;
+    int queued = 0;
+    if (owner[own].x == own && n_targets > 0 && n_targets <= kWave) {
+        tile_near_init(sh, tv, nset, own, tid);
+        __syncthreads();
+        tile_round(sh, tv, l, ti, tj, tid);
+        __syncthreads();
+        if (tid == 0) {
+            const int np = sh.Upre[sh.nU];
+            if (np > kHeavyPieces<T> || sh.nQ > 0) {
+                // the heaviest (more rounds, or 4x the pieces) from the front
+                const bool front = sh.nQ > 0 || np > 4 * kHeavyPieces<T>;
+                const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
+                queued = h < a.hv_list_cap;
+                if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
+            }
+        }
+    }
+    if (tid == 0) a.hv_flag[gb] = (unsigned char)queued;
 }
 
 // Queued (heavy) small tiles, one per block at a time: blocks take tiles
@@ -1985,29 +1997,39 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         // over kSplit waves, heavy tiles shared over the device; up to
         // 16 x 16: two pixels per thread
         if (o.tile_px <= 8) {
-            DC_REQUIRE(pl.hv_list_at > 0, "render plan without the heavy-tile queue");
+            DC_REQUIRE(pl.hv_flag_at > 0, "render plan without the heavy-tile queue");
             a.hv_ctl = reinterpret_cast<int*>(scratch + pl.hv_ctl_at);
             a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
             a.hv_list_cap = pl.leaf_blocks;
+            a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
             hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
             DC_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_tile_scan<T>, dim3(pl.leaf_blocks), dim3(kWave), 0, st, tv, a,
+                               nset, owner);
+            DC_HIP(hipGetLastError());
+            hipStream_t aux = f.aux_stream();
+            DC_HIP(hipEventRecord(f.ev_scan, st));
+            DC_HIP(hipStreamWaitEvent(aux, f.ev_scan, 0));
             constexpr int NT = kWave * kSplit, NB = kWave * kBigSplit<T>;
-            const int bgrid = std::min(512, pl.leaf_blocks);
+            const int bgrid = std::min(kBigBlocks, pl.leaf_blocks);
             if (stats) {
-                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks),
-                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-                DC_HIP(hipGetLastError());
                 hipLaunchKernelGGL((k_tile_big<T, true>), dim3(bgrid), dim3(NB),
-                                   tile_coef_bytes(NB, p), st, tv, pv, a,
-                                   p, Ms, TL, nset, owner);
-            } else {
-                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks),
-                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+                                   tile_coef_bytes(NB, p), aux, tv, pv, a, p, Ms, TL, nset, owner);
                 DC_HIP(hipGetLastError());
+                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks),
+                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL,
+                                   nset, owner);
+            } else {
                 hipLaunchKernelGGL((k_tile_big<T, false>), dim3(bgrid), dim3(NB),
-                                   tile_coef_bytes(NB, p), st, tv, pv, a,
-                                   p, Ms, TL, nset, owner);
+                                   tile_coef_bytes(NB, p), aux, tv, pv, a, p, Ms, TL, nset, owner);
+                DC_HIP(hipGetLastError());
+                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks),
+                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL,
+                                   nset, owner);
             }
+            DC_HIP(hipGetLastError());
+            DC_HIP(hipEventRecord(f.ev_big, aux));
+            DC_HIP(hipStreamWaitEvent(st, f.ev_big, 0));
         } else {
             if (stats)
                 hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128),
@@ -2298,7 +2320,8 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;
     pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
     pl.hv_list_at = up256(pl.hv_ctl_at + 3 * sizeof(int));
-    pl.scratch_bytes = up256(pl.hv_list_at + nl * sizeof(int));
+    pl.hv_flag_at = up256(pl.hv_list_at + nl * sizeof(int));
+    pl.scratch_bytes = up256(pl.hv_flag_at + nl);
 }
 
 void RenderPlan::write_tables(void* host, void* const* outs) const {
@@ -2351,7 +2374,10 @@ void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eva
     f.stage_next = (f.stage_next + 1) % FmmState::kStages;
     void* stage = ps.acquire(pl.desc_bytes);
     pl.write_tables(stage, outs);
-    if (f.scratch.n < pl.scratch_bytes) f.scratch.alloc(pl.scratch_bytes);
+    if (f.scratch.n < pl.scratch_bytes) {
+        if (f.aux) DC_HIP(hipStreamSynchronize(f.aux));  // its kernels read the old scratch
+        f.scratch.alloc(pl.scratch_bytes);
+    }
     if (o.precision == DC_PREC_F32)
         launch_render_t<float>(s, f, pl, o, out_dtype, f.scratch.p, stage, f.timing, f.stats,
                                st);
