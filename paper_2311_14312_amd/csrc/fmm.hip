@@ -333,9 +333,10 @@ struct P2LStage {
 // pieces are dealt round-robin to the groups, whose sums are reduced into
 // group 0 at the end.
 // LDS of one box of the downward pass.
-template <typename T>
+template <typename T, int E = 1>
 struct DownShared {
-    static constexpr size_t kStageM2L = 2 * 3 * kWave * sizeof(cpx<T>);
+    // E: interaction-list entries per group per staging round of M2L
+    static constexpr size_t kStageM2L = 2 * 3 * E * kWave * sizeof(cpx<T>);
     static constexpr size_t kScratch =
         sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
     // the parent's near set and its metadata
@@ -351,8 +352,8 @@ struct DownShared {
 // par) by one wave.  Writes nset[own] (unless the parent is quiet) and,
 // unless the box is quiet (render only, owner != nullptr), L[own]; returns
 // whether it was quiet.
-template <typename T, bool Count>
-__device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView& pv, int l,
+template <typename T, bool Count, int E = 1>
+__device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceView& pv, int l,
                           long long ti, long long tj, int own, int par, int p,
                           const cpx<T>* __restrict__ M, cpx<T>* __restrict__ L,
                           int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
@@ -464,12 +465,14 @@ __device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView
         }
         __syncthreads();
         const int nIL = __popcll(mask);
-        // Source coefficients of each round's ngrp entries are staged in LDS
-        // by the whole wave (coalesced), double-buffered: the loads of round
-        // b+1 are in flight while round b is computed.
-        const int per_round = ngrp * P1 * 3;  // complex values, <= 3 * kWave
+        // Source coefficients of each round's ngrp E entries are staged in
+        // LDS by the whole wave (coalesced), double-buffered: the loads of
+        // round b+1 are in flight while round b is computed.  Group g takes
+        // the round's entries g, g + ngrp, ..., so every group sums the same
+        // entries in the same order whatever E is.
+        const int per_round = ngrp * E * P1 * 3;  // complex values, <= 3 E kWave
         cpx<T>* stage = reinterpret_cast<cpx<T>*>(sh.scratch);
-        constexpr int kPer = 3;
+        constexpr int kPer = 3 * E;
         cpx<T> pre[kPer];
         auto fetch = [&](int base) {
             for (int t = 0; t < kPer; ++t) {
@@ -492,22 +495,25 @@ __device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView
             put(0);
         }
         int buf = 0;
-        for (int base = 0; base < nIL; base += ngrp) {
+        for (int base = 0; base < nIL; base += ngrp * E) {
             __syncthreads();
-            const bool next = base + ngrp < nIL;
-            if (next) fetch(base + ngrp);
-            const int e = base + grp;
-            if (glane && e < nIL) {
-                const cpx<T>* src = stage + buf * per_round + grp * P1 * 3;
-                const cpx<T>* Tk = Ttab + ((size_t)sh.To[e] * P1 + k) * P1;
-                for (int m = 0; m <= p; ++m) {
-                    const cpx<T> t = Tk[m];
-                    for (int ch = 0; ch < 3; ++ch)
-                        gacc[ch] = cadd(gacc[ch], cmul(t, src[m * 3 + ch]));
+            const bool next = base + ngrp * E < nIL;
+            if (next) fetch(base + ngrp * E);
+            for (int j = 0; j < E; ++j) {
+                const int slot = j * ngrp + grp;
+                const int e = base + slot;
+                if (glane && e < nIL) {
+                    const cpx<T>* src = stage + buf * per_round + slot * P1 * 3;
+                    const cpx<T>* Tk = Ttab + ((size_t)sh.To[e] * P1 + k) * P1;
+                    for (int m = 0; m <= p; ++m) {
+                        const cpx<T> t = Tk[m];
+                        for (int ch = 0; ch < 3; ++ch)
+                            gacc[ch] = cadd(gacc[ch], cmul(t, src[m * 3 + ch]));
+                    }
+                    if (k == 0)
+                        for (int ch = 0; ch < 3; ++ch)
+                            gacc[ch] = csub(gacc[ch], cscale(src[ch], log2r));
                 }
-                if (k == 0)
-                    for (int ch = 0; ch < 3; ++ch)
-                        gacc[ch] = csub(gacc[ch], cscale(src[ch], log2r));
             }
             if (next) put(buf ^ 1);
             buf ^= 1;
@@ -618,12 +624,13 @@ __device__ bool down_body(DownShared<T>& sh, const TreeView& tv, const PieceView
     return false;
 }
 
-template <typename T, bool Count>
+// E > 1: deeper M2L staging for levels with few boxes (same values).
+template <typename T, bool Count, int E = 1>
 __global__ void __launch_bounds__(kWave, 4)
 k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
        cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
        int2* __restrict__ owner) {
-    __shared__ DownShared<T> sh;
+    __shared__ DownShared<T, E> sh;
     const int lane = threadIdx.x;
     const int l = dl.l;
     long long ti, tj;
@@ -642,8 +649,8 @@ k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict_
         own = e.off + b;
         par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
     }
-    (void)down_body<T, Count>(sh, tv, pv, l, ti, tj, own, par, p, M, L, nset, Ttab, owner,
-                              dl.stats, lane);
+    (void)down_body<T, Count, E>(sh, tv, pv, l, ti, tj, own, par, p, M, L, nset, Ttab, owner,
+                                 dl.stats, lane);
 }
 
 template <typename T>
@@ -1038,6 +1045,7 @@ constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
 template <typename T>
 constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
 constexpr int kBigBlocks = 512;  // grid of k_tile_big
+constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_down<.., 3>
 
 template <typename T, int PX>
 struct TileTargets {
@@ -1977,9 +1985,17 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             dl.l = l;
             dl.vl = d_lev + pl.lev_begin[l];
             dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
-            if (stats)
+            // levels with few boxes are bound by one wave's latency: deeper staging
+            const bool deep = pl.lev_blocks[l] < kDeepBoxes;
+            if (stats && deep)
+                hipLaunchKernelGGL((k_down<double, true, 3>), dim3(pl.lev_blocks[l]), dim3(kWave), 0,
+                                   st, tv, pv, dl, p, M, TL, nset, Ttab, owner);
+            else if (stats)
                 hipLaunchKernelGGL((k_down<double, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
                                    tv, pv, dl, p, M, TL, nset, Ttab, owner);
+            else if (deep)
+                hipLaunchKernelGGL((k_down<double, false, 3>), dim3(pl.lev_blocks[l]), dim3(kWave),
+                                   0, st, tv, pv, dl, p, M, TL, nset, Ttab, owner);
             else
                 hipLaunchKernelGGL((k_down<double, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
                                    tv, pv, dl, p, M, TL, nset, Ttab, owner);
