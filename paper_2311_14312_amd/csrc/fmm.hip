@@ -1042,6 +1042,9 @@ template <typename T>
 constexpr int kTileWaves = sizeof(T) == 4 ? 8 : 4;
 template <typename T>
 constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
+// the same for 16-pixel tiles (up to 17 x 17 = 289 pixels, 5 per lane in k_tile_big)
+template <typename T>
+constexpr int kHeavyPieces16 = sizeof(T) == 4 ? 64 : 8;
 template <typename T>
 constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
 constexpr int kBigBlocks = 512;  // grid of k_tile_big
@@ -1264,21 +1267,19 @@ __device__ inline void tile_group_sum(TileShared<T, NT>& sh, int tid, double (&a
     if (S == 1) return;
     constexpr int G = NT / S;
     using Sh = TileShared<T, NT>;
-    static_assert((S - 1) * PX * 3 * G * sizeof(double) <= offsetof(Sh, U) - offsetof(Sh, px),
-                  "partial sums fit the staging");
+    static_assert((S - 1) * 3 * G * sizeof(double) <= offsetof(Sh, U) - offsetof(Sh, px),
+                  "partial sums of one pixel slot fit the staging");
     const int gid = tid / G, gt = tid - gid * G;
     double* red = reinterpret_cast<double*>(sh.px);
-    __syncthreads();
-    if (gid > 0)
-        for (int q = 0; q < PX; ++q)
-            for (int ch = 0; ch < 3; ++ch)
-                red[(((size_t)(gid - 1) * PX + q) * 3 + ch) * G + gt] = acc[q][ch];
-    __syncthreads();
-    if (gid == 0)
-        for (int g2 = 1; g2 < S; ++g2)
-            for (int q = 0; q < PX; ++q)
-                for (int ch = 0; ch < 3; ++ch)
-                    acc[q][ch] += red[(((size_t)(g2 - 1) * PX + q) * 3 + ch) * G + gt];
+    for (int q = 0; q < PX; ++q) {
+        __syncthreads();
+        if (gid > 0)
+            for (int ch = 0; ch < 3; ++ch) red[((size_t)(gid - 1) * 3 + ch) * G + gt] = acc[q][ch];
+        __syncthreads();
+        if (gid == 0)
+            for (int g2 = 1; g2 < S; ++g2)
+                for (int ch = 0; ch < 3; ++ch) acc[q][ch] += red[((size_t)(g2 - 1) * 3 + ch) * G + gt];
+    }
     __syncthreads();
 }
 
@@ -1386,7 +1387,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
 // depends only on the tile's own traversal (every tile always takes the
 // same path); the two ends of the list never meet, since it can hold
 // every tile.
-template <typename T>
+template <typename T, int MaxPx, int Heavy>
 __global__ void __launch_bounds__(kWave)
 k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
             const int2* __restrict__ owner) {
@@ -1403,16 +1404,16 @@ k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
     const int ny = max(a.edges[v.row_at + cj] - a.edges[v.row_at + cj + 1], 0);
     const int n_targets = nx > 0 ? nx * ny : 0;
     int queued = 0;
-    if (owner[own].x == own && n_targets > 0 && n_targets <= kWave) {
+    if (owner[own].x == own && n_targets > 0 && n_targets <= MaxPx) {
         tile_near_init(sh, tv, nset, own, tid);
         __syncthreads();
         tile_round(sh, tv, l, ti, tj, tid);
         __syncthreads();
         if (tid == 0) {
             const int np = sh.Upre[sh.nU];
-            if (np > kHeavyPieces<T> || sh.nQ > 0) {
+            if (np > Heavy || sh.nQ > 0) {
                 // the heaviest (more rounds, or 4x the pieces) from the front
-                const bool front = sh.nQ > 0 || np > 4 * kHeavyPieces<T>;
+                const bool front = sh.nQ > 0 || np > 4 * Heavy;
                 const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
                 queued = h < a.hv_list_cap;
                 if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
@@ -1422,9 +1423,9 @@ k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
     if (tid == 0) a.hv_flag[gb] = (unsigned char)queued;
 }
 
-// Queued (heavy) small tiles, one per block at a time: blocks take tiles
-// from a counter until none is left; nothing waits.
-template <typename T, bool Count>
+// Queued (heavy) tiles, one per block at a time, PX pixels per thread:
+// blocks take tiles from a counter until none is left; nothing waits.
+template <typename T, bool Count, int PX>
 __global__ void __launch_bounds__(kWave * kBigSplit<T>)
 k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
            const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
@@ -1453,8 +1454,8 @@ k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __re
         const int nx = a.edges[v.col_at + ci + 1] - k_lo;
         const int r_lo = a.edges[v.row_at + cj + 1];
         const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
-        tile_body<T, NT, 1, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
-                                      k_lo, nx, r_lo, ny, tid);
+        tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
+                                       k_lo, nx, r_lo, ny, tid);
         __syncthreads();
     }
 }
@@ -2009,52 +2010,59 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         a.nvleaf = pl.n;
         a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
         if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
-        // tiles of up to 8 x 8 pixels: one pixel per lane, the near field split
-        // over kSplit waves, heavy tiles shared over the device; up to
-        // 16 x 16: two pixels per thread
-        if (o.tile_px <= 8) {
-            DC_REQUIRE(pl.hv_flag_at > 0, "render plan without the heavy-tile queue");
-            a.hv_ctl = reinterpret_cast<int*>(scratch + pl.hv_ctl_at);
-            a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
-            a.hv_list_cap = pl.leaf_blocks;
-            a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
-            hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
-            DC_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_tile_scan<T>, dim3(pl.leaf_blocks), dim3(kWave), 0, st, tv, a,
-                               nset, owner);
-            DC_HIP(hipGetLastError());
-            hipStream_t aux = f.aux_stream();
-            DC_HIP(hipEventRecord(f.ev_scan, st));
-            DC_HIP(hipStreamWaitEvent(aux, f.ev_scan, 0));
-            constexpr int NT = kWave * kSplit, NB = kWave * kBigSplit<T>;
-            const int bgrid = std::min(kBigBlocks, pl.leaf_blocks);
-            if (stats) {
-                hipLaunchKernelGGL((k_tile_big<T, true>), dim3(bgrid), dim3(NB),
-                                   tile_coef_bytes(NB, p), aux, tv, pv, a, p, Ms, TL, nset, owner);
-                DC_HIP(hipGetLastError());
-                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks),
-                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL,
-                                   nset, owner);
-            } else {
-                hipLaunchKernelGGL((k_tile_big<T, false>), dim3(bgrid), dim3(NB),
-                                   tile_coef_bytes(NB, p), aux, tv, pv, a, p, Ms, TL, nset, owner);
-                DC_HIP(hipGetLastError());
-                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks),
-                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL,
-                                   nset, owner);
-            }
-            DC_HIP(hipGetLastError());
-            DC_HIP(hipEventRecord(f.ev_big, aux));
-            DC_HIP(hipStreamWaitEvent(st, f.ev_big, 0));
-        } else {
-            if (stats)
-                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128),
-                                   tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-            else
-                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128),
-                                   tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-        }
+        // Tiles of up to 8 x 8 pixels: one wave, a pixel per lane; up to
+        // 16 x 16: 128 threads, two pixels each.  k_tile_scan queues the
+        // heavy tiles, which k_tile skips and k_tile_big evaluates at the
+        // same time on the scene's second stream.
+        DC_REQUIRE(pl.hv_flag_at > 0, "render plan without the heavy-tile queue");
+        a.hv_ctl = reinterpret_cast<int*>(scratch + pl.hv_ctl_at);
+        a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
+        a.hv_list_cap = pl.leaf_blocks;
+        a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
+        const bool small = o.tile_px <= 8;
+        hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
         DC_HIP(hipGetLastError());
+        if (small)
+            hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>>), dim3(pl.leaf_blocks),
+                               dim3(kWave), 0, st, tv, a, nset, owner);
+        else
+            hipLaunchKernelGGL((k_tile_scan<T, 5 * kWave, kHeavyPieces16<T>>),
+                               dim3(pl.leaf_blocks), dim3(kWave), 0, st, tv, a, nset, owner);
+        DC_HIP(hipGetLastError());
+        hipStream_t aux = f.aux_stream();
+        DC_HIP(hipEventRecord(f.ev_scan, st));
+        DC_HIP(hipStreamWaitEvent(aux, f.ev_scan, 0));
+        constexpr int NT = kWave * kSplit, NB = kWave * kBigSplit<T>;
+        const int bgrid = std::min(kBigBlocks, pl.leaf_blocks);
+        const size_t lb = tile_coef_bytes(NB, p);
+        if (small && stats)
+            hipLaunchKernelGGL((k_tile_big<T, true, 1>), dim3(bgrid), dim3(NB), lb, aux, tv, pv, a,
+                               p, Ms, TL, nset, owner);
+        else if (small)
+            hipLaunchKernelGGL((k_tile_big<T, false, 1>), dim3(bgrid), dim3(NB), lb, aux, tv, pv,
+                               a, p, Ms, TL, nset, owner);
+        else if (stats)
+            hipLaunchKernelGGL((k_tile_big<T, true, 5>), dim3(bgrid), dim3(NB), lb, aux, tv, pv, a,
+                               p, Ms, TL, nset, owner);
+        else
+            hipLaunchKernelGGL((k_tile_big<T, false, 5>), dim3(bgrid), dim3(NB), lb, aux, tv, pv,
+                               a, p, Ms, TL, nset, owner);
+        DC_HIP(hipGetLastError());
+        if (small && stats)
+            hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks), dim3(NT),
+                               tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+        else if (small)
+            hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks), dim3(NT),
+                               tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+        else if (stats)
+            hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128),
+                               tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+        else
+            hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128),
+                               tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+        DC_HIP(hipGetLastError());
+        DC_HIP(hipEventRecord(f.ev_big, aux));
+        DC_HIP(hipStreamWaitEvent(st, f.ev_big, 0));
     }
     if (timed) {
         DC_HIP(hipEventRecord(f.ev[3], st));
@@ -2332,8 +2340,8 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.queue_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
     pl.ready_at = up256(pl.queue_at + nq * sizeof(QItem));
     pl.ctl_at = up256(pl.ready_at + nq * sizeof(int));
-    // queue of heavy small tiles (it can hold every tile)
-    const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;
+    // queue of heavy tiles (it can hold every tile)
+    const size_t nl = (size_t)pl.leaf_blocks;
     pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
     pl.hv_list_at = up256(pl.hv_ctl_at + 3 * sizeof(int));
     pl.hv_flag_at = up256(pl.hv_list_at + nl * sizeof(int));
