@@ -344,6 +344,7 @@ struct DownShared {
     int IL[36];              // interaction list (compacted)
     signed char To[36];      // its offset classes
     int L4[9], Pre[10], Nl4; // separated leaves and their piece offsets
+    cpx<T> PLoc[3 * (DC_P_MAX + 1)];  // the parent's local expansion (L2L)
     // shared by the M2L staging, the P2L staging and the group reduction
     __align__(16) unsigned char scratch[kScratch];
 };
@@ -366,6 +367,8 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         if (lane == 0) owner[own] = po;
         return true;
     }
+    // the parent's expansion for L2L, loaded while the near set is resolved
+    for (int i = lane; i < 3 * (p + 1); i += kWave) sh.PLoc[i] = L[(size_t)par * 3 * (p + 1) + i];
     __syncthreads();
     // Metadata of the parent's near set, loaded once by lanes 0..8; it
     // serves the near set, the interaction list and the separated leaves.
@@ -430,7 +433,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
     if (klane) {
         const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
-        const cpx<T>* src = L + (size_t)par * P1 * 3;
+        const cpx<T>* src = sh.PLoc;
         cpx<T> pw = {1, 0};
         T binom = 1;
         const T sc = (T)ldexp(1.0, -k);
