@@ -340,10 +340,10 @@ struct DownShared {
     static constexpr size_t kScratch =
         sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
     // the parent's near set and its metadata
-    int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9];
+    int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9], Pb[9];
     int IL[36];              // interaction list (compacted)
     signed char To[36];      // its offset classes
-    int L4[9], Pre[10], Nl4; // separated leaves and their piece offsets
+    int L4b[9], Pre[10], Nl4;  // separated leaves: first piece, piece offsets
     cpx<T> PLoc[3 * (DC_P_MAX + 1)];  // the parent's local expansion (L2L)
     // shared by the M2L staging, the P2L staging and the group reduction
     __align__(16) unsigned char scratch[kScratch];
@@ -374,12 +374,13 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     // serves the near set, the interaction list and the separated leaves.
     if (lane < 9) {
         const int c = sh.PN[lane];
-        int lv = -1, ch = -1, np = 0, pc = 0, tch = 1;
+        int lv = -1, ch = -1, np = 0, pc = 0, pb = 0, tch = 1;
         if (c >= 0) {
             lv = tv.lvl[c];
             ch = tv.child[c];
             np = tv.npc[c];
-            pc = tv.pend[c] - tv.pbeg[c];
+            pb = tv.pbeg[c];
+            pc = tv.pend[c] - pb;
             tch = touches(tv, c, l, ti, tj) ? 1 : 0;
         }
         sh.PL[lane] = lv;
@@ -387,6 +388,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         sh.PN2[lane] = np;
         sh.Pcnt[lane] = pc;
         sh.PT[lane] = tch;
+        sh.Pb[lane] = pb;
     }
     __syncthreads();
     // near set N(own): the 3 x 3 positions around own at level l, each the
@@ -534,7 +536,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
             bool dup = false;
             for (int s2 = 0; s2 < s; ++s2) dup |= (sh.PN[s2] == c);
             if (dup || sh.PN2[s] == 0 || sh.PT[s]) continue;
-            sh.L4[nl4] = c;
+            sh.L4b[nl4] = sh.Pb[s];
             sh.Pre[nl4 + 1] = sh.Pre[nl4] + sh.Pcnt[s];
             ++nl4;
         }
@@ -555,7 +557,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
             if (g < total) {
                 int u = 0;
                 while (u + 1 < nl4 && sh.Pre[u + 1] <= g) ++u;
-                const int e = tv.pbeg[sh.L4[u]] + (g - sh.Pre[u]);
+                const int e = sh.L4b[u] + (g - sh.Pre[u]);
                 const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
                 const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
                 const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
