@@ -517,7 +517,7 @@ def main():
     px = W * H
     err32, err64 = sample_err(img32), sample_err(img64)
     kernel_name = ("k_tile<float, 64, 1, 1, false> + k_tile_big<float, false, 1>" if tile <= 8
-                   else "k_tile<float, 128, 2, 1, false> + k_tile_big<float, false, 5>")
+                   else "k_tile<float, 128, 2, 1, false>")
     line = {
         "metric": METRIC,
         "value": px / (ms32 * 1e-3),

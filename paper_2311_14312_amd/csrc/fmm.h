@@ -101,7 +101,7 @@ struct RenderPlan {
     long long total_boxes = 0;
     size_t leaf_at = 0, edges_at = 0, vlev_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0;
     size_t owner_at = 0, queue_at = 0, ready_at = 0, ctl_at = 0, scratch_bytes = 0;
-    // queue of heavy tiles (k_tile_scan, k_tile_big)
+    // queue of heavy small tiles (k_tile_scan, k_tile_big; 8-pixel tiles)
     size_t hv_ctl_at = 0, hv_list_at = 0, hv_flag_at = 0;
     // Write both descriptor tables (desc_bytes) to host, with output
     // pointers outs[v].

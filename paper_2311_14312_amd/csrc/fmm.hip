@@ -1047,12 +1047,10 @@ template <typename T>
 constexpr int kTileWaves = sizeof(T) == 4 ? 8 : 4;
 template <typename T>
 constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
-// the same for 16-pixel tiles (up to 17 x 17 = 289 pixels, 5 per lane in k_tile_big)
-template <typename T>
-constexpr int kHeavyPieces16 = sizeof(T) == 4 ? 64 : 8;
 template <typename T>
 constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
 constexpr int kBigBlocks = 512;  // grid of k_tile_big
+constexpr int kOverlapTiles = 65536;  // renders with this many tiles overlap k_tile_big
 constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_down<.., 3>
 
 template <typename T, int PX>
@@ -2015,59 +2013,61 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
         a.nvleaf = pl.n;
         a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
         if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
-        // Tiles of up to 8 x 8 pixels: one wave, a pixel per lane; up to
-        // 16 x 16: 128 threads, two pixels each.  k_tile_scan queues the
-        // heavy tiles, which k_tile skips and k_tile_big evaluates at the
-        // same time on the scene's second stream.
-        DC_REQUIRE(pl.hv_flag_at > 0, "render plan without the heavy-tile queue");
-        a.hv_ctl = reinterpret_cast<int*>(scratch + pl.hv_ctl_at);
-        a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
-        a.hv_list_cap = pl.leaf_blocks;
-        a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
-        const bool small = o.tile_px <= 8;
-        hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
-        DC_HIP(hipGetLastError());
-        if (small)
+        // Tiles of up to 8 x 8 pixels: one wave, a pixel per lane; k_tile_scan
+        // queues the heavy tiles, which k_tile skips and k_tile_big
+        // evaluates.  Up to 16 x 16: 128 threads, two pixels each (a queue
+        // for them measured slower on the batch and serving workloads).
+        constexpr int NT = kWave * kSplit, NB = kWave * kBigSplit<T>;
+        if (o.tile_px > 8) {
+            if (stats)
+                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128),
+                                   tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+            else
+                hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128),
+                                   tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+            DC_HIP(hipGetLastError());
+        } else {
+            DC_REQUIRE(pl.hv_flag_at > 0, "render plan without the heavy-tile queue");
+            a.hv_ctl = reinterpret_cast<int*>(scratch + pl.hv_ctl_at);
+            a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
+            a.hv_list_cap = pl.leaf_blocks;
+            a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
+            hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
+            DC_HIP(hipGetLastError());
             hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>>), dim3(pl.leaf_blocks),
                                dim3(kWave), 0, st, tv, a, nset, owner);
-        else
-            hipLaunchKernelGGL((k_tile_scan<T, 5 * kWave, kHeavyPieces16<T>>),
-                               dim3(pl.leaf_blocks), dim3(kWave), 0, st, tv, a, nset, owner);
-        DC_HIP(hipGetLastError());
-        hipStream_t aux = f.aux_stream();
-        DC_HIP(hipEventRecord(f.ev_scan, st));
-        DC_HIP(hipStreamWaitEvent(aux, f.ev_scan, 0));
-        constexpr int NT = kWave * kSplit, NB = kWave * kBigSplit<T>;
-        const int bgrid = std::min(kBigBlocks, pl.leaf_blocks);
-        const size_t lb = tile_coef_bytes(NB, p);
-        if (small && stats)
-            hipLaunchKernelGGL((k_tile_big<T, true, 1>), dim3(bgrid), dim3(NB), lb, aux, tv, pv, a,
-                               p, Ms, TL, nset, owner);
-        else if (small)
-            hipLaunchKernelGGL((k_tile_big<T, false, 1>), dim3(bgrid), dim3(NB), lb, aux, tv, pv,
-                               a, p, Ms, TL, nset, owner);
-        else if (stats)
-            hipLaunchKernelGGL((k_tile_big<T, true, 5>), dim3(bgrid), dim3(NB), lb, aux, tv, pv, a,
-                               p, Ms, TL, nset, owner);
-        else
-            hipLaunchKernelGGL((k_tile_big<T, false, 5>), dim3(bgrid), dim3(NB), lb, aux, tv, pv,
-                               a, p, Ms, TL, nset, owner);
-        DC_HIP(hipGetLastError());
-        if (small && stats)
-            hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks), dim3(NT),
-                               tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-        else if (small)
-            hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks), dim3(NT),
-                               tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-        else if (stats)
-            hipLaunchKernelGGL((k_tile<T, 128, 2, 1, true>), dim3(pl.leaf_blocks), dim3(128),
-                               tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-        else
-            hipLaunchKernelGGL((k_tile<T, 128, 2, 1, false>), dim3(pl.leaf_blocks), dim3(128),
-                               tile_coef_bytes(128, p), st, tv, pv, a, p, Ms, TL, nset, owner);
-        DC_HIP(hipGetLastError());
-        DC_HIP(hipEventRecord(f.ev_big, aux));
-        DC_HIP(hipStreamWaitEvent(st, f.ev_big, 0));
+            DC_HIP(hipGetLastError());
+            // large renders: queued tiles on the second stream, concurrently
+            // with k_tile; small ones keep everything on st, so renders on
+            // different caller streams do not queue behind one another on it
+            const bool overlap = pl.leaf_blocks >= kOverlapTiles;
+            hipStream_t aux = overlap ? f.aux_stream() : st;
+            if (overlap) {
+                DC_HIP(hipEventRecord(f.ev_scan, st));
+                DC_HIP(hipStreamWaitEvent(aux, f.ev_scan, 0));
+            }
+            const int bgrid = std::min(kBigBlocks, pl.leaf_blocks);
+            const size_t lb = tile_coef_bytes(NB, p);
+            if (stats)
+                hipLaunchKernelGGL((k_tile_big<T, true, 1>), dim3(bgrid), dim3(NB), lb, aux, tv, pv,
+                                   a, p, Ms, TL, nset, owner);
+            else
+                hipLaunchKernelGGL((k_tile_big<T, false, 1>), dim3(bgrid), dim3(NB), lb, aux, tv,
+                                   pv, a, p, Ms, TL, nset, owner);
+            DC_HIP(hipGetLastError());
+            if (stats)
+                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, true>), dim3(pl.leaf_blocks), dim3(NT),
+                                   tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset, owner);
+            else
+                hipLaunchKernelGGL((k_tile<T, NT, 1, kSplit, false>), dim3(pl.leaf_blocks),
+                                   dim3(NT), tile_coef_bytes(NT, p), st, tv, pv, a, p, Ms, TL, nset,
+                                   owner);
+            DC_HIP(hipGetLastError());
+            if (overlap) {
+                DC_HIP(hipEventRecord(f.ev_big, aux));
+                DC_HIP(hipStreamWaitEvent(st, f.ev_big, 0));
+            }
+        }
     }
     if (timed) {
         DC_HIP(hipEventRecord(f.ev[3], st));
@@ -2346,7 +2346,7 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.ready_at = up256(pl.queue_at + nq * sizeof(QItem));
     pl.ctl_at = up256(pl.ready_at + nq * sizeof(int));
     // queue of heavy tiles (it can hold every tile)
-    const size_t nl = (size_t)pl.leaf_blocks;
+    const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;
     pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
     pl.hv_list_at = up256(pl.hv_ctl_at + 3 * sizeof(int));
     pl.hv_flag_at = up256(pl.hv_list_at + nl * sizeof(int));
