@@ -69,3 +69,46 @@ def test_c2_solve_and_render(scene, gold):
     assert rep["converged"]
     assert e32 <= 1e-4
     assert e64 <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def scene4(gpu_lib, gold):
+    """The same scene with leaf capacity 4, the configuration bench.py selects."""
+    sc = scenegen.sized_scene(n_curves=CFG["n_curves"], n_stops=CFG["n_stops"],
+                              seed=CFG["seed"])
+    s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=CFG["panels"],
+                      gl=CFG["gl"], segs=CFG["segs"], leaf_max=4)
+    s.set_densities(gold["sigma"])
+    yield s
+    s.close()
+
+
+def test_c2_render_bench_configuration(scene4, gold):
+    """Leaf 4, 8-pixel tiles, FP32 p = 12 and FP64 p = 20: the timed step."""
+    import torch
+    img32 = scene4.render(VP, method="fmm", precision="f32", p=12, tile_px=8).cpu().numpy()
+    img64 = scene4.render(VP, out_dtype=torch.float64, method="fmm", precision="f64", p=20,
+                          tile_px=8).cpu().numpy()
+    e32, e64 = _err(img32, gold), _err(img64, gold)
+    print(f"C2 bench configuration vs oracle: FP32 p=12 {e32:.3e}  FP64 p=20 {e64:.3e}",
+          flush=True)
+    assert e32 <= 1e-4
+    assert e64 <= 1e-6
+
+
+@pytest.mark.parametrize("prec,p", [("f32", 12), ("f64", 20)])
+def test_c2_heavy_tiles_same_on_both_launch_paths(scene4, gold, prec, p):
+    """A 2048^2 render (72,900 tiles) evaluates its queued heavy tiles on the
+    scene's second stream, a 256^2 one on the caller's stream: the same
+    viewport alone and inside the large batch must agree bit for bit."""
+    import torch
+    dt = torch.float64 if prec == "f64" else torch.float32
+    q = gold["node_xy"][1234]
+    small = (float(q[0]), float(q[1]), 2e-3, 2e-3, 256, 256)
+    ev = dict(out_dtype=dt, method="fmm", precision=prec, p=p, tile_px=8)
+    outs = scene4.render_batch([VP, small], **ev)
+    alone_small = scene4.render(small, **ev)
+    alone_big = scene4.render(VP, **ev)
+    assert torch.equal(outs[1], alone_small)
+    assert torch.equal(outs[0], alone_big)
+    assert torch.isfinite(alone_small).all()
