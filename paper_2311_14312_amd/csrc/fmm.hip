@@ -1368,7 +1368,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
     const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    if (a.hv_flag != nullptr && a.hv_flag[gb]) return;  // queued for k_tile_big
+    if (a.hv_flag != nullptr && a.hv_flag[gb]) return;  // done by k_tile_scan or queued
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
     const int blk = gb - v.first_block;
     __shared__ TileShared<T, NT> sh;
@@ -1385,16 +1385,17 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                                    k_lo, nx, r_lo, ny, tid);
 }
 
-// First traversal round of every small tile: a heavy one (see above) is
-// queued for k_tile_big and flagged, so that k_tile leaves it.  Queuing
-// depends only on the tile's own traversal (every tile always takes the
-// same path); the two ends of the list never meet, since it can hold
-// every tile.
-template <typename T, int MaxPx, int Heavy>
+// First pass over every small tile.  A quiet tile (see k_down) is
+// evaluated here (its owner's expansion at its pixels, the same arithmetic
+// as in tile_body) and flagged done; a heavy one (see above) is queued for
+// k_tile_big and flagged; k_tile leaves flagged tiles.  Queuing depends
+// only on the tile's own traversal (every tile always takes the same
+// path); the two ends of the list never meet, since it can hold every tile.
+template <typename T, int MaxPx, int Heavy, bool Count>
 __global__ void __launch_bounds__(kWave)
-k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
-            const int2* __restrict__ owner) {
-    __shared__ TileShared<float, kWave> sh;  // the traversal lists
+k_tile_scan(TreeView tv, LeafArgs a, int p, const cpx<double>* __restrict__ Lc,
+            const int* __restrict__ nset, const int2* __restrict__ owner) {
+    __shared__ TileShared<float, 1> sh;  // the traversal lists only
     const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
     const int blk = gb - v.first_block;
@@ -1403,11 +1404,31 @@ k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
     const long long ti = v.i0 + blk % v.wl, tj = v.j0 + blk / v.wl;
     const int own = v.off + blk;
     const int ci = (int)(ti - v.i0), cj = (int)(tj - v.j0);
-    const int nx = a.edges[v.col_at + ci + 1] - a.edges[v.col_at + ci];
-    const int ny = max(a.edges[v.row_at + cj] - a.edges[v.row_at + cj + 1], 0);
+    const int k_lo = a.edges[v.col_at + ci];
+    const int nx = a.edges[v.col_at + ci + 1] - k_lo;
+    const int r_lo = a.edges[v.row_at + cj + 1];
+    const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
     const int n_targets = nx > 0 ? nx * ny : 0;
-    int queued = 0;
-    if (owner[own].x == own && n_targets > 0 && n_targets <= MaxPx) {
+    int flag = 0;
+    if (owner[own].x != own) {
+        // quiet: no near field
+        double cx, cy;
+        center_of(tv, l, ti, tj, cx, cy);
+        const TileOwner o = tile_owner(tv, Lc, owner, p, l, ti, tj, own);
+        for (int tbase = 0; tbase < n_targets; tbase += kWave) {
+            TileTargets<T, 1> tt;
+            tile_targets<T, 1, kWave>(tt, v, cx, cy, k_lo, nx, r_lo, n_targets, tbase, tid);
+            double acc[1][3] = {{0.0, 0.0, 0.0}};
+            tile_l2p<T, 1>(tt, o.loc, p, o.lo, o.ro, o.ocx, o.ocy, tile_coef(p, tid), tid, acc);
+            if (Count && tid == 0) {
+                const int n_here = min(kWave, n_targets - tbase);
+                if (o.lo >= 2) atomicAdd(a.stats + kStatL2P, (unsigned long long)n_here);
+                if (tbase == 0) atomicAdd(a.stats + kStatLeaf, 1ULL);
+            }
+            tile_store<T, 1>(a, v, tt, true, acc);
+        }
+        flag = 2;
+    } else if (n_targets > 0 && n_targets <= MaxPx) {
         tile_near_init(sh, tv, nset, own, tid);
         __syncthreads();
         tile_round(sh, tv, l, ti, tj, tid);
@@ -1418,12 +1439,13 @@ k_tile_scan(TreeView tv, LeafArgs a, const int* __restrict__ nset,
                 // the heaviest (more rounds, or 4x the pieces) from the front
                 const bool front = sh.nQ > 0 || np > 4 * Heavy;
                 const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
-                queued = h < a.hv_list_cap;
+                const bool queued = h < a.hv_list_cap;
                 if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
+                flag = queued ? 1 : 0;
             }
         }
     }
-    if (tid == 0) a.hv_flag[gb] = (unsigned char)queued;
+    if (tid == 0) a.hv_flag[gb] = (unsigned char)flag;
 }
 
 // Queued (heavy) tiles, one per block at a time, PX pixels per thread:
@@ -2034,8 +2056,14 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
             hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
             DC_HIP(hipGetLastError());
-            hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>>), dim3(pl.leaf_blocks),
-                               dim3(kWave), 0, st, tv, a, nset, owner);
+            if (stats)
+                hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>, true>),
+                                   dim3(pl.leaf_blocks), dim3(kWave), tile_coef_bytes(kWave, p), st,
+                                   tv, a, p, TL, nset, owner);
+            else
+                hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>, false>),
+                                   dim3(pl.leaf_blocks), dim3(kWave), tile_coef_bytes(kWave, p), st,
+                                   tv, a, p, TL, nset, owner);
             DC_HIP(hipGetLastError());
             // large renders: queued tiles on the second stream, concurrently
             // with k_tile; small ones keep everything on st, so renders on
