@@ -176,13 +176,16 @@ int dc_apply_operator(dc_scene s, const double* x_dev, double* y_dev,
  * densities.  Every pixel centre must lie inside the quadtree root.
  * Asynchronous on stream.  Renders of one scene share its device scratch:
  * when they are issued on different streams the caller orders them (the
- * server below has scratch of its own). */
+ * server below has scratch of its own).  A large render (8-pixel tiles,
+ * at least 65,536 of them) runs part of its pixel pass on a second stream
+ * of the scene; that work is joined back into stream by an event before
+ * the call returns, so stream alone orders the result. */
 int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
               int out_dtype, void* out_dev, void* stream);
 
 /* Alg. 4 for n viewports of one scene in one set of launches: one
  * downward launch per quadtree level covers every viewport that reaches
- * that level and one leaf launch covers every viewport's pixel tiles (the
+ * that level and one leaf pass covers every viewport's pixel tiles (the
  * viewports are independent, so this is a batching of Alg. 4, not a change
  * of what it computes).  vps[v] and outs[v] (device [H][W][3], FP32 or FP64
  * per out_dtype) as in dc_render; each image equals dc_render of its
