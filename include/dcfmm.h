@@ -224,6 +224,27 @@ typedef struct {
 int dc_render_counts(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
                      dc_work_counts* counts, void* stream);
 
+/* Repeated renders without per-call launch work: the launches of one
+ * dc_render_batch (same arguments; FMM only) captured into a HIP graph that
+ * dc_render_graph_launch replays on a stream, for callers that render the
+ * same viewports into the same output buffers again and again (frames of
+ * an unchanged view, benchmarks).  The graph owns its plan, descriptor
+ * tables and device scratch, so it does not share scratch with dc_render;
+ * outs[v] must stay allocated while the graph exists.  The scene's
+ * densities must be set; the upward pass for o's order and precision is
+ * done (and waited for) during the call.  Launch fails with
+ * DC_ERR_INVALID when the densities changed since the capture, or when the
+ * resident expansions were rebuilt for another order or precision (a
+ * render with other options; their buffers may have moved): make the
+ * graph again.  Not for a scene registered with a server.  Destroy waits
+ * for the device. */
+typedef struct dc_render_graph_s* dc_render_graph;
+int dc_render_graph_create(dc_scene s, const dc_viewport* vps, int n,
+                           const dc_eval_opts* o, int out_dtype,
+                           void* const* outs_dev, dc_render_graph* out);
+int dc_render_graph_launch(dc_render_graph g, void* stream);
+void dc_render_graph_destroy(dc_render_graph g);
+
 /* Per-phase timing of dc_render with HIP events on the caller's stream.
  * While enabled every dc_render waits for its own completion.
  * dc_get_timing fills ms[5] = {upward, downward, leaf, total (ms, summed

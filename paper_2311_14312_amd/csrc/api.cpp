@@ -475,6 +475,48 @@ int dc_eval_points(dc_scene s, const double* xy, int n, const dc_eval_opts* o, i
     });
 }
 
+struct dc_render_graph_s {
+    std::unique_ptr<dc::RenderGraph> g;
+};
+
+int dc_render_graph_create(dc_scene s, const dc_viewport* vps, int n, const dc_eval_opts* o,
+                           int out_dtype, void* const* outs, dc_render_graph* out) {
+    return guarded([&] {
+        DC_REQUIRE(s && vps && outs && out && n >= 1, "bad argument");
+        *out = nullptr;
+        check_eval(o);
+        check_not_served(s);
+        DC_REQUIRE(o->method == DC_METHOD_FMM, "a render graph is an FMM path");
+        DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
+        for (int v = 0; v < n; ++v) {
+            const dc_viewport* vp = &vps[v];
+            DC_REQUIRE(outs[v], "null output");
+            DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0 &&
+                           std::isfinite(vp->cx) && std::isfinite(vp->cy) &&
+                           std::isfinite(vp->width) && std::isfinite(vp->height),
+                       "bad viewport");
+        }
+        DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
+        auto h = std::make_unique<dc_render_graph_s>();
+        h->g = fmm_graph_create(*s, vps, n, *o, out_dtype, outs);
+        *out = h.release();
+    });
+}
+
+int dc_render_graph_launch(dc_render_graph g, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(g && g->g, "bad argument");
+        check_not_served(g->g->s);
+        fmm_graph_launch(*g->g, as_stream(stream));
+    });
+}
+
+void dc_render_graph_destroy(dc_render_graph g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    delete g;
+}
+
 int dc_render_counts(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
                      dc_work_counts* counts, void* stream) {
     return guarded([&] {

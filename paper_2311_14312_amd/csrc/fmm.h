@@ -132,8 +132,10 @@ struct FmmState {
     // (see m2l_table in fmm.hip).
     std::map<int, std::unique_ptr<DevBuf<double>>> m2l_tab;
     DevBuf<int> nsetS;
-    // Upward pass of the resident densities (render reuses it).
+    // Upward pass of the resident densities (render reuses it); gen counts
+    // the density changes (a captured render graph records it).
     bool up_valid = false;
+    unsigned long long gen = 0;
     int up_p = -1, up_prec = -1;
     // Render of the dc_render / dc_render_batch calls: plan, descriptor
     // staging and device scratch (see RenderPlan).
@@ -180,6 +182,37 @@ struct FmmState {
 };
 
 std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s);
+
+// A render of fixed viewports and output buffers captured into a HIP
+// graph (with its own plan, pinned descriptor tables and device scratch).
+struct RenderGraph {
+    dc_scene_s* s = nullptr;
+    dc_eval_opts o{};
+    int out_dtype = 0;
+    unsigned long long gen = 0;
+    const void* M64 = nullptr;   // the resident expansion buffers the
+    const void* Ms64 = nullptr;  // captured launches read
+    RenderPlan plan;
+    void* stage = nullptr;
+    DevBuf<char> scratch;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    RenderGraph() = default;
+    RenderGraph(const RenderGraph&) = delete;
+    RenderGraph& operator=(const RenderGraph&) = delete;
+    ~RenderGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (stage) (void)hipHostFree(stage);
+    }
+};
+std::unique_ptr<RenderGraph> fmm_graph_create(dc_scene_s& s, const dc_viewport* vps, int n,
+                                              const dc_eval_opts& o, int out_dtype,
+                                              void* const* outs);
+// Throws DC_ERR_INVALID when the scene's densities changed since the
+// capture, or its resident expansions were rebuilt for another order or
+// precision (their buffers may have moved: the graph must be made again).
+void fmm_graph_launch(RenderGraph& g, hipStream_t st);
 // Throws DC_ERR_TIMEOUT (and clears the word) when an earlier render of the
 // scene stalled on the device; its images are then incomplete.
 void fmm_check_stall(FmmState& f);

@@ -2185,7 +2185,10 @@ std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s) {
     return f;
 }
 
-void fmm_invalidate(FmmState& f) { f.up_valid = false; }
+void fmm_invalidate(FmmState& f) {
+    f.up_valid = false;
+    f.gen++;
+}
 
 void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
                        dc_work_counts* counts, hipStream_t st) {
@@ -2419,6 +2422,66 @@ void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int
                 void* out, hipStream_t st) {
     void* outs[1] = {out};
     fmm_render_batch(s, &vp, 1, o, out_dtype, outs, st);
+}
+
+std::unique_ptr<RenderGraph> fmm_graph_create(dc_scene_s& s, const dc_viewport* vps, int n,
+                                              const dc_eval_opts& o, int out_dtype,
+                                              void* const* outs) {
+    FmmState& f = *s.fmm;
+    fmm_check_stall(f);
+    auto g = std::make_unique<RenderGraph>();
+    g->s = &s;
+    g->o = o;
+    g->out_dtype = out_dtype;
+    plan_render(f, vps, n, o.tile_px, o.p, g->plan);
+    DC_HIP(hipHostMalloc(&g->stage, g->plan.desc_bytes, hipHostMallocDefault));
+    g->plan.write_tables(g->stage, outs);
+    g->scratch.alloc(g->plan.scratch_bytes);
+    // everything the launches need but do not make, made now: the upward
+    // pass, the operator table and the second stream
+    hipStream_t cap = nullptr;
+    DC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    try {
+        fmm_prepare(s, o, cap);
+        DC_HIP(hipStreamSynchronize(cap));
+        (void)f.aux_stream();
+        g->gen = f.gen;
+        g->M64 = f.M64.p;
+        g->Ms64 = f.Ms64.p;
+        DC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        try {
+            if (o.precision == DC_PREC_F32)
+                launch_render_t<float>(s, f, g->plan, o, out_dtype, g->scratch.p, g->stage, false,
+                                       nullptr, cap);
+            else
+                launch_render_t<double>(s, f, g->plan, o, out_dtype, g->scratch.p, g->stage, false,
+                                        nullptr, cap);
+        } catch (...) {
+            hipGraph_t partial = nullptr;
+            (void)hipStreamEndCapture(cap, &partial);
+            if (partial) (void)hipGraphDestroy(partial);
+            throw;
+        }
+        DC_HIP(hipStreamEndCapture(cap, &g->graph));
+        DC_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    } catch (...) {
+        (void)hipStreamDestroy(cap);
+        throw;
+    }
+    DC_HIP(hipStreamDestroy(cap));
+    return g;
+}
+
+void fmm_graph_launch(RenderGraph& g, hipStream_t st) {
+    FmmState& f = *g.s->fmm;
+    fmm_check_stall(f);
+    const int prec = g.o.precision == DC_PREC_F32 ? 4 : 8;
+    DC_REQUIRE(f.gen == g.gen, "the scene's densities changed since the render graph was made");
+    DC_REQUIRE(f.up_valid && f.up_p == g.o.p && f.up_prec == prec && f.M64.p == g.M64 &&
+                   f.Ms64.p == g.Ms64,
+               "the scene's resident expansions were rebuilt since the render graph was made "
+               "(make the graph again)");
+    DC_HIP(hipGraphLaunch(g.exec, st));
 }
 
 void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,

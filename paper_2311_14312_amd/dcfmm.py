@@ -64,6 +64,45 @@ class WorkCounts(C.Structure):
                 ("levels", C.c_int), ("p", C.c_int)]
 
 
+class RenderGraph:
+    """Launches of one batched render captured into a HIP graph
+    (dc_render_graph_*): launch() renders the same viewports into the same
+    output tensors (self.outs) again."""
+
+    def __init__(self, scene, viewports, outs=None, out_dtype=None, **ev):
+        import torch
+        n = len(viewports)
+        vps = (Viewport * n)()
+        for i, (cx, cy, w, h, W, H) in enumerate(viewports):
+            vps[i] = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        if outs is None:
+            outs = [torch.empty((int(v[5]), int(v[4]), 3), device="cuda",
+                                dtype=out_dtype or torch.float32) for v in viewports]
+        assert len(outs) == n and len({o.dtype for o in outs}) == 1
+        for o, v in zip(outs, viewports):
+            assert o.is_cuda and o.is_contiguous() and tuple(o.shape) == (v[5], v[4], 3)
+        code = {torch.float32: OUT_F32, torch.float64: OUT_F64}[outs[0].dtype]
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        o = eval_opts(**ev)
+        h = C.c_void_p()
+        _check(_lib.dc_render_graph_create(scene._h, vps, n, C.byref(o), code, ptrs, C.byref(h)))
+        self._h = h
+        self.scene = scene
+        self.outs = outs
+
+    def launch(self):
+        _check(_lib.dc_render_graph_launch(self._h, _stream()))
+        return self.outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.dc_render_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("eval", EvalOpts), ("out_dtype", C.c_int), ("n_streams", C.c_int),
                 ("max_batch", C.c_int), ("max_batch_pixels", C.c_longlong),
@@ -114,6 +153,10 @@ def _load():
         "dc_eval_points": (I, [P, V, I, C.POINTER(EvalOpts), I, V, V]),
         "dc_render_counts": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts),
                                  C.POINTER(WorkCounts), V]),
+        "dc_render_graph_create": (I, [P, C.POINTER(Viewport), I, C.POINTER(EvalOpts), I,
+                                       C.POINTER(V), C.POINTER(P)]),
+        "dc_render_graph_launch": (I, [P, V]),
+        "dc_render_graph_destroy": (None, [P]),
         "dc_set_timing": (I, [P, I]),
         "dc_get_timing": (I, [P, dp]),
         "dc_default_server_opts": (None, [C.POINTER(ServerOpts)]),
@@ -297,6 +340,11 @@ class Scene:
         o = eval_opts(**ev)
         _check(_lib.dc_render_batch(self._h, vps, n, C.byref(o), code, ptrs, _stream()))
         return outs
+
+    def render_graph(self, viewports, outs=None, out_dtype=None, **ev):
+        """A RenderGraph that replays render_batch(viewports, outs) (see
+        dc_render_graph_create)."""
+        return RenderGraph(self, viewports, outs, out_dtype, **ev)
 
     def eval_points(self, xy, out_dtype=None, **ev):
         """Representation at points xy (torch cuda float64 [n, 2]) -> [n, 3]."""
