@@ -344,9 +344,12 @@ struct DownShared {
     int IL[36];              // interaction list (compacted)
     signed char To[36];      // its offset classes
     int L4b[9], Pre[10], Nl4;  // separated leaves: first piece, piece offsets
-    cpx<T> PLoc[3 * (DC_P_MAX + 1)];  // the parent's local expansion (L2L)
-    // shared by the M2L staging, the P2L staging and the group reduction
+    // Shared in turn by the parent's local expansion (read by L2L, which
+    // every lane finishes before the barrier that ends the interaction
+    // list), the M2L staging, the P2L staging and the group reduction.
     __align__(16) unsigned char scratch[kScratch];
+    static_assert(kScratch >= 3 * (DC_P_MAX + 1) * sizeof(cpx<T>), "scratch holds the parent's L");
+    __device__ cpx<T>* ploc() { return reinterpret_cast<cpx<T>*>(scratch); }
 };
 
 // Downward pass of one target box (own, at level l, cell (ti, tj), parent
@@ -368,7 +371,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         return true;
     }
     // the parent's expansion for L2L, loaded while the near set is resolved
-    for (int i = lane; i < 3 * (p + 1); i += kWave) sh.PLoc[i] = L[(size_t)par * 3 * (p + 1) + i];
+    for (int i = lane; i < 3 * (p + 1); i += kWave) sh.ploc()[i] = L[(size_t)par * 3 * (p + 1) + i];
     __syncthreads();
     // Metadata of the parent's near set, loaded once by lanes 0..8; it
     // serves the near set, the interaction list and the separated leaves.
@@ -435,7 +438,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
     if (klane) {
         const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
-        const cpx<T>* src = sh.PLoc;
+        const cpx<T>* src = sh.ploc();
         cpx<T> pw = {1, 0};
         T binom = 1;
         const T sc = (T)ldexp(1.0, -k);
