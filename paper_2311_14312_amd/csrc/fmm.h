@@ -114,6 +114,7 @@ struct FmmState {
     double X0 = 0, Y0 = 0, side = 1;
     std::vector<int> level_start;
     DevBuf<int> lvl, child, parent, pbeg, pend, npc, nbeg, nend, node_perm, target_leaves;
+    DevBuf<int> cmask;  // per box: bit q set when child q holds pieces (0 for leaves)
     DevBuf<long long> ix, iy;
     // Pieces: start point, unit tangent, length, end point, segment.
     DevBuf<double> px0, py0, px1, py1, ptx, pty, plen;

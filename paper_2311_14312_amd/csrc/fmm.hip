@@ -63,6 +63,7 @@ struct TreeView {
     double X0, Y0, side;
     const int *lvl, *child, *parent, *pbeg, *pend, *npc, *nbeg, *nend, *node_perm;
     const long long *ix, *iy;
+    const int* cmask;  // bit q: child q holds pieces
 };
 
 struct PieceView {
@@ -340,7 +341,7 @@ struct DownShared {
     static constexpr size_t kScratch =
         sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
     // the parent's near set and its metadata
-    int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9], Pb[9];
+    int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9], Pb[9], PM[9];
     int IL[36];              // interaction list (compacted)
     signed char To[36];      // its offset classes
     int L4b[9], Pre[10], Nl4;  // separated leaves: first piece, piece offsets
@@ -377,11 +378,12 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     // serves the near set, the interaction list and the separated leaves.
     if (lane < 9) {
         const int c = sh.PN[lane];
-        int lv = -1, ch = -1, np = 0, pc = 0, pb = 0, tch = 1;
+        int lv = -1, ch = -1, np = 0, pc = 0, pb = 0, tch = 1, pm = 0;
         if (c >= 0) {
             lv = tv.lvl[c];
             ch = tv.child[c];
             np = tv.npc[c];
+            pm = tv.cmask[c];
             pb = tv.pbeg[c];
             pc = tv.pend[c] - pb;
             tch = touches(tv, c, l, ti, tj) ? 1 : 0;
@@ -392,6 +394,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         sh.Pcnt[lane] = pc;
         sh.PT[lane] = tch;
         sh.Pb[lane] = pb;
+        sh.PM[lane] = pm;
     }
     __syncthreads();
     // near set N(own): the 3 x 3 positions around own at level l, each the
@@ -462,7 +465,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                 d = sh.PC[sl] + q;
                 const int dx = (int)(2 * ppx + (q & 1) - ti), dy = (int)(2 * ppy + (q >> 1) - tj);
                 o = (dy + 3) * 7 + (dx + 3);
-                valid = !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) && tv.npc[d] > 0;
+                valid = !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) && ((sh.PM[sl] >> q) & 1);
             }
         }
         const unsigned long long mask = __ballot(valid);
@@ -764,14 +767,15 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                 int nU = 0, nW = 0;
                 while (sh.nS > 0 && nU < kUCap && nW + 4 <= kWCap) {
                     const int c = sh.stack[--sh.nS];
-                    if (tv.child[c] < 0) {
+                    const int c0 = tv.child[c], cm = tv.cmask[c];
+                    if (c0 < 0) {
                         sh.Upre[nU] = 0;
                         sh.U[nU++] = c;
                         continue;
                     }
                     for (int q = 0; q < 4; ++q) {
-                        const int d = tv.child[c] + q;
-                        if (tv.npc[d] == 0) continue;
+                        const int d = c0 + q;
+                        if (!((cm >> q) & 1)) continue;
                         if (touches(tv, d, l, ti, tj)) {
                             if (sh.nS < kSCap) sh.stack[sh.nS++] = d;
                         } else {
@@ -956,12 +960,13 @@ __device__ void tile_round(TileShared<T, NT>& sh, const TreeView& tv, int l, lon
         if (lane < chunk) {
             c = sh.Q[b0 + lane];
             ch0 = tv.child[c];
+            const int cm = tv.cmask[c];  // loaded with the child index
             if (ch0 < 0) {
                 isU = 1;
             } else {
                 for (int q = 0; q < 4; ++q) {
+                    if (!((cm >> q) & 1)) continue;  // no pieces below
                     const int d = ch0 + q;
-                    if (tv.npc[d] == 0) continue;
                     if (touches(tv, d, l, ti, tj)) fm |= 1 << q; else wm |= 1 << q;
                 }
             }
@@ -1694,7 +1699,7 @@ k_self_correct(int N, const double* __restrict__ nx, const double* __restrict__ 
 
 TreeView tree_view(const FmmState& f) {
     return {f.n_cells, f.X0, f.Y0, f.side, f.lvl.p, f.child.p, f.parent.p, f.pbeg.p,
-            f.pend.p, f.npc.p, f.nbeg.p, f.nend.p, f.node_perm.p, f.ix.p, f.iy.p};
+            f.pend.p, f.npc.p, f.nbeg.p, f.nend.p, f.node_perm.p, f.ix.p, f.iy.p, f.cmask.p};
 }
 PieceView piece_view(const FmmState& f) {
     return {f.n_pieces, f.px0.p, f.py0.p, f.px1.p, f.py1.p, f.ptx.p, f.pty.p, f.plen.p, f.pseg.p,
@@ -2149,6 +2154,13 @@ std::unique_ptr<FmmState> fmm_create(const dc_scene_s& s) {
     f->pbeg.upload(T.pbeg);
     f->pend.upload(T.pend);
     f->npc.upload(T.npc);
+    {
+        std::vector<int> cm(T.n_cells, 0);
+        for (int c = 0; c < T.n_cells; ++c)
+            if (T.child[c] >= 0)
+                for (int q = 0; q < 4; ++q) cm[c] |= (T.npc[T.child[c] + q] > 0 ? 1 : 0) << q;
+        f->cmask.upload(cm);
+    }
     f->nbeg.upload(T.nbeg);
     f->nend.upload(T.nend);
     f->node_perm.upload(T.node_perm);
