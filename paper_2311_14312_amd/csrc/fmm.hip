@@ -86,9 +86,8 @@ __device__ inline void center_of(const TreeView& t, int l, long long i, long lon
 
 // Does source box c (any level <= l... or finer) touch target box (l, ti, tj)?
 // Boxes touch when their closed squares intersect (edges or corners).
-__device__ inline bool touches(const TreeView& t, int c, int l, long long ti, long long tj) {
-    const int lc = t.lvl[c];
-    long long cx = t.ix[c], cy = t.iy[c];
+__device__ inline bool touches_at(int lc, long long cx, long long cy, int l, long long ti,
+                                  long long tj) {
     if (lc <= l) {
         const int s = l - lc;
         const long long lo_x = cx << s, hi_x = ((cx + 1) << s) - 1;
@@ -99,6 +98,9 @@ __device__ inline bool touches(const TreeView& t, int c, int l, long long ti, lo
     const long long lo_x = ti << s, hi_x = ((ti + 1) << s) - 1;
     const long long lo_y = tj << s, hi_y = ((tj + 1) << s) - 1;
     return cx >= lo_x - 1 && cx <= hi_x + 1 && cy >= lo_y - 1 && cy <= hi_y + 1;
+}
+__device__ inline bool touches(const TreeView& t, int c, int l, long long ti, long long tj) {
+    return touches_at(t.lvl[c], t.ix[c], t.iy[c], l, ti, tj);
 }
 
 template <typename T>
@@ -767,7 +769,8 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                 int nU = 0, nW = 0;
                 while (sh.nS > 0 && nU < kUCap && nW + 4 <= kWCap) {
                     const int c = sh.stack[--sh.nS];
-                    const int c0 = tv.child[c], cm = tv.cmask[c];
+                    const int c0 = tv.child[c], cm = tv.cmask[c], lc = tv.lvl[c];
+                    const long long cx = tv.ix[c], cy = tv.iy[c];
                     if (c0 < 0) {
                         sh.Upre[nU] = 0;
                         sh.U[nU++] = c;
@@ -776,7 +779,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                     for (int q = 0; q < 4; ++q) {
                         const int d = c0 + q;
                         if (!((cm >> q) & 1)) continue;
-                        if (touches(tv, d, l, ti, tj)) {
+                        if (touches_at(lc + 1, 2 * cx + (q & 1), 2 * cy + (q >> 1), l, ti, tj)) {
                             if (sh.nS < kSCap) sh.stack[sh.nS++] = d;
                         } else {
                             sh.W[nW++] = d;
@@ -959,15 +962,20 @@ __device__ void tile_round(TileShared<T, NT>& sh, const TreeView& tv, int l, lon
         int c = -1, ch0 = -1, isU = 0, wm = 0, fm = 0;
         if (lane < chunk) {
             c = sh.Q[b0 + lane];
+            // one round of loads: the children's cells follow from c's
+            // (child q is at (2 ix + (q & 1), 2 iy + (q >> 1)) one level down)
             ch0 = tv.child[c];
-            const int cm = tv.cmask[c];  // loaded with the child index
+            const int cm = tv.cmask[c], lc = tv.lvl[c];
+            const long long cx = tv.ix[c], cy = tv.iy[c];
             if (ch0 < 0) {
                 isU = 1;
             } else {
                 for (int q = 0; q < 4; ++q) {
                     if (!((cm >> q) & 1)) continue;  // no pieces below
-                    const int d = ch0 + q;
-                    if (touches(tv, d, l, ti, tj)) fm |= 1 << q; else wm |= 1 << q;
+                    if (touches_at(lc + 1, 2 * cx + (q & 1), 2 * cy + (q >> 1), l, ti, tj))
+                        fm |= 1 << q;
+                    else
+                        wm |= 1 << q;
                 }
             }
         }
