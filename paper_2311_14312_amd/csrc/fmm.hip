@@ -400,7 +400,8 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     }
     __syncthreads();
     // near set N(own): the 3 x 3 positions around own at level l, each the
-    // deepest source box at level <= l covering it
+    // deepest source box at level <= l covering it, or -1 where that box
+    // holds no pieces (its subtree adds nothing to any list)
     if (lane < 9) {
         const long long px = ti + (lane % 3) - 1, py = tj + (lane / 3) - 1;
         int c = -1;
@@ -408,8 +409,12 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         if (px >= 0 && py >= 0 && px < lim && py < lim) {
             const int slot = (int)((px >> 1) - (ti >> 1) + 1) + 3 * (int)((py >> 1) - (tj >> 1) + 1);
             c = sh.PN[slot];
-            if (c >= 0 && sh.PL[slot] == l - 1 && sh.PC[slot] >= 0)
-                c = sh.PC[slot] + (int)(px & 1) + 2 * (int)(py & 1);
+            if (c >= 0 && sh.PL[slot] == l - 1 && sh.PC[slot] >= 0) {
+                const int q = (int)(px & 1) + 2 * (int)(py & 1);
+                c = ((sh.PM[slot] >> q) & 1) ? sh.PC[slot] + q : -1;
+            } else if (c >= 0 && sh.PN2[slot] == 0) {
+                c = -1;
+            }
         }
         nset[(size_t)own * 9 + lane] = c;
     }
@@ -1140,13 +1145,20 @@ __device__ inline void tile_near_init(TileShared<T, NT>& sh, const TreeView& tv,
             c = nset[(size_t)own * 9 + tid];
             ok = c >= 0;
             for (int s2 = 0; s2 < tid && ok; ++s2) ok = nset[(size_t)own * 9 + s2] != c;
-            ok = ok && tv.npc[c] > 0;
         }
         const unsigned long long m = __ballot(ok);
         if (ok) sh.Q[__popcll(m & ((1ULL << tid) - 1ULL))] = c;
         if (tid == 0) sh.nQ = __popcll(m);
     }
 }
+
+// The expansion a tile evaluates (its own, or its owner's when quiet).
+struct TileOwner {
+    const cpx<double>* loc;
+    int lo;
+    double ro, ocx, ocy;
+    bool quiet;
+};
 
 // Near field of a tile pass (see above): near-set traversal by wave 0 in
 // rounds bounded by the list capacities (the stack starts with the
@@ -1158,15 +1170,21 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const int* __restrict__ nset, int l, long long ti, long long tj,
                           int own, double cx, double cy, const TileTargets<T, PX>& tt,
-                          int n_here, int tid, double (&acc)[PX][3]) {
+                          const TileOwner* l2p, int n_here, int tid, double (&acc)[PX][3]) {
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
     const T* wts = weights<T>(pv);
     tile_near_init(sh, tv, nset, own, tid);
     __syncthreads();
     int u_run = 0;
+    bool first = true;
     for (;;) {
-        if (tid < kWave) tile_round(sh, tv, l, ti, tj, tid);
+        if (tid < kWave)
+            tile_round(sh, tv, l, ti, tj, tid);
+        else if (first && l2p != nullptr && gid == 1)  // beside wave 0's first round
+            tile_l2p<T, PX>(tt, l2p->loc, p, l2p->lo, l2p->ro, l2p->ocx, l2p->ocy,
+                            tile_coef(p, tid), tid % kWave, acc);
+        first = false;
         __syncthreads();
         const int nU = sh.nU, nW = sh.nW, more = sh.nQ > 0;
         // target-from-outgoing (Eq. t-f-o), scaled:
@@ -1319,13 +1337,6 @@ __device__ inline void tile_store(const LeafArgs& a, const VpLeaf& v, const Tile
 }
 
 // Geometry of a tile's owner expansion (quiet tiles evaluate an ancestor's).
-struct TileOwner {
-    const cpx<double>* loc;
-    int lo;
-    double ro, ocx, ocy;
-    bool quiet;
-};
-
 __device__ inline TileOwner tile_owner(const TreeView& tv, const cpx<double>* Lc,
                                        const int2* owner, int p, int l, long long ti,
                                        long long tj, int own) {
@@ -1360,7 +1371,11 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         double acc[PX][3];
         for (int q = 0; q < PX; ++q)
             for (int ch = 0; ch < 3; ++ch) acc[q][ch] = 0.0;
-        if (gid == 0)
+        // FP64 with several groups: group 1 evaluates the expansion in
+        // tile_near while wave 0 runs the first traversal round (measured
+        // faster in FP64, slower in FP32).
+        const bool l2p_near = sizeof(T) == 8 && S > 1 && G == kWave && !o.quiet;
+        if (gid == 0 && !l2p_near)
             tile_l2p<T, PX>(tt, o.loc, p, o.lo, o.ro, o.ocx, o.ocy, tile_coef(p, tid),
                             tid % kWave, acc);
         const int n_here = min(G * PX, n_targets - tbase);
@@ -1370,6 +1385,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         }
         if (!o.quiet)
             tile_near<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, nset, l, ti, tj, own, cx, cy, tt,
+                                           l2p_near ? &o : nullptr,
                                            n_here, tid, acc);
         tile_group_sum<T, NT, PX, S>(sh, tid, acc);
         tile_store<T, PX>(a, v, tt, gid == 0, acc);
