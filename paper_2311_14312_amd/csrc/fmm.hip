@@ -358,7 +358,7 @@ struct DownShared {
 // Downward pass of one target box (own, at level l, cell (ti, tj), parent
 // par) by one wave.  Writes nset[own] (unless the parent is quiet) and,
 // unless the box is quiet (render only, owner != nullptr), L[own]; returns
-// whether it was quiet.
+// whether it was quiet.  Near sets hold -1 for cells without pieces.
 template <typename T, bool Count, int E = 1>
 __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceView& pv, int l,
                           long long ti, long long tj, int own, int par, int p,
@@ -366,10 +366,22 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                           int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
                           int2* __restrict__ owner, unsigned long long* stats, int lane) {
     // Render: the children of a quiet box are quiet (below); they record the
-    // owner and leave without loading the near set (which nothing reads).
+    // owner and leave without using the parent's near set.
     const int2 po = owner != nullptr ? owner[par] : make_int2(par, 0);
-    if (lane < 9) sh.PN[lane] = nset[(size_t)par * 9 + lane];
+    int pn = -1;
+    if (lane < 9) {
+        pn = nset[(size_t)par * 9 + lane];
+        sh.PN[lane] = pn;
+    }
     if (po.x != par) {
+        if (lane == 0) owner[own] = po;
+        return true;
+    }
+    // Render: a parent's near set without pieces (every cell -1) makes the
+    // box quiet (see below) before anything else is loaded; its own near
+    // set is then empty too.
+    if (owner != nullptr && __ballot(pn >= 0) == 0) {
+        if (lane < 9) nset[(size_t)own * 9 + lane] = -1;
         if (lane == 0) owner[own] = po;
         return true;
     }
