@@ -1919,19 +1919,16 @@ int tile_level(double side, const dc_viewport& vp, int tile_px) {
 
 __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
                              cpx<double>* __restrict__ L, int* __restrict__ nset,
-                             int2* __restrict__ owner) {
+                             int2* __restrict__ owner, int* __restrict__ hv_ctl) {
     const int v = blockIdx.x;
+    // the counters of the heavy-tile queue (if any), cleared for this render
+    if (v == 0 && hv_ctl != nullptr && threadIdx.x < 3) hv_ctl[threadIdx.x] = 0;
     if (v >= n) return;
     const int own = roots[v].off;
     const int t = threadIdx.x;
     if (t == 0) owner[own] = make_int2(own, 0);
     if (t < 9) nset[(size_t)own * 9 + t] = (t == 4) ? 0 : -1;
     for (int i = t; i < (p + 1) * 3; i += blockDim.x) L[(size_t)own * (p + 1) * 3 + i] = {0, 0};
-}
-
-// Counters of the heavy-tile queue, cleared before each leaf pass.
-__global__ void k_heavy_init(int* __restrict__ ctl) {
-    if (threadIdx.x < 3) ctl[threadIdx.x] = 0;
 }
 
 // Ticks of the device's constant-rate wall clock in about one second.
@@ -2045,8 +2042,10 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
                             TL, nset, owner, d_lev, d_leaf, st);
     } else {
         const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
+        int* hv_ctl = o.tile_px <= 8 && pl.hv_flag_at > 0
+                          ? reinterpret_cast<int*>(scratch + pl.hv_ctl_at) : nullptr;
         hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
-                           nset, owner);
+                           nset, owner, hv_ctl);
         DC_HIP(hipGetLastError());
         for (int l = 1; l <= pl.maxL; ++l) {
             DownLevel dl{};
@@ -2098,8 +2097,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
             a.hv_list_cap = pl.leaf_blocks;
             a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
-            hipLaunchKernelGGL(k_heavy_init, dim3(1), dim3(kWave), 0, st, a.hv_ctl);
-            DC_HIP(hipGetLastError());
+            // (hv_ctl was cleared by k_init_roots)
             if (stats)
                 hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>, true>),
                                    dim3(pl.leaf_blocks), dim3(kWave), tile_coef_bytes(kWave, p), st,
