@@ -103,6 +103,8 @@ struct RenderPlan {
     size_t owner_at = 0, queue_at = 0, ready_at = 0, ctl_at = 0, scratch_bytes = 0;
     // queue of heavy small tiles (k_tile_scan, k_tile_big; 8-pixel tiles)
     size_t hv_ctl_at = 0, hv_list_at = 0, hv_flag_at = 0;
+    // first-round traversal lists of light small tiles (k_tile_scan -> k_tile)
+    size_t lists_at = 0;
     // Write both descriptor tables (desc_bytes) to host, with output
     // pointers outs[v].
     void write_tables(void* host, void* const* outs) const;

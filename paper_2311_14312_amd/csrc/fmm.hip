@@ -708,7 +708,9 @@ struct LeafArgs {
     int* hv_ctl;             // [0] / [2] tiles queued at the front / back, [1] next to take
     int* hv_list;            // queued tiles (global leaf block), hv_list_cap entries
     int hv_list_cap;
-    unsigned char* hv_flag;  // per global leaf block: 1 if queued
+    unsigned char* hv_flag;  // per global leaf block: 0 k_tile, 1 queued, 2 done,
+                             // 3 k_tile with the lists kept in `lists`
+    int* lists;              // kListInts per global leaf block (8-px tiles)
 };
 
 template <typename T, int NT>
@@ -1083,6 +1085,12 @@ constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
 template <typename T>
 constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
 constexpr int kBigBlocks = 512;  // grid of k_tile_big
+// A light small tile's first-round traversal lists, kept by k_tile_scan so
+// that k_tile need not repeat the traversal, when they hold at most kListU
+// near leaves and kListW separated boxes.  Record of kListInts ints per
+// tile: nU, nW, U[kListU], Upre[kListU + 1], W[kListW].
+constexpr int kListU = 48, kListW = 48;
+constexpr int kListInts = 2 + kListU + (kListU + 1) + kListW + 1;  // (padded to 16 B)
 constexpr int kOverlapTiles = 65536;  // renders with this many tiles overlap k_tile_big
 constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_down<.., 3>
 
@@ -1182,18 +1190,39 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const int* __restrict__ nset, int l, long long ti, long long tj,
                           int own, double cx, double cy, const TileTargets<T, PX>& tt,
-                          const TileOwner* l2p, int n_here, int tid, double (&acc)[PX][3]) {
+                          const TileOwner* l2p, const int* lists, int n_here, int tid,
+                          double (&acc)[PX][3]) {
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
     const T* wts = weights<T>(pv);
-    tile_near_init(sh, tv, nset, own, tid);
+    if (lists != nullptr) {
+        // the lists of the only round, as k_tile_scan's tile_round left them
+        // (every slot of the record is read in one round of loads)
+        if (tid < kWave) {
+            const int nU = lists[0], nW = lists[1];
+            const int u = tid < kListU ? lists[2 + tid] : 0;
+            const int up = tid <= kListU ? lists[2 + kListU + tid] : 0;
+            const int w = tid < kListW ? lists[3 + 2 * kListU + tid] : 0;
+            if (tid < nU) sh.U[tid] = u;
+            if (tid <= nU) sh.Upre[tid] = up;
+            if (tid < nW) sh.W[tid] = w;
+            if (tid == 0) {
+                sh.nU = nU;
+                sh.nW = nW;
+                sh.nQ = 0;
+            }
+        }
+    } else {
+        tile_near_init(sh, tv, nset, own, tid);
+    }
     __syncthreads();
     int u_run = 0;
     bool first = true;
     for (;;) {
-        if (tid < kWave)
-            tile_round(sh, tv, l, ti, tj, tid);
-        else if (first && l2p != nullptr && gid == 1)  // beside wave 0's first round
+        if (tid < kWave) {
+            if (!(first && lists != nullptr)) tile_round(sh, tv, l, ti, tj, tid);
+        }
+        if (tid >= kWave && first && l2p != nullptr && gid == 1)  // beside wave 0's first round
             tile_l2p<T, PX>(tt, l2p->loc, p, l2p->lo, l2p->ro, l2p->ocx, l2p->ocy,
                             tile_coef(p, tid), tid % kWave, acc);
         first = false;
@@ -1368,7 +1397,8 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
                           const int2* __restrict__ owner, const VpLeaf& v, int l, long long ti,
-                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid) {
+                          long long tj, int own, int k_lo, int nx, int r_lo, int ny, int tid,
+                          const int* lists) {
     static_assert(NT % S == 0 && (S == 1 || (NT / S) % kWave == 0), "split groups are waves");
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
@@ -1397,7 +1427,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         }
         if (!o.quiet)
             tile_near<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, nset, l, ti, tj, own, cx, cy, tt,
-                                           l2p_near ? &o : nullptr,
+                                           l2p_near ? &o : nullptr, lists,
                                            n_here, tid, acc);
         tile_group_sum<T, NT, PX, S>(sh, tid, acc);
         tile_store<T, PX>(a, v, tt, gid == 0, acc);
@@ -1412,7 +1442,8 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
     const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    if (a.hv_flag != nullptr && a.hv_flag[gb]) return;  // done by k_tile_scan or queued
+    const int fl = a.hv_flag != nullptr ? a.hv_flag[gb] : 0;
+    if (fl == 1 || fl == 2) return;  // queued, or done by k_tile_scan
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
     const int blk = gb - v.first_block;
     __shared__ TileShared<T, NT> sh;
@@ -1426,7 +1457,8 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     const int r_lo = a.edges[v.row_at + cj + 1];
     const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
     tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
-                                   k_lo, nx, r_lo, ny, tid);
+                                   k_lo, nx, r_lo, ny, tid,
+                                   fl == 3 ? a.lists + (size_t)gb * kListInts : nullptr);
 }
 
 // First pass over every small tile.  A quiet tile (see k_down) is
@@ -1477,9 +1509,9 @@ k_tile_scan(TreeView tv, LeafArgs a, int p, const cpx<double>* __restrict__ Lc,
         __syncthreads();
         tile_round(sh, tv, l, ti, tj, tid);
         __syncthreads();
-        if (tid == 0) {
-            const int np = sh.Upre[sh.nU];
-            if (np > Heavy || sh.nQ > 0) {
+        const int nU = sh.nU, nW = sh.nW, np = sh.Upre[nU];
+        if (np > Heavy || sh.nQ > 0) {
+            if (tid == 0) {
                 // the heaviest (more rounds, or 4x the pieces) from the front
                 const bool front = sh.nQ > 0 || np > 4 * Heavy;
                 const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
@@ -1487,6 +1519,17 @@ k_tile_scan(TreeView tv, LeafArgs a, int p, const cpx<double>* __restrict__ Lc,
                 if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
                 flag = queued ? 1 : 0;
             }
+        } else if (a.lists != nullptr && nU <= kListU && nW <= kListW) {
+            // a light tile: its lists are kept for k_tile
+            int* rec = a.lists + (size_t)gb * kListInts;
+            if (tid < nU) rec[2 + tid] = sh.U[tid];
+            if (tid <= nU) rec[2 + kListU + tid] = sh.Upre[tid];
+            if (tid < nW) rec[3 + 2 * kListU + tid] = sh.W[tid];
+            if (tid == 0) {
+                rec[0] = nU;
+                rec[1] = nW;
+            }
+            flag = 3;
         }
     }
     if (tid == 0) a.hv_flag[gb] = (unsigned char)flag;
@@ -1524,7 +1567,7 @@ k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __re
         const int r_lo = a.edges[v.row_at + cj + 1];
         const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
         tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
-                                       k_lo, nx, r_lo, ny, tid);
+                                       k_lo, nx, r_lo, ny, tid, nullptr);
         __syncthreads();
     }
 }
@@ -2097,6 +2140,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             a.hv_list = reinterpret_cast<int*>(scratch + pl.hv_list_at);
             a.hv_list_cap = pl.leaf_blocks;
             a.hv_flag = reinterpret_cast<unsigned char*>(scratch + pl.hv_flag_at);
+            a.lists = reinterpret_cast<int*>(scratch + pl.lists_at);
             // (hv_ctl was cleared by k_init_roots)
             if (stats)
                 hipLaunchKernelGGL((k_tile_scan<T, kWave, kHeavyPieces<T>, true>),
@@ -2430,7 +2474,8 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
     pl.hv_list_at = up256(pl.hv_ctl_at + 3 * sizeof(int));
     pl.hv_flag_at = up256(pl.hv_list_at + nl * sizeof(int));
-    pl.scratch_bytes = up256(pl.hv_flag_at + nl);
+    pl.lists_at = up256(pl.hv_flag_at + nl);
+    pl.scratch_bytes = up256(pl.lists_at + nl * kListInts * sizeof(int));
 }
 
 void RenderPlan::write_tables(void* host, void* const* outs) const {
