@@ -709,7 +709,7 @@ struct LeafArgs {
     int* hv_list;            // queued tiles (global leaf block), hv_list_cap entries
     int hv_list_cap;
     unsigned char* hv_flag;  // per global leaf block: 0 k_tile, 1 queued, 2 done,
-                             // 3 k_tile with the lists kept in `lists`
+                             // 3 k_tile and 4 queued, with the lists kept in `lists`
     int* lists;              // kListInts per global leaf block (8-px tiles)
 };
 
@@ -1085,12 +1085,13 @@ constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
 template <typename T>
 constexpr int kBigSplit = sizeof(T) == 4 ? 8 : 4;
 constexpr int kBigBlocks = 512;  // grid of k_tile_big
-// A light small tile's first-round traversal lists, kept by k_tile_scan so
-// that k_tile need not repeat the traversal, when they hold at most kListU
-// near leaves and kListW separated boxes.  Record of kListInts ints per
-// tile: nU, nW, U[kListU], Upre[kListU + 1], W[kListW].
-constexpr int kListU = 48, kListW = 48;
-constexpr int kListInts = 2 + kListU + (kListU + 1) + kListW + 1;  // (padded to 16 B)
+// A small tile's traversal lists, kept by k_tile_scan when its first round
+// is its only one and finds at most kListW separated boxes (a round never
+// holds more than kUCap near leaves), so that k_tile or k_tile_big need not
+// repeat the traversal.  Record of kListInts ints per tile: nU, nW,
+// U[kListU], Upre[kListU + 1], W[kListW], one int of padding.
+constexpr int kListU = kUCap, kListW = 64;
+constexpr int kListInts = 2 + kListU + (kListU + 1) + kListW + 1;
 constexpr int kOverlapTiles = 65536;  // renders with this many tiles overlap k_tile_big
 constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_down<.., 3>
 
@@ -1198,19 +1199,27 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
     if (lists != nullptr) {
         // the lists of the only round, as k_tile_scan's tile_round left them
         // (every slot of the record is read in one round of loads)
-        if (tid < kWave) {
-            const int nU = lists[0], nW = lists[1];
-            const int u = tid < kListU ? lists[2 + tid] : 0;
-            const int up = tid <= kListU ? lists[2 + kListU + tid] : 0;
-            const int w = tid < kListW ? lists[3 + 2 * kListU + tid] : 0;
-            if (tid < nU) sh.U[tid] = u;
-            if (tid <= nU) sh.Upre[tid] = up;
-            if (tid < nW) sh.W[tid] = w;
-            if (tid == 0) {
-                sh.nU = nU;
-                sh.nW = nW;
-                sh.nQ = 0;
+        constexpr int kRec = kListInts - 2, kPer = (kRec + NT - 1) / NT;
+        int val[kPer];
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * NT;
+            val[j] = i < kRec ? lists[2 + i] : 0;
+        }
+        const int nU = lists[0], nW = lists[1];
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * NT;
+            if (i < kListU) {
+                if (i < nU) sh.U[i] = val[j];
+            } else if (i < 2 * kListU + 1) {
+                if (i - kListU <= nU) sh.Upre[i - kListU] = val[j];
+            } else if (i < 2 * kListU + 1 + kListW) {
+                if (i - 2 * kListU - 1 < nW) sh.W[i - 2 * kListU - 1] = val[j];
             }
+        }
+        if (tid == 0) {
+            sh.nU = nU;
+            sh.nW = nW;
+            sh.nQ = 0;
         }
     } else {
         tile_near_init(sh, tv, nset, own, tid);
@@ -1443,7 +1452,7 @@ k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
        const int2* __restrict__ owner) {
     const int gb = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int fl = a.hv_flag != nullptr ? a.hv_flag[gb] : 0;
-    if (fl == 1 || fl == 2) return;  // queued, or done by k_tile_scan
+    if (fl == 1 || fl == 2 || fl == 4) return;  // queued, or done by k_tile_scan
     const VpLeaf& v = find_entry(a.vleaf, a.nvleaf, gb);
     const int blk = gb - v.first_block;
     __shared__ TileShared<T, NT> sh;
@@ -1510,26 +1519,30 @@ k_tile_scan(TreeView tv, LeafArgs a, int p, const cpx<double>* __restrict__ Lc,
         tile_round(sh, tv, l, ti, tj, tid);
         __syncthreads();
         const int nU = sh.nU, nW = sh.nW, np = sh.Upre[nU];
+        // lists of a tile whose first round is its only one, kept
+        const bool keep = a.lists != nullptr && sh.nQ == 0 && nU <= kListU && nW <= kListW;
+        if (keep) {
+            int* rec = a.lists + (size_t)gb * kListInts;
+            for (int i = tid; i < nU; i += kWave) rec[2 + i] = sh.U[i];
+            for (int i = tid; i <= nU; i += kWave) rec[2 + kListU + i] = sh.Upre[i];
+            for (int i = tid; i < nW; i += kWave) rec[3 + 2 * kListU + i] = sh.W[i];
+            if (tid == 0) {
+                rec[0] = nU;
+                rec[1] = nW;
+            }
+        }
+        flag = keep ? 3 : 0;
         if (np > Heavy || sh.nQ > 0) {
             if (tid == 0) {
                 // the heaviest (more rounds, or 4x the pieces) from the front
                 const bool front = sh.nQ > 0 || np > 4 * Heavy;
                 const int h = atomicAdd(&a.hv_ctl[front ? 0 : 2], 1);
                 const bool queued = h < a.hv_list_cap;
-                if (queued) a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
-                flag = queued ? 1 : 0;
+                if (queued) {
+                    a.hv_list[front ? h : a.hv_list_cap - 1 - h] = gb;
+                    flag = keep ? 4 : 1;
+                }
             }
-        } else if (a.lists != nullptr && nU <= kListU && nW <= kListW) {
-            // a light tile: its lists are kept for k_tile
-            int* rec = a.lists + (size_t)gb * kListInts;
-            if (tid < nU) rec[2 + tid] = sh.U[tid];
-            if (tid <= nU) rec[2 + kListU + tid] = sh.Upre[tid];
-            if (tid < nW) rec[3 + 2 * kListU + tid] = sh.W[tid];
-            if (tid == 0) {
-                rec[0] = nU;
-                rec[1] = nW;
-            }
-            flag = 3;
         }
     }
     if (tid == 0) a.hv_flag[gb] = (unsigned char)flag;
@@ -1566,8 +1579,9 @@ k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __re
         const int nx = a.edges[v.col_at + ci + 1] - k_lo;
         const int r_lo = a.edges[v.row_at + cj + 1];
         const int ny = max(a.edges[v.row_at + cj] - r_lo, 0);
+        const int* rec = a.hv_flag[gb] == 4 ? a.lists + (size_t)gb * kListInts : nullptr;
         tile_body<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own,
-                                       k_lo, nx, r_lo, ny, tid, nullptr);
+                                       k_lo, nx, r_lo, ny, tid, rec);
         __syncthreads();
     }
 }
