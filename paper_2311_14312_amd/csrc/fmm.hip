@@ -1092,6 +1092,26 @@ constexpr int kBigBlocks = 512;  // grid of k_tile_big
 // U[kListU], Upre[kListU + 1], W[kListW], one int of padding.
 constexpr int kListU = kUCap, kListW = 64;
 constexpr int kListInts = 2 + kListU + (kListU + 1) + kListW + 1;
+
+// A kept record, loaded into registers (this thread's slots) when a tile's
+// evaluation starts, so that the loads overlap the expansion's.
+template <int NT>
+struct KeptLists {
+    static constexpr int kRec = kListInts - 2, kPer = (kRec + NT - 1) / NT;
+    int val[kPer];
+    int nU = 0, nW = 0;
+    bool on = false;
+    __device__ void load(const int* rec, int tid) {
+        on = rec != nullptr;
+        if (!on) return;
+        for (int j = 0; j < kPer; ++j) {
+            const int i = tid + j * NT;
+            val[j] = i < kRec ? rec[2 + i] : 0;
+        }
+        nU = rec[0];
+        nW = rec[1];
+    }
+};
 constexpr int kOverlapTiles = 65536;  // renders with this many tiles overlap k_tile_big
 constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_down<.., 3>
 
@@ -1191,29 +1211,22 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                           const LeafArgs& a, int p, const cpx<double>* __restrict__ Ms,
                           const int* __restrict__ nset, int l, long long ti, long long tj,
                           int own, double cx, double cy, const TileTargets<T, PX>& tt,
-                          const TileOwner* l2p, const int* lists, int n_here, int tid,
+                          const TileOwner* l2p, const KeptLists<NT>& kl, int n_here, int tid,
                           double (&acc)[PX][3]) {
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
     const T* wts = weights<T>(pv);
-    if (lists != nullptr) {
+    if (kl.on) {
         // the lists of the only round, as k_tile_scan's tile_round left them
-        // (every slot of the record is read in one round of loads)
-        constexpr int kRec = kListInts - 2, kPer = (kRec + NT - 1) / NT;
-        int val[kPer];
-        for (int j = 0; j < kPer; ++j) {
-            const int i = tid + j * NT;
-            val[j] = i < kRec ? lists[2 + i] : 0;
-        }
-        const int nU = lists[0], nW = lists[1];
-        for (int j = 0; j < kPer; ++j) {
+        const int nU = kl.nU, nW = kl.nW;
+        for (int j = 0; j < KeptLists<NT>::kPer; ++j) {
             const int i = tid + j * NT;
             if (i < kListU) {
-                if (i < nU) sh.U[i] = val[j];
+                if (i < nU) sh.U[i] = kl.val[j];
             } else if (i < 2 * kListU + 1) {
-                if (i - kListU <= nU) sh.Upre[i - kListU] = val[j];
+                if (i - kListU <= nU) sh.Upre[i - kListU] = kl.val[j];
             } else if (i < 2 * kListU + 1 + kListW) {
-                if (i - 2 * kListU - 1 < nW) sh.W[i - 2 * kListU - 1] = val[j];
+                if (i - 2 * kListU - 1 < nW) sh.W[i - 2 * kListU - 1] = kl.val[j];
             }
         }
         if (tid == 0) {
@@ -1229,7 +1242,7 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
     bool first = true;
     for (;;) {
         if (tid < kWave) {
-            if (!(first && lists != nullptr)) tile_round(sh, tv, l, ti, tj, tid);
+            if (!(first && kl.on)) tile_round(sh, tv, l, ti, tj, tid);
         }
         if (tid >= kWave && first && l2p != nullptr && gid == 1)  // beside wave 0's first round
             tile_l2p<T, PX>(tt, l2p->loc, p, l2p->lo, l2p->ro, l2p->ocx, l2p->ocy,
@@ -1414,6 +1427,8 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
     const int n_targets = nx > 0 ? nx * ny : 0;
     double cx, cy;
     center_of(tv, l, ti, tj, cx, cy);
+    KeptLists<NT> kl;
+    kl.load(lists, tid);
     const TileOwner o = tile_owner(tv, Lc, owner, p, l, ti, tj, own);
     for (int tbase = 0; tbase < n_targets; tbase += G * PX) {
         TileTargets<T, PX> tt;
@@ -1436,7 +1451,7 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
         }
         if (!o.quiet)
             tile_near<T, NT, PX, S, Count>(sh, tv, pv, a, p, Ms, nset, l, ti, tj, own, cx, cy, tt,
-                                           l2p_near ? &o : nullptr, lists,
+                                           l2p_near ? &o : nullptr, kl,
                                            n_here, tid, acc);
         tile_group_sum<T, NT, PX, S>(sh, tid, acc);
         tile_store<T, PX>(a, v, tt, gid == 0, acc);
