@@ -322,10 +322,11 @@ __device__ inline T wave_sum(T v) {
 }
 
 // Per-piece data of the incoming-from-source pass, one piece per lane.
+template <typename T>
 struct P2LStage {
-    double zAr[kWave], zAi[kWave], zBr[kWave], zBi[kWave];  // 1/A, 1/B
-    double wr[kWave], wi[kWave];                             // wbar
-    double qs[3][kWave], qm[3][kWave];
+    T zAr[kWave], zAi[kWave], zBr[kWave], zBi[kWave];  // 1/A, 1/B
+    T wr[kWave], wi[kWave];                             // wbar
+    T qs[3][kWave], qm[3][kWave];
 };
 
 // Downward pass at one level, one wave per target box: near set from the
@@ -341,7 +342,7 @@ struct DownShared {
     // E: interaction-list entries per group per staging round of M2L
     static constexpr size_t kStageM2L = 2 * 3 * E * kWave * sizeof(cpx<T>);
     static constexpr size_t kScratch =
-        sizeof(P2LStage) > kStageM2L ? sizeof(P2LStage) : kStageM2L;
+        sizeof(P2LStage<T>) > kStageM2L ? sizeof(P2LStage<T>) : kStageM2L;
     // the parent's near set and its metadata
     int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9], Pb[9], PM[9];
     int IL[36];              // interaction list (compacted)
@@ -362,8 +363,8 @@ struct DownShared {
 template <typename T, bool Count, int E = 1>
 __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceView& pv, int l,
                           long long ti, long long tj, int own, int par, int p,
-                          const cpx<T>* __restrict__ M, cpx<T>* __restrict__ L,
-                          int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
+                          const cpx<double>* __restrict__ M, cpx<double>* __restrict__ L,
+                          int* __restrict__ nset, const cpx<double>* __restrict__ Ttab,
                           int2* __restrict__ owner, unsigned long long* stats, int lane) {
     // Render: the children of a quiet box are quiet (below); they record the
     // owner and leave without using the parent's near set.
@@ -386,7 +387,10 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         return true;
     }
     // the parent's expansion for L2L, loaded while the near set is resolved
-    for (int i = lane; i < 3 * (p + 1); i += kWave) sh.ploc()[i] = L[(size_t)par * 3 * (p + 1) + i];
+    for (int i = lane; i < 3 * (p + 1); i += kWave) {
+        const cpx<double> v = L[(size_t)par * 3 * (p + 1) + i];
+        sh.ploc()[i] = to_c<T>(v.re, v.im);
+    }
     __syncthreads();
     // Metadata of the parent's near set, loaded once by lanes 0..8; it
     // serves the near set, the interaction list and the separated leaves.
@@ -510,7 +514,12 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                 if (i < per_round) {
                     const int g = i / (P1 * 3), off = i - g * (P1 * 3);
                     const int e = base + g;
-                    pre[t] = e < nIL ? M[(size_t)sh.IL[e] * P1 * 3 + off] : cpx<T>{0, 0};
+                    if (e < nIL) {
+                        const cpx<double> v = M[(size_t)sh.IL[e] * P1 * 3 + off];
+                        pre[t] = to_c<T>(v.re, v.im);
+                    } else {
+                        pre[t] = cpx<T>{0, 0};
+                    }
                 }
             }
         };
@@ -534,9 +543,9 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                 const int e = base + slot;
                 if (glane && e < nIL) {
                     const cpx<T>* src = stage + buf * per_round + slot * P1 * 3;
-                    const cpx<T>* Tk = Ttab + ((size_t)sh.To[e] * P1 + k) * P1;
+                    const cpx<double>* Tk = Ttab + ((size_t)sh.To[e] * P1 + k) * P1;
                     for (int m = 0; m <= p; ++m) {
-                        const cpx<T> t = Tk[m];
+                        const cpx<T> t = to_c<T>(Tk[m].re, Tk[m].im);
                         for (int ch = 0; ch < 3; ++ch)
                             gacc[ch] = cadd(gacc[ch], cmul(t, src[m * 3 + ch]));
                     }
@@ -570,7 +579,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     __syncthreads();
     const int nl4 = sh.Nl4, total = sh.Pre[nl4];
     if (total > 0) {
-        P2LStage& sp = *reinterpret_cast<P2LStage*>(sh.scratch);
+        P2LStage<T>& sp = *reinterpret_cast<P2LStage<T>*>(sh.scratch);
         const double inv_r = 1.0 / r;
         const T rr = (T)r, logr = (T)log(r);
         const T* w = weights<T>(pv);
@@ -649,16 +658,16 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     if (!klane) return false;
     for (int g = 0; g < ngrp; ++g)
         for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], sRed[g * P1 + k][ch]);
-    cpx<T>* out = L + ((size_t)own * P1 + k) * 3;
-    for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+    cpx<double>* out = L + ((size_t)own * P1 + k) * 3;
+    for (int ch = 0; ch < 3; ++ch) out[ch] = {(double)acc[ch].re, (double)acc[ch].im};
     return false;
 }
 
 // E > 1: deeper M2L staging for levels with few boxes (same values).
 template <typename T, bool Count, int E = 1>
 __global__ void __launch_bounds__(kWave, 4)
-k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<T>* __restrict__ M,
-       cpx<T>* __restrict__ L, int* __restrict__ nset, const cpx<T>* __restrict__ Ttab,
+k_down(TreeView tv, PieceView pv, DownLevel dl, int p, const cpx<double>* __restrict__ M,
+       cpx<double>* __restrict__ L, int* __restrict__ nset, const cpx<double>* __restrict__ Ttab,
        int2* __restrict__ owner) {
     __shared__ DownShared<T, E> sh;
     const int lane = threadIdx.x;
@@ -2129,16 +2138,16 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             // levels with few boxes are bound by one wave's latency: deeper staging
             const bool deep = pl.lev_blocks[l] < kDeepBoxes;
             if (stats && deep)
-                hipLaunchKernelGGL((k_down<double, true, 3>), dim3(pl.lev_blocks[l]), dim3(kWave), 0,
+                hipLaunchKernelGGL((k_down<T, true, 3>), dim3(pl.lev_blocks[l]), dim3(kWave), 0,
                                    st, tv, pv, dl, p, M, TL, nset, Ttab, owner);
             else if (stats)
-                hipLaunchKernelGGL((k_down<double, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
+                hipLaunchKernelGGL((k_down<T, true>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
                                    tv, pv, dl, p, M, TL, nset, Ttab, owner);
             else if (deep)
-                hipLaunchKernelGGL((k_down<double, false, 3>), dim3(pl.lev_blocks[l]), dim3(kWave),
+                hipLaunchKernelGGL((k_down<T, false, 3>), dim3(pl.lev_blocks[l]), dim3(kWave),
                                    0, st, tv, pv, dl, p, M, TL, nset, Ttab, owner);
             else
-                hipLaunchKernelGGL((k_down<double, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
+                hipLaunchKernelGGL((k_down<T, false>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st,
                                    tv, pv, dl, p, M, TL, nset, Ttab, owner);
             DC_HIP(hipGetLastError());
         }
