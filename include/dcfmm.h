@@ -52,9 +52,9 @@ extern "C" {
                                       are incomplete */
 
 #define DC_PREC_F64 0   /* everything in FP64 */
-#define DC_PREC_F32 1   /* FP32 downward pass (M2L, P2L, L2L) and near
-                           field; FP64 upward pass, stored expansions,
-                           L2P, M2P and near-singular chord pairs */
+#define DC_PREC_F32 1   /* FP32 downward pass (M2L, P2L, L2L), L2P and
+                           near field; FP64 upward pass, stored
+                           expansions, M2P and near-singular chord pairs */
 #define DC_METHOD_FMM 0
 #define DC_METHOD_DIRECT 1   /* brute-force sum over every chord segment */
 #define DC_OUT_F32 0

@@ -1171,14 +1171,30 @@ __device__ inline void tile_l2p(const TileTargets<T, PX>& tt, const cpx<double>*
                                 int lo, double ro, double ocx, double ocy, cpx<double>* cbuf,
                                 int lane, double (&acc)[PX][3]) {
     if (lo < 2) return;
-    stage_coef(cbuf, loc, (p + 1) * 3, lane);
     const double ir = 1.0 / ro;
-    for (int q = 0; q < PX; ++q) {
-        const cpx<double> z = {(tt.x[q] - ocx) * ir, (tt.y[q] - ocy) * ir};
-        for (int ch = 0; ch < 3; ++ch) {
-            cpx<double> s = cbuf[p * 3 + ch];
-            for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), cbuf[kk * 3 + ch]);
-            acc[q][ch] += s.re;
+    if constexpr (sizeof(T) == 4) {
+        // FP32 path: the stored FP64 expansion evaluated in FP32 (|z| < 1.5)
+        cpx<float>* fbuf = reinterpret_cast<cpx<float>*>(cbuf);
+        for (int i = lane; i < (p + 1) * 3; i += kWave)
+            fbuf[i] = {(float)loc[i].re, (float)loc[i].im};
+        __builtin_amdgcn_wave_barrier();
+        for (int q = 0; q < PX; ++q) {
+            const cpx<float> z = {(float)((tt.x[q] - ocx) * ir), (float)((tt.y[q] - ocy) * ir)};
+            for (int ch = 0; ch < 3; ++ch) {
+                cpx<float> s = fbuf[p * 3 + ch];
+                for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), fbuf[kk * 3 + ch]);
+                acc[q][ch] += (double)s.re;
+            }
+        }
+    } else {
+        stage_coef(cbuf, loc, (p + 1) * 3, lane);
+        for (int q = 0; q < PX; ++q) {
+            const cpx<double> z = {(tt.x[q] - ocx) * ir, (tt.y[q] - ocy) * ir};
+            for (int ch = 0; ch < 3; ++ch) {
+                cpx<double> s = cbuf[p * 3 + ch];
+                for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), cbuf[kk * 3 + ch]);
+                acc[q][ch] += s.re;
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
