@@ -322,6 +322,9 @@ __device__ inline T wave_sum(T v) {
 }
 
 // Per-piece data of the incoming-from-source pass, one piece per lane.
+// FP32 P2L (FP32 path) for boxes whose pieces all have max|q| length below this
+constexpr double kP2LFloat = 0.05;
+
 template <typename T>
 struct P2LStage {
     T zAr[kWave], zAi[kWave], zBr[kWave], zBi[kWave];  // 1/A, 1/B
@@ -342,7 +345,7 @@ struct DownShared {
     // E: interaction-list entries per group per staging round of M2L
     static constexpr size_t kStageM2L = 2 * 3 * E * kWave * sizeof(cpx<T>);
     static constexpr size_t kScratch =
-        sizeof(P2LStage<T>) > kStageM2L ? sizeof(P2LStage<T>) : kStageM2L;
+        sizeof(P2LStage<double>) > kStageM2L ? sizeof(P2LStage<double>) : kStageM2L;
     // the parent's near set and its metadata
     int PN[9], PL[9], PC[9], PN2[9], Pcnt[9], PT[9], Pb[9], PM[9];
     int IL[36];              // interaction list (compacted)
@@ -578,7 +581,27 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     }
     __syncthreads();
     const int nl4 = sh.Nl4, total = sh.Pre[nl4];
-    if (total > 0) {
+    // FP32 arithmetic (FP32 path) only when every piece's charge is small:
+    // a separated leaf's pieces can carry large charges of both signs whose
+    // contributions cancel, and those boxes take the FP64 form.
+    bool p2l32 = false;
+    if constexpr (sizeof(T) == 4) {
+        if (total > 0) {
+            const double* w64 = weights<double>(pv);
+            double mq = 0.0;
+            for (int g = lane; g < total; g += kWave) {
+                int u = 0;
+                while (u + 1 < nl4 && sh.Pre[u + 1] <= g) ++u;
+                const int e = sh.L4b[u] + (g - sh.Pre[u]);
+                double q = 0.0;
+                for (int c6 = 0; c6 < 6; ++c6) q = fmax(q, fabs(w64[(size_t)c6 * pv.n + e]));
+                mq = fmax(mq, q * pv.len[e]);
+            }
+            for (int o = kWave / 2; o > 0; o >>= 1) mq = fmax(mq, __shfl_xor(mq, o, kWave));
+            p2l32 = mq <= kP2LFloat;
+        }
+    }
+    if (total > 0 && p2l32) {
         P2LStage<T>& sp = *reinterpret_cast<P2LStage<T>*>(sh.scratch);
         const double inv_r = 1.0 / r;
         const T rr = (T)r, logr = (T)log(r);
@@ -645,7 +668,78 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                 const cpx<T> v = {wave_sum(c01[kk][ch].re), wave_sum(c01[kk][ch].im)};
                 if (klane && k == kk) acc[ch] = cadd(acc[ch], v);
             }
-    }
+        } else if (total > 0) {
+        // In FP64 whatever T: a separated leaf's pieces can carry large
+        // charges of both signs whose contributions cancel.
+        P2LStage<double>& sp = *reinterpret_cast<P2LStage<double>*>(sh.scratch);
+        const double inv_r = 1.0 / r;
+        const double rr = r, logr = log(r);
+        const double* w = weights<double>(pv);
+        cpx<double> c01[2][3];  // this lane's k = 0, 1 terms, summed over its pieces
+        cpx<double> pacc[3] = {{0, 0}, {0, 0}, {0, 0}};  // this lane's k >= 2 share
+        for (int ch = 0; ch < 3; ++ch) c01[0][ch] = c01[1][ch] = {0, 0};
+        for (int base = 0; base < total; base += kWave) {
+            // stage: one piece per lane
+            const int g = base + lane;
+            if (g < total) {
+                int u = 0;
+                while (u + 1 < nl4 && sh.Pre[u + 1] <= g) ++u;
+                const int e = sh.L4b[u] + (g - sh.Pre[u]);
+                const cpx<double> A = {(pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r};
+                const cpx<double> B = {(pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r};
+                const cpx<double> wbar = {pv.tx[e], -pv.ty[e]};
+                const double len = pv.len[e];
+                const cpx<double> zA = cinv(A), zB = cinv(B);
+                const cpx<double> BA = cmul(B, cpx<double>{A.re, -A.im});
+                const double nA = A.re * A.re + A.im * A.im, nB = B.re * B.re + B.im * B.im;
+                const cpx<double> Lam = {0.5 * log(nB / nA), atan2(BA.im, BA.re)};
+                const cpx<double> lA = clog(A);
+                const cpx<double> t2 = cmul(cmul(wbar, cscale(B, rr)), Lam);
+                const cpx<double> sv0 = {-(len * (logr + lA.re) + t2.re - len), -(len * lA.im + t2.im)};
+                const cpx<double> mv0 = {Lam.im, -Lam.re};
+                const cpx<double> sv1 = cmul(wbar, cscale(Lam, rr));
+                const cpx<double> d1 = csub(zB, zA);
+                const cpx<double> mv1 = {-d1.im, d1.re};
+                sp.zAr[lane] = zA.re;
+                sp.zAi[lane] = zA.im;
+                sp.zBr[lane] = zB.re;
+                sp.zBi[lane] = zB.im;
+                sp.wr[lane] = wbar.re;
+                sp.wi[lane] = wbar.im;
+                for (int ch = 0; ch < 3; ++ch) {
+                    const double qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
+                    sp.qs[ch][lane] = qs;
+                    sp.qm[ch][lane] = qm;
+                    c01[0][ch] = cadd(c01[0][ch], cadd(cscale(sv0, qs), cscale(mv0, qm)));
+                    c01[1][ch] = cadd(c01[1][ch], cadd(cscale(sv1, qs), cscale(mv1, qm)));
+                }
+            }
+            __syncthreads();
+            // k >= 2: the groups deal the staged pieces round-robin
+            const int n = min(kWave, total - base);
+            if (glane && k >= 2) {
+                const double sck = rr * recip<double>(k) * recip<double>(k - 1), rk = recip<double>(k);
+                for (int j = grp; j < n; j += ngrp) {
+                    const cpx<double> zA = {sp.zAr[j], sp.zAi[j]}, zB = {sp.zBr[j], sp.zBi[j]};
+                    const cpx<double> pa = cpow(zA, k - 1), pb = cpow(zB, k - 1);
+                    const cpx<double> sv = cmul(cpx<double>{sp.wr[j], sp.wi[j]}, cscale(csub(pa, pb), sck));
+                    const cpx<double> dd = cscale(csub(cmul(pb, zB), cmul(pa, zA)), rk);
+                    const cpx<double> mv = {-dd.im, dd.re};
+                    for (int ch = 0; ch < 3; ++ch)
+                        pacc[ch] = cadd(pacc[ch], cadd(cscale(sv, sp.qs[ch][j]),
+                                                       cscale(mv, sp.qm[ch][j])));
+                }
+            }
+            __syncthreads();
+        }
+        for (int ch = 0; ch < 3; ++ch) gacc[ch] = cadd(gacc[ch], to_c<T>(pacc[ch].re, pacc[ch].im));
+        // k = 0, 1 terms: summed over the wave
+        for (int kk = 0; kk < 2; ++kk)
+            for (int ch = 0; ch < 3; ++ch) {
+                const double vr = wave_sum(c01[kk][ch].re), vi = wave_sum(c01[kk][ch].im);
+                if (klane && k == kk) acc[ch] = cadd(acc[ch], to_c<T>(vr, vi));
+            }
+        }
     if (Count && lane == 0) {
         atomicAdd(stats + kStatP2L, (unsigned long long)total);
         atomicAdd(stats + kStatL2L, 1ULL);

@@ -96,6 +96,18 @@ def test_c2_render_bench_configuration(scene4, gold):
     assert e64 <= 1e-6
 
 
+def test_c2_fp32_arithmetic_floor(scene4, gold):
+    """At p = 16 truncation is far below FP32 rounding, so the FP32 path's
+    error is its arithmetic floor: the near field in FP32 with FP64 redo,
+    the downward pass and L2P in FP32 from FP64-stored expansions, M2P in
+    FP64.  Measured 3.9e-6 at p = 14, where an FP32 M2P (the near-cusp
+    curve's boxes have large moments) measured 1.9e-5."""
+    img = scene4.render(VP, method="fmm", precision="f32", p=16, tile_px=8).cpu().numpy()
+    e = _err(img, gold)
+    print(f"C2 FP32 p=16 vs oracle: {e:.3e}", flush=True)
+    assert e <= 1e-5
+
+
 @pytest.mark.parametrize("prec,p", [("f32", 12), ("f64", 20)])
 def test_c2_heavy_tiles_same_on_both_launch_paths(scene4, gold, prec, p):
     """A 2048^2 render (72,900 tiles) evaluates its queued heavy tiles on the
