@@ -52,9 +52,10 @@ extern "C" {
                                       are incomplete */
 
 #define DC_PREC_F64 0   /* everything in FP64 */
-#define DC_PREC_F32 1   /* FP32 downward pass (M2L, P2L, L2L), L2P and
-                           near field; FP64 upward pass, stored
-                           expansions, M2P and near-singular chord pairs */
+#define DC_PREC_F32 1   /* FP32 M2L, L2L, L2P, near field and P2L of
+                           small charges; FP64 upward pass, stored
+                           expansions, M2P, P2L of large charges and
+                           near-singular chord pairs */
 #define DC_METHOD_FMM 0
 #define DC_METHOD_DIRECT 1   /* brute-force sum over every chord segment */
 #define DC_OUT_F32 0
