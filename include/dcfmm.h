@@ -60,7 +60,7 @@ extern "C" {
 #define DC_METHOD_DIRECT 1   /* brute-force sum over every chord segment */
 #define DC_OUT_F32 0
 #define DC_OUT_F64 1
-#define DC_P_MAX 40          /* largest expansion order supported */
+#define DC_P_MAX 63          /* largest expansion order supported */
 
 typedef struct dc_scene_s* dc_scene;
 
@@ -181,7 +181,10 @@ int dc_apply_operator(dc_scene s, const double* x_dev, double* y_dev,
  * server below has scratch of its own).  A large render (8-pixel tiles,
  * at least 65,536 of them) runs part of its pixel pass on a second stream
  * of the scene; that work is joined back into stream by an event before
- * the call returns, so stream alone orders the result. */
+ * the call returns, so stream alone orders the result.  That second stream
+ * and its two events are used under a lock of the scene, so a direct render
+ * of a scene registered with a server may be issued from another host
+ * thread while the server's worker renders the same scene. */
 int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
               int out_dtype, void* out_dev, void* stream);
 

@@ -4,6 +4,7 @@
 
 #include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "dc_common.h"
@@ -164,6 +165,11 @@ struct FmmState {
     // concurrently with the other tiles), ordered by two events against
     // the caller's stream.  Renders of the scene on different caller
     // streams share it, which only serialises their heavy-tile kernels.
+    // aux_mu is held from the stream's creation through the launch
+    // sequence record(ev_scan) -> wait -> launches -> record(ev_big) ->
+    // wait, so that a direct render and a server batch of the same scene
+    // issued from two host threads cannot interleave their events.
+    std::mutex aux_mu;
     hipStream_t aux = nullptr;
     hipEvent_t ev_scan = nullptr, ev_big = nullptr;
     hipStream_t aux_stream() {

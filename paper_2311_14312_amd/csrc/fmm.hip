@@ -23,10 +23,12 @@
 // Eq. t-f-o).  When the target tree is the source tree (the solve) this is
 // exactly Alg. 8; for a render the target tree is the complete quadtree over
 // the viewport down to pixel tiles.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstddef>
 #include <cstring>
+#include <string>
 
 #include "scene.h"
 
@@ -2303,6 +2305,8 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             // with k_tile; small ones keep everything on st, so renders on
             // different caller streams do not queue behind one another on it
             const bool overlap = pl.leaf_blocks >= kOverlapTiles;
+            std::unique_lock<std::mutex> aux_lock(f.aux_mu, std::defer_lock);
+            if (overlap) aux_lock.lock();
             hipStream_t aux = overlap ? f.aux_stream() : st;
             if (overlap) {
                 DC_HIP(hipEventRecord(f.ev_scan, st));
@@ -2686,7 +2690,10 @@ std::unique_ptr<RenderGraph> fmm_graph_create(dc_scene_s& s, const dc_viewport* 
     try {
         fmm_prepare(s, o, cap);
         DC_HIP(hipStreamSynchronize(cap));
-        (void)f.aux_stream();
+        {
+            std::lock_guard<std::mutex> lk(f.aux_mu);
+            (void)f.aux_stream();
+        }
         g->gen = f.gen;
         g->M64 = f.M64.p;
         g->Ms64 = f.Ms64.p;

@@ -19,7 +19,7 @@ DC_ERR_TIMEOUT = -5
 PREC_F64, PREC_F32 = 0, 1
 METHOD_FMM, METHOD_DIRECT = 0, 1
 OUT_F32, OUT_F64 = 0, 1
-P_MAX = 40
+P_MAX = 63
 
 
 class SceneOpts(C.Structure):

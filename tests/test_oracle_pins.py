@@ -85,6 +85,51 @@ def test_arc_length_matches_richardson_polyline():
     assert abs(oracle.curve_length(2.5 * ctrl) - 2.5 * oracle.curve_length(ctrl)) < 1e-13
 
 
+# --------------------------------------------------------------------------
+# Boundary colours (Sec. 5.3): stops at normalised arc length k/(n-1)
+# --------------------------------------------------------------------------
+STOPS3 = np.array([[0.0, 0.0, 0.0], [1.0, 0.5, 0.2], [0.0, 1.0, 1.0]])
+
+
+def test_colour_at_three_stops_by_hand():
+    # values worked out by hand: stops at lambda = 0, 1/2, 1
+    lam = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    want = np.array([[0.0, 0.5, 1.0, 0.5, 0.0],
+                     [0.0, 0.25, 0.5, 0.75, 1.0],
+                     [0.0, 0.1, 0.2, 0.6, 1.0]])
+    np.testing.assert_allclose(oracle.colour_at(STOPS3, lam), want, atol=1e-15)
+    # two stops: plain linear blend
+    two = np.array([[0.2, 0.4, 0.6], [1.0, 0.0, 0.6]])
+    np.testing.assert_allclose(oracle.colour_at(two, np.array([0.25])).ravel(),
+                               [0.4, 0.3, 0.6], atol=1e-15)
+
+
+def _hand_colour(stops, lam):
+    """Three stops at 0, 1/2, 1 by the two linear pieces, written out."""
+    lam = np.asarray(lam)[None, :]
+    s0, s1, s2 = (stops[k][:, None] for k in range(3))
+    return np.where(lam < 0.5, s0 + (s1 - s0) * 2 * lam, s1 + (s2 - s1) * (2 * lam - 1))
+
+
+@pytest.mark.parametrize("reverse", [False, True])
+def test_boundary_values_follow_arc_length_from_the_first_point(reverse):
+    """A straight Bezier from (0,0) to (1,0) with evenly spaced control
+    points has arc length equal to x, so a node's colour must be the stop
+    interpolation at lambda = x (or 1 - x for the reversed curve); the left
+    colour is u+."""
+    a, b = np.array([0.0, 0.0]), np.array([1.0, 0.0])
+    if reverse:
+        a, b = b, a
+    ctrl = np.array([[a, a + (b - a) / 3, a + 2 * (b - a) / 3, b]])
+    right = STOPS3[::-1].copy()[None] * 0.5
+    disc = oracle.discretize(ctrl, 4, 8, 16)
+    up, um = oracle.boundary_values(disc, STOPS3[None], right)
+    x = disc.node_xy[:, 0]
+    lam = 1.0 - x if reverse else x
+    np.testing.assert_allclose(up, _hand_colour(STOPS3, lam), atol=1e-13)
+    np.testing.assert_allclose(um, _hand_colour(right[0], lam), atol=1e-13)
+
+
 def test_arc_length_inverse_hits_targets():
     ctrl = np.array([[0.0, 0.0], [0.1, 0.9], [0.9, 0.9], [1.0, 0.0]])
     L = oracle.curve_length(ctrl)
