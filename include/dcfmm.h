@@ -188,6 +188,27 @@ int dc_apply_operator(dc_scene s, const double* x_dev, double* y_dev,
 int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
               int out_dtype, void* out_dev, void* stream);
 
+/* dc_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, images and error codes as dc_render (o->method must be
+ * DC_METHOD_FMM); the image is bit-identical to dc_render's.  It calls no
+ * hipMalloc, hipFree, pinned-host allocation or stream creation: the render's
+ * device scratch is a fixed array of DC_NOALLOC_SCRATCH_BYTES bytes that
+ * each GPU the library runs on holds until the process ends, the render's
+ * descriptor tables reach it as kernel arguments, and every launch goes on
+ * stream (no second stream).  Requirements, each refused with
+ * DC_ERR_INVALID: the scene must already be prepared for o's order and
+ * precision (an earlier dc_render, dc_render_batch or dc_server_add_scene
+ * with the same p and precision made its resident expansions), and the
+ * render's scratch must fit the array (roughly 34 bytes per pixel with
+ * 8-pixel tiles and 4 with 16-pixel tiles at p = 12).  All calls on one GPU
+ * share that GPU's array and the array keeps the last call's contents:
+ * calls that overlap on one GPU (on different streams without ordering
+ * between them) race; calls on one stream are ordered. */
+#define DC_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int dc_render_noalloc(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
+                      int out_dtype, void* out_dev, void* stream);
+
 /* Alg. 4 for n viewports of one scene in one set of launches: one
  * downward launch per quadtree level covers every viewport that reaches
  * that level and one leaf pass covers every viewport's pixel tiles (the

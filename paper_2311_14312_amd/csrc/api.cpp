@@ -441,6 +441,23 @@ int dc_render(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o, int out_
     });
 }
 
+int dc_render_noalloc(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o, int out_dtype,
+                      void* out, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && vp && out, "null argument");
+        check_eval(o);
+        check_served_opts(s, o);
+        DC_REQUIRE(o->method == DC_METHOD_FMM, "dc_render_noalloc is an FMM path");
+        DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
+        DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0 &&
+                       std::isfinite(vp->cx) && std::isfinite(vp->cy) &&
+                       std::isfinite(vp->width) && std::isfinite(vp->height),
+                   "bad viewport");
+        DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
+        fmm_render_noalloc(*s, *vp, *o, out_dtype, out, as_stream(stream));
+    });
+}
+
 int dc_render_batch(dc_scene s, const dc_viewport* vps, int n, const dc_eval_opts* o,
                     int out_dtype, void* const* outs, void* stream) {
     return guarded([&] {

@@ -146,6 +146,10 @@ struct FmmState {
     // The staging is a ring, so the host can plan the next render while the
     // device still runs the previous ones.
     RenderPlan plan;
+    // Plan and host copy of the descriptor tables of dc_render_noalloc
+    // (whose device scratch is a fixed array, see fmm.hip).
+    RenderPlan noalloc_plan;
+    std::vector<char> noalloc_tables;
     static constexpr int kStages = 3;
     PinnedStage stage[kStages];
     int stage_next = 0;
@@ -231,6 +235,12 @@ void fmm_apply_nodes(dc_scene_s& s, const double* sigma, const double* mu, doubl
                      const dc_eval_opts& o, hipStream_t st);
 void fmm_render(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o, int out_dtype,
                 void* out, hipStream_t st);
+// dc_render without allocating: device scratch from a fixed array of
+// DC_NOALLOC_SCRATCH_BYTES, every launch on st (throws DC_ERR_INVALID when
+// the scene is not prepared for o's order and precision, or the render needs
+// more scratch).
+void fmm_render_noalloc(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
+                        int out_dtype, void* out, hipStream_t st);
 // Render of n viewports in one set of launches (outs[v] is [H][W][3]).
 void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,
                       int out_dtype, void* const* outs, hipStream_t st);

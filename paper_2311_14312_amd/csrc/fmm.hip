@@ -32,6 +32,12 @@
 
 #include "scene.h"
 
+// Device scratch of dc_render_noalloc (DC_NOALLOC_SCRATCH_BYTES per GPU,
+// held until the process ends).  In host code this name is only a stand-in
+// for the symbol: host code uses the address hipGetSymbolAddress returns
+// for the current device (noalloc_scratch_ptr), never the name itself.
+static __device__ __align__(256) char dc_noalloc_scratch[DC_NOALLOC_SCRATCH_BYTES];
+
 namespace dc {
 
 namespace {
@@ -2202,13 +2208,17 @@ void launch_fused(FmmState& f, const RenderPlan& pl, const dc_eval_opts& o, int 
 // already written to the pinned host buffer `stage` (RenderPlan::write_tables).
 // One downward launch per level covers every viewport that reaches it, and
 // one leaf launch covers every viewport's pixel tiles.
+// stage: pinned host memory holding the plan's descriptor tables, copied to
+// the head of scratch first; null when the caller has already put them
+// there.  allow_aux = false keeps every launch on st (no second stream).
 template <typename T>
 void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_eval_opts& o,
                      int out_dtype, char* scratch, const void* stage, bool timed,
-                     unsigned long long* stats, hipStream_t st) {
+                     unsigned long long* stats, hipStream_t st, bool allow_aux = true) {
     const int p = o.p;
     DC_REQUIRE(pl.p == p && pl.tile_px == o.tile_px, "render plan does not match the options");
-    DC_HIP(hipMemcpyAsync(scratch, stage, pl.desc_bytes, hipMemcpyHostToDevice, st));
+    if (stage != nullptr)
+        DC_HIP(hipMemcpyAsync(scratch, stage, pl.desc_bytes, hipMemcpyHostToDevice, st));
     const VpLevel* d_lev = reinterpret_cast<const VpLevel*>(scratch);
     const VpLeaf* d_leaf = reinterpret_cast<const VpLeaf*>(scratch + pl.leaf_at);
     cpx<double>* TL = reinterpret_cast<cpx<double>*>(scratch + pl.tl_at);
@@ -2304,7 +2314,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             // large renders: queued tiles on the second stream, concurrently
             // with k_tile; small ones keep everything on st, so renders on
             // different caller streams do not queue behind one another on it
-            const bool overlap = pl.leaf_blocks >= kOverlapTiles;
+            const bool overlap = allow_aux && pl.leaf_blocks >= kOverlapTiles;
             std::unique_lock<std::mutex> aux_lock(f.aux_mu, std::defer_lock);
             if (overlap) aux_lock.lock();
             hipStream_t aux = overlap ? f.aux_stream() : st;
@@ -2731,6 +2741,77 @@ void fmm_graph_launch(RenderGraph& g, hipStream_t st) {
                "the scene's resident expansions were rebuilt since the render graph was made "
                "(make the graph again)");
     DC_HIP(hipGraphLaunch(g.exec, st));
+}
+
+namespace {
+
+// Per-device address of dc_noalloc_scratch, looked up once per device with
+// that device current (each GPU holds its own copy of the array).
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxDevices] = {};
+
+char* noalloc_scratch_ptr() {
+    int dev = 0;
+    DC_HIP(hipGetDevice(&dev));
+    DC_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        DC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(dc_noalloc_scratch)));
+        DC_REQUIRE(p != nullptr, "no device address for the allocation-free scratch");
+        g_noalloc_ptr[dev] = static_cast<char*>(p);
+    }
+    return g_noalloc_ptr[dev];
+}
+
+// Descriptor tables reach the device scratch as kernel arguments, in chunks
+// (no copy from host memory, so the launches can be captured in a graph).
+constexpr int kPutChunk = 2048;
+struct PutChunk {
+    unsigned int off, n;
+    unsigned char b[kPutChunk];
+};
+
+__global__ void __launch_bounds__(256) k_put_bytes(PutChunk c, char* __restrict__ dst) {
+    for (unsigned int i = threadIdx.x; i < c.n; i += blockDim.x) dst[c.off + i] = (char)c.b[i];
+}
+
+}  // namespace
+
+void fmm_render_noalloc(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts& o,
+                        int out_dtype, void* out, hipStream_t st) {
+    FmmState& f = *s.fmm;
+    fmm_check_stall(f);
+    const int prec = o.precision == DC_PREC_F32 ? 4 : 8;
+    DC_REQUIRE(f.up_valid && f.up_p == o.p && f.up_prec == prec && f.m2l_tab.count(o.p) == 1,
+               "dc_render_noalloc: the scene is not prepared for this order and precision "
+               "(render it once with dc_render, or register it with a server, using the "
+               "same order and precision first)");
+    RenderPlan& pl = f.noalloc_plan;
+    plan_render(f, &vp, 1, o.tile_px, o.p, pl);
+    if (pl.scratch_bytes > (size_t)DC_NOALLOC_SCRATCH_BYTES)
+        throw Error(DC_ERR_INVALID,
+                    "dc_render_noalloc: this render needs " + std::to_string(pl.scratch_bytes) +
+                        " bytes of scratch, more than DC_NOALLOC_SCRATCH_BYTES (" +
+                        std::to_string((size_t)DC_NOALLOC_SCRATCH_BYTES) +
+                        "); use dc_render, a smaller viewport or larger tiles");
+    char* scr = noalloc_scratch_ptr();
+    f.noalloc_tables.resize(pl.desc_bytes);
+    void* outs[1] = {out};
+    pl.write_tables(f.noalloc_tables.data(), outs);
+    for (size_t off = 0; off < pl.desc_bytes; off += kPutChunk) {
+        PutChunk c;
+        c.off = (unsigned int)off;
+        c.n = (unsigned int)std::min<size_t>(kPutChunk, pl.desc_bytes - off);
+        std::memcpy(c.b, f.noalloc_tables.data() + off, c.n);
+        hipLaunchKernelGGL(k_put_bytes, dim3(1), dim3(256), 0, st, c, scr);
+        DC_HIP(hipGetLastError());
+    }
+    if (o.precision == DC_PREC_F32)
+        launch_render_t<float>(s, f, pl, o, out_dtype, scr, nullptr, false, nullptr, st, false);
+    else
+        launch_render_t<double>(s, f, pl, o, out_dtype, scr, nullptr, false, nullptr, st, false);
 }
 
 void fmm_render_batch(dc_scene_s& s, const dc_viewport* vps, int n, const dc_eval_opts& o,

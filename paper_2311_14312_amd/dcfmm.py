@@ -148,6 +148,7 @@ def _load():
         "dc_set_densities": (I, [P, dp]),
         "dc_apply_operator": (I, [P, V, V, I, C.POINTER(EvalOpts), V]),
         "dc_render": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, V, V]),
+        "dc_render_noalloc": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, V, V]),
         "dc_render_batch": (I, [P, C.POINTER(Viewport), I, C.POINTER(EvalOpts), I,
                                 C.POINTER(V), V]),
         "dc_eval_points": (I, [P, V, I, C.POINTER(EvalOpts), I, V, V]),
@@ -320,6 +321,19 @@ class Scene:
         o = eval_opts(**ev)
         _check(_lib.dc_render(self._h, C.byref(vp), C.byref(o), code,
                               C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def render_noalloc(self, viewport, out, **ev):
+        """dc_render_noalloc: render into the caller's tensor `out` with the
+        library's fixed device scratch (nothing is allocated)."""
+        import torch
+        cx, cy, w, h, W, H = viewport
+        vp = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == (H, W, 3)
+        code = {torch.float32: OUT_F32, torch.float64: OUT_F64}[out.dtype]
+        o = eval_opts(**ev)
+        _check(_lib.dc_render_noalloc(self._h, C.byref(vp), C.byref(o), code,
+                                      C.c_void_p(out.data_ptr()), _stream()))
         return out
 
     def render_batch(self, viewports, outs=None, out_dtype=None, **ev):
