@@ -116,17 +116,19 @@ def test_c4_batch_with_oracle_densities(c4):
     outs = s.render_batch(vps, method="fmm", precision="f32", p=16, tile_px=16)
     e32 = _sampled_err(outs, g)
     del outs
-    outs = s.render_batch(vps, out_dtype=torch.float64, method="fmm", p=40, tile_px=16)
+    outs = s.render_batch(vps, out_dtype=torch.float64, method="fmm", p=28, tile_px=16)
     e64 = _sampled_err(outs, g)
-    print(f"C4 batch vs oracle: FP32 max {e32.max():.3e}  FP64 p=40 max {e64.max():.3e}",
+    print(f"C4 batch vs oracle: FP32 max {e32.max():.3e}  FP64 p=28 max {e64.max():.3e}",
           flush=True)
     # spot-check batch == alone on the largest and the most zoomed viewports
     big = int(np.argmax([v[4] for v in vps]))
     deep = int(np.argmin([v[2] for v in vps]))
     for i in {big, deep}:
-        alone = s.render(vps[i], out_dtype=torch.float64, method="fmm", p=40, tile_px=16)
+        alone = s.render(vps[i], out_dtype=torch.float64, method="fmm", p=28, tile_px=16)
         assert torch.equal(alone, outs[i])
-    assert e64.max() <= 1e-8
+    # the FP64 bar (measured 1.2e-11 at p = 28, the library's direct sum
+    # agreeing with the oracle to the same 1.2e-11)
+    assert e64.max() <= 1e-10
     assert e32.max() <= 1e-4
 
 

@@ -2,7 +2,19 @@
 segments, 2048 x 2048 pixels), in the launch configuration bench.py times,
 checked at 1,536 sampled pixels (stride-64 grid + pixels holding chord
 midpoints) against stored FP64 oracle values (tests/golden, written by the
-committed scripts there from the oracle's dense LU densities)."""
+committed scripts there from the oracle's dense LU densities).
+
+FP64 bar.  The FMM's own error (truncation and arithmetic) is measured
+against the library's FP64 direct sum on the same geometry and must be
+<= 1e-10 (order 28 and up).  Against the oracle the agreement is limited by
+the workload itself: one curve has a near-cusp with densities up to 1e7 and
+cancelling charges (sum |q| ~ 1e4 for a net charge ~ 1), and the oracle's own
+pixel values move by up to 1.2e-9 (densities held) and 1.6e-8 (densities
+re-solved) when its chord end points are rounded differently by one ulp
+(tests/golden/c2_sensitivity.npz, written by the oracle alone).  Two
+independent FP64 discretisations differ by such roundings, so the bars
+against the oracle are 1e-10 plus that measured change (twice it for the
+re-solved densities, whose geometry differs in more than one rounding)."""
 import os
 
 import numpy as np
@@ -18,12 +30,27 @@ CFG = scenegen.FMM
 VP = CFG["viewport"]
 
 
+P64 = 28  # FP64 order whose FMM error is <= 1e-10 on this workload
+
+
 @pytest.fixture(scope="module")
 def gold():
     s = np.load(os.path.join(GOLD, "c2_sigma.npz"))
     t = np.load(os.path.join(GOLD, "c2_samples.npz"))
+    z = np.load(os.path.join(GOLD, "c2_sensitivity.npz"))
+    assert np.array_equal(z["rows"], t["rows"]) and np.array_equal(z["cols"], t["cols"])
     return dict(sigma=s["sigma"], node_xy=s["node_xy"], rows=t["rows"], cols=t["cols"],
-                vals=t["vals"])
+                vals=t["vals"], bar_render=1e-10 + float(z["render"].max()),
+                bar_solve=1e-10 + 2.0 * float(z["solve"].max()))
+
+
+def _direct(scene, gold):
+    """The library's FP64 direct sum at the sampled pixel centres."""
+    import torch
+    import oracle
+    xs, ys = oracle.pixel_centres(VP)
+    pts = torch.tensor(np.stack([xs[gold["cols"]], ys[gold["rows"]]], axis=1), device="cuda")
+    return scene.eval_points(pts, method="direct").cpu().numpy()
 
 
 @pytest.fixture(scope="module")
@@ -50,11 +77,14 @@ def test_c2_render_with_oracle_densities(scene, gold):
     scene.set_densities(gold["sigma"])
     img32 = scene.render(VP, method="fmm", precision="f32", p=16, tile_px=8).cpu().numpy()
     img64 = scene.render(VP, out_dtype=torch.float64, method="fmm", precision="f64",
-                         p=40).cpu().numpy()
+                         p=P64).cpu().numpy()
     e32, e64 = _err(img32, gold), _err(img64, gold)
-    print(f"C2 render vs oracle (oracle densities): FP32 {e32:.3e}  FP64 p=40 {e64:.3e}",
+    fmm_own = np.abs(img64[gold["rows"], gold["cols"]] - _direct(scene, gold)).max()
+    print(f"C2 render (oracle densities): FP32 vs oracle {e32:.3e}; FP64 p={P64} vs oracle "
+          f"{e64:.3e} (bar {gold['bar_render']:.3e}), vs library direct sum {fmm_own:.3e}",
           flush=True)
-    assert e64 <= 1e-8
+    assert fmm_own <= 1e-10
+    assert e64 <= gold["bar_render"]
     assert e32 <= 1e-4
 
 
@@ -63,12 +93,13 @@ def test_c2_solve_and_render(scene, gold):
     print("C2 FMM GMRES", rep, flush=True)
     import torch
     img32 = scene.render(VP, method="fmm", precision="f32", p=16, tile_px=8).cpu().numpy()
-    img64 = scene.render(VP, out_dtype=torch.float64, method="fmm", p=40).cpu().numpy()
+    img64 = scene.render(VP, out_dtype=torch.float64, method="fmm", p=P64).cpu().numpy()
     e32, e64 = _err(img32, gold), _err(img64, gold)
-    print(f"C2 end-to-end render vs oracle: FP32 {e32:.3e}  FP64 p=40 {e64:.3e}", flush=True)
+    print(f"C2 end-to-end render vs oracle: FP32 {e32:.3e}  FP64 p={P64} {e64:.3e} "
+          f"(bar {gold['bar_solve']:.3e})", flush=True)
     assert rep["converged"]
     assert e32 <= 1e-4
-    assert e64 <= 1e-6
+    assert e64 <= gold["bar_solve"]
 
 
 @pytest.fixture(scope="module")
@@ -84,16 +115,19 @@ def scene4(gpu_lib, gold):
 
 
 def test_c2_render_bench_configuration(scene4, gold):
-    """Leaf 4, 8-pixel tiles, FP32 p = 12 and FP64 p = 20: the timed step."""
+    """Leaf 4, 8-pixel tiles, FP32 p = 12 and the FP64 comparator at p = 28:
+    the timed step."""
     import torch
     img32 = scene4.render(VP, method="fmm", precision="f32", p=12, tile_px=8).cpu().numpy()
-    img64 = scene4.render(VP, out_dtype=torch.float64, method="fmm", precision="f64", p=20,
+    img64 = scene4.render(VP, out_dtype=torch.float64, method="fmm", precision="f64", p=P64,
                           tile_px=8).cpu().numpy()
     e32, e64 = _err(img32, gold), _err(img64, gold)
-    print(f"C2 bench configuration vs oracle: FP32 p=12 {e32:.3e}  FP64 p=20 {e64:.3e}",
-          flush=True)
+    fmm_own = np.abs(img64[gold["rows"], gold["cols"]] - _direct(scene4, gold)).max()
+    print(f"C2 bench configuration vs oracle: FP32 p=12 {e32:.3e}  FP64 p={P64} {e64:.3e}; "
+          f"FP64 vs library direct sum {fmm_own:.3e}", flush=True)
     assert e32 <= 1e-4
-    assert e64 <= 1e-6
+    assert fmm_own <= 1e-10
+    assert e64 <= gold["bar_render"]
 
 
 def test_c2_fp32_arithmetic_floor(scene4, gold):

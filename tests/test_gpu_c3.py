@@ -63,9 +63,11 @@ def test_c3_render_fp32_and_fp64(c3):
     img32 = s.render(vp, method="fmm", precision="f32", p=12, tile_px=8).cpu().numpy()
     m32, r32 = _errs(img32, g)
     del img32
-    img64 = s.render(vp, out_dtype=torch.float64, method="fmm", p=30, tile_px=8).cpu().numpy()
+    img64 = s.render(vp, out_dtype=torch.float64, method="fmm", p=28, tile_px=8).cpu().numpy()
     m64, r64 = _errs(img64, g)
-    print(f"C3 render vs oracle: FP32 max {m32:.3e} rms {r32:.3e}; FP64 p=30 max {m64:.3e} "
+    print(f"C3 render vs oracle: FP32 max {m32:.3e} rms {r32:.3e}; FP64 p=28 max {m64:.3e} "
           f"rms {r64:.3e}", flush=True)
     assert m32 <= 1e-4
-    assert m64 <= 1e-8
+    # the FP64 bar (smooth densities: no near-cusp amplification of geometry
+    # rounding here, measured 1.2e-11 at p = 28)
+    assert m64 <= 1e-10
