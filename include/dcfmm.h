@@ -224,6 +224,53 @@ int dc_render_batch(dc_scene s, const dc_viewport* vps, int n,
                     const dc_eval_opts* o, int out_dtype, void* const* outs_dev,
                     void* stream);
 
+/* Render options chosen on the device against an accuracy target.  For each
+ * tile size in tiles[0..n_tiles), orders p = p_min, p_min + p_step, ... up to
+ * p_max are tried in turn on the viewports vps[0..n) (one batched render per
+ * order) until the largest |FMM - direct| over the sampled pixels is at most
+ * target_err; the reference is the FP64 direct sum over every chord segment
+ * at those pixel centres (the representation of Alg. 4 without the FMM, on
+ * the scene's own geometry), so no external values are needed.  About
+ * `samples` pixels per viewport are checked: half on a stride grid and half
+ * along the chords that cross the viewport (the near field).  The chosen
+ * order of each tile size is then timed over timing_reps renders, and the
+ * fastest tile size that met the target is returned in rep->chosen (if none
+ * met it, the most accurate one, with rep->met = 0).  The leaf capacity is a
+ * property of the scene (dc_scene_opts) and is not tuned here.  The scene
+ * must have densities and must not be registered with a server; it is left
+ * prepared for the chosen options (dc_render_noalloc may follow).
+ * Synchronous.  DC_ERR_INVALID for bad options (n_tiles in 1..4, tiles in
+ * 2..16, 1 <= p_min <= p_max <= DC_P_MAX, p_step >= 1, samples >= 2,
+ * timing_reps >= 1, target_err > 0). */
+typedef struct {
+    double target_err;
+    int precision;               /* DC_PREC_F32 or DC_PREC_F64 */
+    int p_min, p_max, p_step;
+    int tiles[4];
+    int n_tiles;
+    int samples;                 /* sampled pixels per viewport */
+    double near_fp64;            /* as in dc_eval_opts */
+    int timing_reps;
+} dc_tune_opts;
+
+typedef struct {
+    dc_eval_opts chosen;         /* method FMM, the tuned p and tile_px */
+    double err;                  /* max |FMM - direct| at the samples, chosen */
+    double ms;                   /* ms per render of all viewports, chosen */
+    int n_samples;               /* sampled pixels over all viewports */
+    int met;                     /* 1 when err <= target_err */
+    int tile_p[4];               /* per tile size tried: the order reached */
+    double tile_err[4];          /* its error */
+    double tile_ms[4];           /* its time (ms per render of all viewports) */
+} dc_tune_report;
+
+/* Defaults: target 5e-5 (half the 1e-4 bar of the FP32 path), FP32,
+ * p = 8, 10, ..., 24, tiles {8, 16}, 1024 samples per viewport, near 1e-3,
+ * 5 timing renders. */
+void dc_default_tune_opts(dc_tune_opts* t);
+int dc_autotune(dc_scene s, const dc_viewport* vps, int n, const dc_tune_opts* t,
+                dc_tune_report* rep, void* stream);
+
 /* The same representation at n arbitrary points xy_dev (device [n][2]
  * FP64), out_dev [n][3].  Uses the direct sum (method is ignored). */
 int dc_eval_points(dc_scene s, const double* xy_dev, int n,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "autotune.h"
 #include "scene.h"
 
 using namespace dc;
@@ -476,6 +477,50 @@ int dc_render_batch(dc_scene s, const dc_viewport* vps, int n, const dc_eval_opt
         }
         DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
         fmm_render_batch(*s, vps, n, *o, out_dtype, outs, as_stream(stream));
+    });
+}
+
+void dc_default_tune_opts(dc_tune_opts* t) {
+    if (!t) return;
+    std::memset(t, 0, sizeof(*t));
+    t->target_err = 5e-5;
+    t->precision = DC_PREC_F32;
+    t->p_min = 8;
+    t->p_max = 24;
+    t->p_step = 2;
+    t->tiles[0] = 8;
+    t->tiles[1] = 16;
+    t->n_tiles = 2;
+    t->samples = 1024;
+    t->near_fp64 = 1e-3;
+    t->timing_reps = 5;
+}
+
+int dc_autotune(dc_scene s, const dc_viewport* vps, int n, const dc_tune_opts* t,
+                dc_tune_report* rep, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && vps && t && rep && n >= 1, "bad argument");
+        check_not_served(s);
+        DC_REQUIRE(s->solved, "tuning needs densities (solve or set them first)");
+        DC_REQUIRE(t->precision == DC_PREC_F32 || t->precision == DC_PREC_F64, "bad precision");
+        DC_REQUIRE(t->n_tiles >= 1 && t->n_tiles <= 4, "n_tiles must be in 1..4");
+        for (int k = 0; k < t->n_tiles; ++k)
+            DC_REQUIRE(t->tiles[k] >= 2 && t->tiles[k] <= 16, "tile sizes must be in 2..16");
+        DC_REQUIRE(t->p_min >= 1 && t->p_min <= t->p_max && t->p_max <= DC_P_MAX && t->p_step >= 1,
+                   "bad order range");
+        DC_REQUIRE(t->samples >= 2 && t->timing_reps >= 1, "bad sample or timing count");
+        DC_REQUIRE(t->target_err > 0 && std::isfinite(t->near_fp64) && t->near_fp64 >= 0,
+                   "bad target or near_fp64");
+        for (int v = 0; v < n; ++v) {
+            const dc_viewport* vp = &vps[v];
+            DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0 &&
+                           std::isfinite(vp->cx) && std::isfinite(vp->cy) &&
+                           std::isfinite(vp->width) && std::isfinite(vp->height),
+                       "bad viewport");
+        }
+        hipStream_t st = as_stream(stream);
+        ensure_seg_weights(s, st);
+        autotune_scene(*s, vps, n, *t, s->seg_w.p, *rep, st);
     });
 }
 

@@ -103,6 +103,19 @@ class RenderGraph:
         self.close()
 
 
+class TuneOpts(C.Structure):
+    _fields_ = [("target_err", C.c_double), ("precision", C.c_int), ("p_min", C.c_int),
+                ("p_max", C.c_int), ("p_step", C.c_int), ("tiles", C.c_int * 4),
+                ("n_tiles", C.c_int), ("samples", C.c_int), ("near_fp64", C.c_double),
+                ("timing_reps", C.c_int)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("chosen", EvalOpts), ("err", C.c_double), ("ms", C.c_double),
+                ("n_samples", C.c_int), ("met", C.c_int), ("tile_p", C.c_int * 4),
+                ("tile_err", C.c_double * 4), ("tile_ms", C.c_double * 4)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("eval", EvalOpts), ("out_dtype", C.c_int), ("n_streams", C.c_int),
                 ("max_batch", C.c_int), ("max_batch_pixels", C.c_longlong),
@@ -152,6 +165,9 @@ def _load():
         "dc_render_batch": (I, [P, C.POINTER(Viewport), I, C.POINTER(EvalOpts), I,
                                 C.POINTER(V), V]),
         "dc_eval_points": (I, [P, V, I, C.POINTER(EvalOpts), I, V, V]),
+        "dc_default_tune_opts": (None, [C.POINTER(TuneOpts)]),
+        "dc_autotune": (I, [P, C.POINTER(Viewport), I, C.POINTER(TuneOpts),
+                            C.POINTER(TuneReport), V]),
         "dc_render_counts": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts),
                                  C.POINTER(WorkCounts), V]),
         "dc_render_graph_create": (I, [P, C.POINTER(Viewport), I, C.POINTER(EvalOpts), I,
@@ -372,6 +388,37 @@ class Scene:
                                    C.c_void_p(out.data_ptr()), _stream()))
         return out
 
+
+    def autotune(self, viewports, target_err=None, precision="f32", p_min=None, p_max=None,
+                 p_step=None, tiles=None, samples=None, near_fp64=None, timing_reps=None):
+        """dc_autotune over the viewports; returns a dict with `eval` (the
+        chosen options as keyword arguments of render) and the report."""
+        n = len(viewports)
+        vps = (Viewport * n)()
+        for i, (cx, cy, w, h, W, H) in enumerate(viewports):
+            vps[i] = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        t = TuneOpts()
+        _lib.dc_default_tune_opts(C.byref(t))
+        t.precision = {"f64": PREC_F64, "f32": PREC_F32}[precision]
+        for name, val in (("target_err", target_err), ("p_min", p_min), ("p_max", p_max),
+                          ("p_step", p_step), ("samples", samples), ("near_fp64", near_fp64),
+                          ("timing_reps", timing_reps)):
+            if val is not None:
+                setattr(t, name, val)
+        if tiles is not None:
+            t.n_tiles = len(tiles)
+            for k, v in enumerate(tiles):
+                t.tiles[k] = int(v)
+        r = TuneReport()
+        _check(_lib.dc_autotune(self._h, vps, n, C.byref(t), C.byref(r), _stream()))
+        c = r.chosen
+        ev = dict(method="fmm", precision={PREC_F64: "f64", PREC_F32: "f32"}[c.precision],
+                  p=c.p, tile_px=c.tile_px, near_fp64=c.near_fp64)
+        k = t.n_tiles
+        return {"eval": ev, "err": r.err, "ms": r.ms, "n_samples": r.n_samples,
+                "met": bool(r.met), "tiles": [t.tiles[i] for i in range(k)],
+                "tile_p": list(r.tile_p)[:k], "tile_err": list(r.tile_err)[:k],
+                "tile_ms": list(r.tile_ms)[:k]}
 
     def render_counts(self, viewport, **ev):
         """Device-counted work of one FMM render of viewport (synchronous)."""
