@@ -68,6 +68,12 @@ def leaf_flops(c, p):
             + c["l2p_targets"] * flops_l2p(p))
 
 
+def p64_of(args):
+    """FP64 order of the side workloads: 28 reaches the FP64 bar on them
+    (measured against the oracle and the device's direct sum)."""
+    return args.p64 if args.p64 > 0 else 28
+
+
 def sample_pixels(W, H, segs_p1, segs_p2, rng, n_near=4096, stride=16):
     rows, cols = np.meshgrid(np.arange(stride // 2, H, stride),
                              np.arange(stride // 2, W, stride), indexing="ij")
@@ -80,10 +86,29 @@ def sample_pixels(W, H, segs_p1, segs_p2, rng, n_near=4096, stride=16):
     return r, c
 
 
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(cfg, sc, workers):
     """Oracle on the host cores: discretisation, then the direct-sum render
-    of a bounded pixel sample (timed) with the golden oracle densities."""
+    of a bounded pixel sample (timed) with the golden oracle densities.
+    One worker process per core, each with one BLAS thread (set before the
+    workers are forked), so `workers` is the number of threads used."""
     import oracle
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(oracle, cfg, sc, workers)
+
+
+def _cpu_baseline(oracle, cfg, sc, workers):
     t0 = time.time()
     disc = oracle.discretize(sc["ctrl"], cfg["panels"], cfg["gl"], cfg["segs"], workers=workers)
     t_disc = time.time() - t0
@@ -141,7 +166,6 @@ def batch_bench(args, torch, dcfmm):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    orders = [int(v) for v in args.batch_orders.split(",")]
     tune, best, scenes = [], None, {}
     for leaf in [int(v) for v in args.batch_leaves.split(",")]:
         scn = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
@@ -153,21 +177,18 @@ def batch_bench(args, torch, dcfmm):
         else:
             rep = scn.solve(tol=1e-10, max_iter=1000, method="fmm", p=20)
         scenes[leaf] = (scn, rep)
-        for tile in (8, 16):
-            chosen = orders[-1]
-            if gold is not None:
-                for pp in orders:
-                    scn.render_batch(vps, outs=outs, method="fmm", precision="f32", p=pp,
-                                     tile_px=tile)
-                    if err(outs) <= 5e-5:
-                        chosen = pp
-                        break
-            ev = dict(method="fmm", precision="f32", p=chosen, tile_px=tile)
-            ms = time_it(lambda: scn.render_batch(vps, outs=outs, **ev), 3, 1)
-            tune.append({"leaf": leaf, "tile": tile, "p": chosen, "ms": ms})
-            print("batch autotune", tune[-1], flush=True)
-            if best is None or ms < best["ms"]:
-                best = dict(tune[-1])
+        # order and tile size from dc_autotune over all 64 viewports (its own
+        # sampled pixels against the device's FP64 direct sum); the stored
+        # oracle pixels stay held out for the reported error
+        tr = scn.autotune(vps, target_err=5e-5, precision="f32", p_min=8, p_max=24, p_step=2,
+                          tiles=(8, 16), samples=256, timing_reps=2)
+        ev = tr["eval"]
+        ms = time_it(lambda: scn.render_batch(vps, outs=outs, **ev), 3, 1)
+        tune.append({"leaf": leaf, "tile": ev["tile_px"], "p": ev["p"], "ms": ms,
+                     "tuner_err": tr["err"], "tuner_samples": tr["n_samples"]})
+        print("batch autotune", tune[-1], flush=True)
+        if best is None or ms < best["ms"]:
+            best = dict(tune[-1])
     scn, rep = scenes[best["leaf"]]
     ev32 = dict(method="fmm", precision="f32", p=best["p"], tile_px=best["tile"])
     ms_batch = time_it(lambda: scn.render_batch(vps, outs=outs, **ev32), args.steps,
@@ -181,7 +202,7 @@ def batch_bench(args, torch, dcfmm):
     ms_seq = time_it(lambda: one_by_one(ev32, outs), max(1, args.steps // 2), 1)
     del outs
     outs64 = [torch.empty((v[5], v[4], 3), device="cuda", dtype=torch.float64) for v in vps]
-    ev64 = dict(method="fmm", precision="f64", p=args.p64, tile_px=best["tile"])
+    ev64 = dict(method="fmm", precision="f64", p=p64_of(args), tile_px=best["tile"])
     ms64 = time_it(lambda: one_by_one(ev64, outs64), max(1, args.steps // 4), 1)
     e64 = err(outs64)
     del outs64
@@ -197,7 +218,7 @@ def batch_bench(args, torch, dcfmm):
         "err_sample": None if gold is None else f"{len(gold['vals'])} oracle pixels "
                                                 "(8x8 grid + 8x8 centre block per viewport)",
         "one_at_a_time_fp32": {"value": px / (ms_seq * 1e-3), "ms": ms_seq},
-        "one_at_a_time_fp64": {"value": px / (ms64 * 1e-3), "ms": ms64, "p": args.p64,
+        "one_at_a_time_fp64": {"value": px / (ms64 * 1e-3), "ms": ms64, "p": p64_of(args),
                                "max_err_vs_oracle": e64},
         "densities": "oracle (stored)" if gold is not None else "GPU FMM GMRES",
         "autotune": tune,
@@ -246,7 +267,8 @@ def precision_bench(args, torch, dcfmm):
     for name, ev, dtype in (
             ("fp32", dict(method="fmm", precision="f32", p=args.precision_p32, tile_px=8),
              torch.float32),
-            ("fp64", dict(method="fmm", precision="f64", p=args.p64, tile_px=8), torch.float64)):
+            ("fp64", dict(method="fmm", precision="f64", p=p64_of(args), tile_px=8),
+             torch.float64)):
         ms, img = timed(ev, dtype, 3)
         mx, rms = errs(img)
         del img
@@ -279,27 +301,40 @@ def serving_bench(args, torch, dcfmm):
     t0 = time.time()
     raw = scenegen.serving_scenes(n_scenes=cfg["n_scenes"], seed0=cfg["seed0"],
                                   panels=cfg["panels"], gl=cfg["gl"], segs=cfg["segs"])
-    scenes, solve = [], []
+    n_req, n_warm = cfg["n_requests"], cfg["n_warmup"]
+    reqs = scenegen.serving_requests(raw, n_req + n_warm, seed=7)
+    first_req = {}
+    for i, (k, vp) in enumerate(reqs):
+        first_req.setdefault(k, i)
+    scenes, solve, tuned = [], [], []
     for k, sc in enumerate(raw):
         s = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
-                        gl=cfg["gl"], segs=cfg["segs"], leaf_max=32, domain=cfg["domain"])
-        # densities for timing renders: a bounded solve (scenes with thousands
-        # of random crossing curves converge slowly; the residual is reported)
-        rep = s.solve(tol=1e-6, max_iter=300, method="fmm", p=16, raise_on_fail=False)
+                        gl=cfg["gl"], segs=cfg["segs"], leaf_max=32,
+                        domain=scenegen.serving_domain(sc))
+        rep = s.solve(tol=1e-6, max_iter=1000, method="fmm", p=16, raise_on_fail=False)
+        # render options of the scene: dc_autotune on its first request of
+        # the stream (FP32, target 5e-5 against the device's FP64 direct sum)
+        if args.serve_p > 0:
+            ev = dict(method="fmm", precision="f32", p=args.serve_p, tile_px=args.serve_tile)
+            tr = None
+        else:
+            tr = s.autotune([reqs[first_req[k]][1]], target_err=5e-5, precision="f32",
+                            tiles=(8, 16), samples=1024, timing_reps=2)
+            ev = tr["eval"]
+        tuned.append(ev)
         solve.append({"curves": int(sc["ctrl"].shape[0]), "N": s.info()["N"],
                       "iters": max(rep["iters"]), "s": round(rep["seconds"], 3),
                       "rel_residual": max(rep["true_rel_residual"]),
-                      "converged": bool(rep["converged"])})
+                      "converged": bool(rep["converged"]),
+                      "p": ev["p"], "tile_px": ev["tile_px"],
+                      "tune_err": None if tr is None else tr["err"]})
         print("serving scene", k, solve[-1], flush=True)
         scenes.append(s)
     t_setup = time.time() - t0
-    ev = dict(precision="f32", p=args.serve_p, tile_px=args.serve_tile)
-    srv = dcfmm.Server(**ev, n_streams=4, max_batch=32, max_batch_pixels=1 << 25,
+    srv = dcfmm.Server(precision="f32", n_streams=4, max_batch=32, max_batch_pixels=1 << 25,
                        hbm_budget=32 << 30)
-    for s in scenes:
-        srv.add_scene(s)
-    n_req, n_warm = cfg["n_requests"], cfg["n_warmup"]
-    reqs = scenegen.serving_requests(raw, n_req + n_warm, seed=7)
+    for s, ev in zip(scenes, tuned):
+        srv.add_scene(s, **ev)
     sink = torch.empty(2048 * 2048 * 3, device="cuda", dtype=torch.float32)
 
     def fetch(t, vp):
@@ -354,12 +389,16 @@ def serving_bench(args, torch, dcfmm):
         print("serving", runs[-1], flush=True)
     st = srv.stats()
     srv.close()
+    check = serving_oracle_check(dcfmm, scenes, tuned, reqs)
     for s in scenes:
         s.close()
     return {
-        "workload": "16 resident scenes (10-5000 curves, log-uniform; 16 panels x 16 GL "
-                    "nodes), requests 256-2048 px a side, zoom 10^U(0,6), Poisson arrivals",
-        "p": args.serve_p, "tile_px": args.serve_tile, "precision": "f32",
+        "workload": "16 resident scenes (10-5000 curves, log-uniform, 200 curves per unit "
+                    "area; 16 panels x 16 GL nodes), requests 256-2048 px a side, zoom "
+                    "10^U(0,6), Poisson arrivals",
+        "options": "per scene, dc_autotune on its first request (FP32, target 5e-5)"
+                   if args.serve_p <= 0 else f"fixed p {args.serve_p}, tile {args.serve_tile}",
+        "precision": "f32", "oracle_check": check,
         "capacity_req_s": cap, "capacity_pixels_per_s": cap_px,
         "requests_per_run": n_req, "warmup_per_run": n_warm, "runs": runs,
         "server": {"n_streams": 4, "max_batch": 32, "hbm_budget_GiB": 32,
@@ -369,19 +408,49 @@ def serving_bench(args, torch, dcfmm):
     }
 
 
+def serving_oracle_check(dcfmm, scenes, tuned, reqs):
+    """The first request of every serving scene, served with the scene's
+    options but with synthetic densities (the oracle cannot solve the large
+    scenes), against stored oracle values at 1,024 pixels per request."""
+    path = os.path.join(ROOT, "tests", "golden", "c5_golden.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    srv = dcfmm.Server(precision="f32", n_streams=4, max_batch=16, hbm_budget=16 << 30)
+    errs, rms = [], []
+    try:
+        for k, s in enumerate(scenes):
+            s.set_densities(scenegen.synthetic_densities(s.N))
+            srv.add_scene(s, **tuned[k])
+        tickets = [srv.submit(scenes[int(k)], reqs[int(i)][1])
+                   for i, k in zip(g["req"], g["scene"])]
+        for j, t in enumerate(tickets):
+            srv.wait(t)
+            img = srv.fetch(t).cpu().numpy()
+            a, b = int(g["first"][j]), int(g["first"][j + 1])
+            d = img[g["rows"][a:b], g["cols"][a:b]] - g["vals"][a:b]
+            errs.append(float(np.abs(d).max()))
+            rms.append(float(np.sqrt(np.mean(d * d))))
+    finally:
+        srv.close()
+    return {"requests": len(errs), "pixels_per_request": int(np.diff(g["first"]).max()),
+            "max_err_vs_oracle": max(errs), "rms_err_vs_oracle": float(np.sqrt(np.mean(
+                np.square(rms)))), "per_request_max": errs,
+            "densities": "synthetic (scenegen.synthetic_densities); served with the timed "
+                         "per-scene options"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--orders", default="8,10,12,14,16,18,20",
-                    help="expansion orders tried for the FP32 path (smallest meeting 5e-5)")
-    ap.add_argument("--p64", type=int, default=20, help="expansion order, FP64 path")
+    ap.add_argument("--p64", type=int, default=0,
+                    help="expansion order of the FP64 path (0: dc_autotune to 1e-10)")
     ap.add_argument("--tiles", default="8,16")
     ap.add_argument("--leaves", default="4,8,16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-viewport batch")
-    ap.add_argument("--batch-orders", default="10,12,14,16,18,20,24")
     ap.add_argument("--batch-leaves", default="4,8")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--no-precision", action="store_true",
@@ -391,9 +460,13 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB three times (reference "
                          "for hardware byte counters)")
-    ap.add_argument("--serve-p", type=int, default=12)
+    ap.add_argument("--serve-p", type=int, default=0,
+                    help="fixed serving order (0: per-scene dc_autotune)")
     ap.add_argument("--serve-tile", type=int, default=16)
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    # the host share of one GPU on the measurement boxes is 16 cores,
+    # whatever os.cpu_count() reports there
+    ap.add_argument("--workers", type=int,
+                    default=min(16, len(os.sched_getaffinity(0)) or 1))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -431,7 +504,7 @@ def main():
         sc_ = dcfmm.Scene(sc["ctrl"], sc["left"], sc["right"], panels=cfg["panels"],
                           gl=cfg["gl"], segs=cfg["segs"], leaf_max=leaf)
         t_create = time.time() - t0
-        rep_ = sc_.solve(tol=cfg["gmres_tol"], max_iter=1000, method="fmm", p=args.p64)
+        rep_ = sc_.solve(tol=cfg["gmres_tol"], max_iter=1000, method="fmm", p=cfg["p"])
         print(f"leaf {leaf}: scene {sc_.info()} create {t_create:.2f} s, solve {rep_}",
               flush=True)
         return sc_, rep_, t_create
@@ -455,40 +528,42 @@ def main():
             return None
         return float(np.abs(img[cpu["rows"], cpu["cols"]] - cpu["vals"]).max())
 
-    # Autotune: leaf capacity and tile size by time; for each, the smallest
-    # expansion order whose sampled error against the oracle is <= 5e-5
-    # (half the bar).  Without oracle values the order is fixed.
+    # Autotune: the leaf capacity (a scene property) by time; for each, the
+    # library's dc_autotune picks the expansion order and tile size against
+    # its own FP64 direct sum at sampled pixels (target 5e-5, half the bar).
+    # The oracle pixels that give max_err_vs_oracle are not seen by the tuner.
     leaves = [int(v) for v in args.leaves.split(",")]
-    tiles = [int(v) for v in args.tiles.split(",")]
-    orders = [int(v) for v in args.orders.split(",")]
+    tiles = tuple(int(v) for v in args.tiles.split(","))
     tune = []
     best = None
     scenes = {}
     for leaf in leaves:
         scn, rep, t_create = make_scene(leaf)
         scenes[leaf] = (scn, rep, t_create)
-        for tile in tiles:
-            chosen = orders[-1]
-            if cpu is not None and cpu["vals"] is not None:
-                for pp in orders:
-                    img = scn.render(vp, method="fmm", precision="f32", p=pp, tile_px=tile)
-                    if sample_err(img.cpu().numpy()) <= 5e-5:
-                        chosen = pp
-                        break
-            ev = dict(method="fmm", precision="f32", p=chosen, tile_px=tile)
-            ms, _ = timed(scn, ev, 5, 2, torch.float32)
-            tune.append({"leaf": leaf, "tile": tile, "p": chosen, "ms": ms})
-            print("autotune", tune[-1], flush=True)
-            if best is None or ms < best["ms"]:
-                best = dict(tune[-1])
+        tr = scn.autotune([vp], target_err=5e-5, precision="f32", p_min=8, p_max=24,
+                          p_step=2, tiles=tiles, samples=2048, timing_reps=5)
+        ev = tr["eval"]
+        ms, _ = timed(scn, ev, 5, 2, torch.float32)
+        tune.append({"leaf": leaf, "tile": ev["tile_px"], "p": ev["p"], "ms": ms,
+                     "tuner_err": tr["err"], "tuner_samples": tr["n_samples"],
+                     "per_tile": {"tiles": tr["tiles"], "p": tr["tile_p"], "ms": tr["tile_ms"]}})
+        print("autotune", tune[-1], flush=True)
+        if best is None or ms < best["ms"]:
+            best = dict(tune[-1])
         if best["leaf"] != leaf:
             scn.close()
             del scenes[leaf]
     scene, rep, t_create = scenes[best["leaf"]]
     p32, tile, leaf = best["p"], best["tile"], best["leaf"]
+    # the FP64 comparator's order: dc_autotune against the same direct sum
+    # with the FP64 bar (1e-10) as target
+    tr64 = scene.autotune([vp], target_err=1e-10, precision="f64", p_min=20, p_max=40,
+                          p_step=4, tiles=(tile,), samples=1024, timing_reps=1)
+    p64 = tr64["eval"]["p"] if args.p64 <= 0 else args.p64
+    print(f"FP64 order {p64} (tuner error {tr64['err']:.2e})", flush=True)
 
     ev32 = dict(method="fmm", precision="f32", p=p32, tile_px=tile)
-    ev64 = dict(method="fmm", precision="f64", p=args.p64, tile_px=tile)
+    ev64 = dict(method="fmm", precision="f64", p=p64, tile_px=tile)
     ms32, img32 = timed(scene, ev32, args.steps, args.warmup, torch.float32)
     img32 = img32.cpu().numpy()
     ms64, img64 = timed(scene, ev64, max(1, args.steps // 2), 1, torch.float64)
@@ -530,7 +605,7 @@ def main():
     scene.set_timing(False)
     counts64 = scene.render_counts(vp, **ev64)
     leaf64_ms = tm64["leaf_ms"] / max(1, tm64["calls"])
-    achieved64 = leaf_flops(counts64, args.p64) / (leaf64_ms * 1e-3)
+    achieved64 = leaf_flops(counts64, p64) / (leaf64_ms * 1e-3)
 
     px = W * H
     err32, err64 = sample_err(img32), sample_err(img64)
@@ -552,13 +627,14 @@ def main():
         "config": {"workload": "200 random cubic Beziers (lengths log-uniform 0.01-0.5), "
                                "16 panels x 16 GL nodes (51,200 nodes), 80 segments/panel, "
                                "3 colour stops/side; 2048x2048 render of [0,1]^2",
-                   "p_fp32": p32, "p_fp64": args.p64, "tile_px": tile,
+                   "p_fp32": p32, "p_fp64": p64, "tile_px": tile,
                    "leaf_max": leaf, "gmres_tol": cfg["gmres_tol"], "autotune": tune},
         "max_err_vs_oracle": err32,
         "err_sample": (f"{cpu['n']} pixels (128x128 stride-16 grid + 4096 near-chord)"
                        if cpu else None),
         "fp64_fmm": {"value": px / (ms64 * 1e-3), "unit": "RGB pixels/s", "ms_per_step": ms64,
-                     "max_err_vs_oracle": err64,
+                     "max_err_vs_oracle": err64, "p": p64,
+                     "tuner_err_vs_direct_sum": tr64["err"],
                      "roofline": {"bound": "alu", "achieved": achieved64 / 1e12,
                                   "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                                   "frac": achieved64 / PEAK_FP64}},
@@ -575,13 +651,18 @@ def main():
         "phases_ms": {k: v / max(1, tm["calls"]) for k, v in tm.items() if k.endswith("_ms")},
         "work": counts,
         "solve": {"seconds": rep["seconds"], "iters": rep["iters"], "precond": "block",
-                  "true_rel_residual": rep["true_rel_residual"], "p": args.p64,
+                  "true_rel_residual": rep["true_rel_residual"], "p": cfg["p"],
                   "scene_create_s": t_create},
         "cpu_baseline": None if cpu is None else {
             "value": cpu["value"], "unit": "RGB pixels/s", "cores": args.workers,
             "kind": "oracle",
             "sample": f"{cpu['n']} sampled pixels of the 2048x2048 viewport x {cpu['S']} "
-                      f"segments, FP64 NumPy direct sum ({cpu['seconds']:.1f} s)"},
+                      f"segments, FP64 NumPy direct sum ({cpu['seconds']:.1f} s); value is "
+                      f"the rate on that sample",
+            "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count(),
+            "threads": f"{args.workers} worker processes x 1 BLAS thread",
+            "pairs_per_s": cpu["value"] * cpu["S"],
+            "full_frame_s_extrapolated": W * H / cpu["value"]},
     }
     for scn, _, _ in scenes.values():
         scn.close()

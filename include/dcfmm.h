@@ -345,8 +345,8 @@ int dc_get_timing(dc_scene s, double* ms);
  * Threading: submit, wait, fetch and get_stats may be called from any host
  * threads.  A registered scene is read-only: dc_solve_densities,
  * dc_set_densities, dc_set_boundary and dc_apply_operator fail on it, renders
- * must use the server's order and precision, and dc_scene_destroy leaves it
- * alive, until dc_server_destroy.
+ * must use the order and precision it was registered with, and
+ * dc_scene_destroy leaves it alive, until dc_server_destroy.
  * ------------------------------------------------------------------------ */
 typedef struct dc_server_s* dc_server;
 
@@ -386,6 +386,13 @@ int dc_server_create(const dc_server_opts* o, dc_server* out);
 /* Register a scene with densities and run its upward pass for the server's
  * options (synchronous).  The scene must live on the server's device. */
 int dc_server_add_scene(dc_server sv, dc_scene s);
+
+/* The same with render options of the scene's own (method FMM; e.g. the
+ * order and tile size dc_autotune chose for it): every request of the scene
+ * is rendered with *o, requests of other scenes with theirs.  Images are
+ * written in the server's out_dtype.  Registering a scene again with other
+ * options fails with DC_ERR_INVALID. */
+int dc_server_add_scene_opts(dc_server sv, dc_scene s, const dc_eval_opts* o);
 
 /* Queue a render of vp of registered scene s; *ticket identifies it.
  * Fails with DC_ERR_INVALID for a viewport outside the scene's quadtree

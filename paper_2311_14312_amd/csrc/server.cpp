@@ -3,6 +3,7 @@
 // admission by device footprint from a fixed arena.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -100,6 +101,7 @@ struct dc_server_s {
     Arena arena{0};
     std::vector<Slot> slots;
     std::vector<dc_scene> scenes;
+    std::vector<dc_eval_opts> scene_eval;  // render options of scenes[k]
 
     std::mutex mu;
     std::condition_variable work_cv;  // worker: new requests, freed memory, stop
@@ -121,6 +123,11 @@ struct dc_server_s {
     }
     bool registered(dc_scene s) const {
         return std::find(scenes.begin(), scenes.end(), s) != scenes.end();
+    }
+    // Render options of a registered scene (under mu, or after registration,
+    // which never changes them).
+    const dc_eval_opts& eval_of(dc_scene s) const {
+        return scene_eval[std::find(scenes.begin(), scenes.end(), s) - scenes.begin()];
     }
 
     void run();
@@ -197,10 +204,11 @@ bool dc_server_s::launch_next() {
     std::vector<dc_viewport> vps;
     std::vector<size_t> out_off;
     size_t scratch_off = SIZE_MAX;
+    const dc_eval_opts ev = eval_of(sc);
     while (!pick.empty()) {
         vps.clear();
         for (long long id : pick) vps.push_back(reqs[id].vp);
-        plan_render(*sc->fmm, vps.data(), (int)vps.size(), opts.eval.tile_px, opts.eval.p, pl);
+        plan_render(*sc->fmm, vps.data(), (int)vps.size(), ev.tile_px, ev.p, pl);
         out_off.clear();
         bool ok = true;
         for (long long id : pick) {
@@ -273,8 +281,8 @@ bool dc_server_s::launch_next() {
     stats.bytes_in_use = (long long)arena.used();
     stats.bytes_peak = (long long)arena.peak();
     try {
-        fmm_launch_render(*sc, pl, opts.eval, opts.out_dtype, arena_base + scratch_off,
-                          sl->stage, sl->st);
+        fmm_launch_render(*sc, pl, ev, opts.out_dtype, arena_base + scratch_off, sl->stage,
+                          sl->st);
         DC_HIP(hipEventRecord(sl->done, sl->st));
     } catch (const Error&) {
         // nothing of this batch may still be queued behind a failed launch
@@ -377,21 +385,47 @@ int dc_server_create(const dc_server_opts* o, dc_server* out) {
     });
 }
 
+namespace {
+
+void add_scene(dc_server sv, dc_scene s, const dc_eval_opts& ev) {
+    DC_REQUIRE(s->solved, "the scene has no densities (solve or set them first)");
+    DC_REQUIRE(ev.method == DC_METHOD_FMM, "the server renders with the FMM");
+    DC_REQUIRE(ev.precision == DC_PREC_F64 || ev.precision == DC_PREC_F32, "bad precision");
+    DC_REQUIRE(ev.p >= 1 && ev.p <= DC_P_MAX, "bad expansion order");
+    DC_REQUIRE(ev.tile_px >= 2 && ev.tile_px <= 16, "bad tile_px");
+    DC_REQUIRE(std::isfinite(ev.near_fp64) && ev.near_fp64 >= 0.0, "bad near_fp64");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->registered(s)) {
+        const dc_eval_opts& have = sv->eval_of(s);
+        DC_REQUIRE(have.p == ev.p && have.precision == ev.precision &&
+                       have.tile_px == ev.tile_px && have.near_fp64 == ev.near_fp64,
+                   "the scene is registered with this server under other options");
+        return;
+    }
+    const FmmState& f = *s->fmm;
+    DC_REQUIRE(s->served.load() == 0 ||
+                   (f.up_p == ev.p && f.up_prec == (ev.precision == DC_PREC_F32 ? 4 : 8)),
+               "the scene is registered with a server of another order or precision");
+    fmm_prepare(*s, ev, nullptr);
+    DC_HIP(hipDeviceSynchronize());
+    s->served.fetch_add(1);
+    sv->scenes.push_back(s);
+    sv->scene_eval.push_back(ev);
+}
+
+}  // namespace
+
 int dc_server_add_scene(dc_server sv, dc_scene s) {
     return guarded([&] {
         DC_REQUIRE(sv && s, "null argument");
-        DC_REQUIRE(s->solved, "the scene has no densities (solve or set them first)");
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->registered(s)) return;
-        const FmmState& f = *s->fmm;
-        DC_REQUIRE(s->served.load() == 0 ||
-                       (f.up_p == sv->opts.eval.p &&
-                        f.up_prec == (sv->opts.eval.precision == DC_PREC_F32 ? 4 : 8)),
-                   "the scene is registered with a server of another order or precision");
-        fmm_prepare(*s, sv->opts.eval, nullptr);
-        DC_HIP(hipDeviceSynchronize());
-        s->served.fetch_add(1);
-        sv->scenes.push_back(s);
+        add_scene(sv, s, sv->opts.eval);
+    });
+}
+
+int dc_server_add_scene_opts(dc_server sv, dc_scene s, const dc_eval_opts* o) {
+    return guarded([&] {
+        DC_REQUIRE(sv && s && o, "null argument");
+        add_scene(sv, s, *o);
     });
 }
 
@@ -409,8 +443,13 @@ int dc_server_submit(dc_server sv, dc_scene s, const dc_viewport* vp, long long*
         }
         // The plan of the request alone validates the viewport and gives
         // its smallest footprint (host only; the scene's tree is immutable).
+        dc_eval_opts ev;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            ev = sv->eval_of(s);
+        }
         RenderPlan pl;
-        plan_render(*s->fmm, vp, 1, sv->opts.eval.tile_px, sv->opts.eval.p, pl);
+        plan_render(*s->fmm, vp, 1, ev.tile_px, ev.p, pl);
         const size_t img = sv->image_bytes(*vp);
         if (align_up(img) + align_up(pl.scratch_bytes) > (size_t)sv->opts.hbm_budget)
             throw Error(DC_ERR_OOM, "request needs more device memory than hbm_budget");

@@ -179,6 +179,7 @@ def _load():
         "dc_default_server_opts": (None, [C.POINTER(ServerOpts)]),
         "dc_server_create": (I, [C.POINTER(ServerOpts), C.POINTER(P)]),
         "dc_server_add_scene": (I, [P, P]),
+        "dc_server_add_scene_opts": (I, [P, P, C.POINTER(EvalOpts)]),
         "dc_server_submit": (I, [P, P, C.POINTER(Viewport), C.POINTER(C.c_longlong)]),
         "dc_server_wait": (I, [P, C.c_longlong, C.c_double, C.POINTER(RequestInfo)]),
         "dc_server_fetch": (I, [P, C.c_longlong, V, I]),
@@ -468,8 +469,14 @@ class Server:
         self._shapes = {}
         self._scenes = []
 
-    def add_scene(self, scene):
-        _check(_lib.dc_server_add_scene(self._h, scene._h))
+    def add_scene(self, scene, **ev):
+        """Register a scene; keyword render options (those of render, e.g.
+        the `eval` dict of Scene.autotune) give it options of its own."""
+        if ev:
+            o = eval_opts(**ev)
+            _check(_lib.dc_server_add_scene_opts(self._h, scene._h, C.byref(o)))
+        else:
+            _check(_lib.dc_server_add_scene(self._h, scene._h))
         self._scenes.append(scene)
 
     def submit(self, scene, viewport):

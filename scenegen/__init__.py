@@ -25,7 +25,7 @@ __all__ = [
     "Scene", "uniform_scene", "sized_scene", "clustered_scene",
     "zoom_viewports", "serving_scenes", "polygon_ctrl", "circle_ctrl",
     "bernstein_point", "batch_scene", "serving_requests", "poisson_arrivals",
-    "synthetic_densities",
+    "synthetic_densities", "serving_extent", "serving_domain",
     "TINY", "FMM", "PRECISION", "BATCH", "SERVING",
 ]
 
@@ -143,14 +143,39 @@ def batch_scene(cfg=None):
     return sc, vps
 
 
-def serving_scenes(n_scenes=16, seed0=100, nmin=10, nmax=5000, **kw):
-    """Resident scenes of log-uniform curve counts for the serving loop."""
+def serving_extent(n_curves, per_unit_area=200):
+    """Side of the square [0, a]^2 holding the bbox centres of a serving
+    scene's curves: the unit square up to per_unit_area curves, growing so
+    that larger scenes keep that many curves per unit area."""
+    return max(1.0, float(np.sqrt(n_curves / per_unit_area)))
+
+
+def serving_scenes(n_scenes=16, seed0=100, nmin=10, nmax=5000, per_unit_area=200,
+                   lmin=0.01, lmax=0.5, **kw):
+    """Resident scenes of log-uniform curve counts for the serving loop.
+
+    Curves are drawn as in sized_scene (lengths log-uniform in [lmin, lmax]),
+    with bbox centres uniform in [0, a]^2, a = serving_extent(n): a scene of
+    n curves covers n / per_unit_area unit squares, like a larger canvas,
+    instead of packing thousands of curves of length up to 0.5 into the unit
+    square (where they would cross each other some 10^5 times)."""
     out = []
     for k in range(n_scenes):
         rng = np.random.default_rng(seed0 + k)
         n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
-        out.append(sized_scene(n_curves=n, seed=seed0 + k, **kw))
+        a = serving_extent(n, per_unit_area)
+        rng = np.random.default_rng(seed0 + k)
+        shape = _sized_shape(lmin, lmax, lambda r, c, a=a: r.uniform(0.0, a, size=2))
+        ctrl, left, right = _draw_curves(rng, n, 3, shape)
+        out.append(Scene(ctrl=ctrl, left=left, right=right, extent=a, **kw))
     return out
+
+
+def serving_domain(sc):
+    """Quadtree root of a serving scene: its square extent with a margin of
+    one unit, so zoom-1 viewports centred on any curve point fit."""
+    a = sc.get("extent", 1.0)
+    return (-1.0, -1.0, a + 1.0, a + 1.0)
 
 
 def serving_requests(scenes, n, seed=7, sides=(256, 512, 1024, 2048), zoom=(1.0, 1e6)):
@@ -232,4 +257,4 @@ PRECISION = dict(seed=2, panels=32, gl=16, segs=80,
 BATCH = dict(n_curves=500, n_stops=2, seed=3, panels=4, gl=16, segs=80,
              n_viewports=64, domain=(-1.0, -1.0, 2.0, 2.0))
 SERVING = dict(n_scenes=16, seed0=100, panels=16, gl=16, segs=80,
-               domain=(-1.0, -1.0, 2.0, 2.0), n_requests=2000, n_warmup=100)
+               n_requests=2000, n_warmup=100)
