@@ -21,21 +21,7 @@ struct VpLevel {
     int off, poff;         // global index of the first box, and of the parent's
     int first_block;       // first block of this viewport in the level's launch
     int hl;                // rectangle height
-};
-
-// Work item of the fused render kernel: target box (ti, tj) at `level` of
-// viewport `vp`, with its parent's slot.
-struct QItem {
-    long long ti, tj;
-    int vp, level, parent, pad;
-};
-
-// Counters of the fused render kernel's work queue.
-struct QueueCtl {
-    int head;     // next slot to claim
-    int tail;     // next slot to fill
-    int pending;  // items filled but not finished
-    int error;    // set when a wait exceeded its bound
+    int level, pad;        // quadtree level of the rectangle
 };
 
 // One viewport's target leaves (pixel tiles) in a (batched) render.
@@ -89,8 +75,8 @@ struct PinnedStage {
 // Host plan of one render of n viewports: per (viewport, level) rectangles
 // of target boxes, launch sizes and the layout of the render's device
 // scratch, [level table | leaf table | edge table | level index | local
-// coefficients | near sets | expansion owners | work queue | ready flags |
-// queue counters].
+// coefficients | near sets | expansion owners | done flags | claim counter |
+// heavy-tile queue | kept traversal lists].
 struct RenderPlan {
     int n = 0, p = 0, tile_px = 0, maxL = 0;
     std::vector<VpLevel> lev;
@@ -101,7 +87,9 @@ struct RenderPlan {
     int leaf_blocks = 0;
     long long total_boxes = 0;
     size_t leaf_at = 0, edges_at = 0, vlev_at = 0, desc_bytes = 0, tl_at = 0, nset_at = 0;
-    size_t owner_at = 0, queue_at = 0, ready_at = 0, ctl_at = 0, scratch_bytes = 0;
+    size_t owner_at = 0, scratch_bytes = 0;
+    // per-box done flags and the claim counter of the persistent downward pass
+    size_t done_at = 0, dctl_at = 0;
     // queue of heavy small tiles (k_tile_scan, k_tile_big; 8-pixel tiles)
     size_t hv_ctl_at = 0, hv_list_at = 0, hv_flag_at = 0;
     // first-round traversal lists of light small tiles (k_tile_scan -> k_tile)

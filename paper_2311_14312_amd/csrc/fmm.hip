@@ -1225,6 +1225,9 @@ struct KeptLists {
 };
 constexpr int kOverlapTiles = 65536;  // renders with this many tiles overlap k_tile_big
 constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_down<.., 3>
+// Render downward pass: one persistent launch over every level (else one
+// k_down launch per level).
+constexpr bool kPersistentDown = false;
 
 template <typename T, int PX>
 struct TileTargets {
@@ -1728,169 +1731,94 @@ k_tile_big(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __re
     }
 }
 
-// ------------------------------------------------------ fused render kernel
-// Switched off: its first device run ended in an illegal memory access
-// whose cause is not found yet; renders use the per-level launches below.
-constexpr bool kFusedRender = false;
+// ------------------------------------------------ persistent downward pass
+// One launch runs the downward step of every target box of a batch, over
+// all levels and viewports: waves claim boxes from a counter in the plan's
+// level-major order, wait until the box's parent has been done, run the
+// step (down_body) and mark the box done.  Coarse levels, whose few boxes
+// each run a long chain of dependent loads, then overlap with the finer
+// levels instead of running one launch after another.  A box's parent has
+// a smaller index and was claimed before it by a wave that was already
+// running, so every wait ends; each wait is also bounded by the device's
+// wall clock (a wave that waits longer sets the stall flag and leaves).
+struct DownCtl {
+    int next;   // boxes claimed so far (after the roots)
+    int error;  // set when a wait ran out
+};
 
-// One persistent launch renders a whole batch: waves take target boxes from
-// a work queue in the order they become ready (a box is queued by its
-// parent once the parent's near set and local expansion are written), run
-// the downward pass on them and, at the tile level or when a box is quiet,
-// evaluate its pixels.  Levels and viewports overlap; quiet subtrees cost
-// one item.  Every wait is bounded (wait_ticks of the constant-rate wall
-// clock): a wave that waits longer sets the error flags and leaves, and the
-// others follow when their own waits run out.
-
-__device__ inline int ld_acquire(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Flags are polled with relaxed loads (coherent across XCDs, no cache
+// maintenance) and the acquire is one fence after the flag is seen: an
+// acquire load on this hardware invalidates the caches on every poll, and
+// thousands of polling waves would keep the working waves' data out of them.
+__device__ inline int ld_relaxed(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void st_release(int* p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-// Roots of every viewport as ready items in slots 0..n-1; every other slot
-// not ready; counters reset.
-__global__ void __launch_bounds__(256)
-k_fused_init(int n_vp, const VpLevel* __restrict__ lev, const int* __restrict__ vlev, int maxL,
-             int n_slots, int p, cpx<double>* __restrict__ L, int* __restrict__ nset,
-             int2* __restrict__ owner, QItem* __restrict__ q, int* __restrict__ ready,
-             QueueCtl* __restrict__ ctl) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_slots) ready[i] = i < n_vp ? 1 : 0;  // the roots are ready
-    if (i == 0) {
-        ctl->head = 0;
-        ctl->tail = n_vp;
-        ctl->pending = n_vp;
-        ctl->error = 0;
-    }
-    if (i < n_vp) {
-        const VpLevel& e = lev[vlev[(size_t)i * (maxL + 1)]];
-        q[i] = QItem{e.i0, e.j0, i, 0, -1, 0};
-        for (int t = 0; t < 9; ++t) nset[(size_t)i * 9 + t] = (t == 4) ? 0 : -1;
-        for (int t = 0; t < (p + 1) * 3; ++t) L[(size_t)i * (p + 1) * 3 + t] = {0, 0};
-        owner[i] = make_int2(i, 0);
-    }
-}
-
-// Out-of-line bodies for the fused kernel: separate register allocation for
-// the downward and the leaf phase (inlined together they spill heavily).
-template <typename T, bool Count>
-__device__ __noinline__ bool down_call(DownShared<T>& sh, const TreeView& tv,
-                                       const PieceView& pv, int l, long long ti, long long tj,
-                                       int own, int par, int p, const cpx<T>* M, cpx<T>* L,
-                                       int* nset, const cpx<T>* Ttab, int2* owner,
-                                       unsigned long long* stats, int lane) {
-    return down_body<T, Count>(sh, tv, pv, l, ti, tj, own, par, p, M, L, nset, Ttab, owner,
-                               stats, lane);
-}
-
-template <typename T, int NT, int PX, bool Count>
-__device__ __noinline__ void tile_call(TileShared<T, NT>& sh, const TreeView& tv,
-                                       const PieceView& pv, const LeafArgs& a, int p,
-                                       const cpx<double>* Ms, const cpx<double>* Lc,
-                                       const int* nset, const int2* owner, const VpLeaf& v, int l,
-                                       long long ti, long long tj, int own, int k_lo, int nx,
-                                       int r_lo, int ny, int tid) {
-    tile_body<T, NT, PX, 1, Count>(sh, tv, pv, a, p, Ms, Lc, nset, owner, v, l, ti, tj, own, k_lo,
-                                   nx, r_lo, ny, tid);
-}
-
-template <typename T>
-union FusedShared {
-    DownShared<double> d;
-    TileShared<T, kWave> t;
-};
+// Polls of one wait at most (with the back-off below, about a second).
+constexpr int kMaxPolls = 1 << 20;
 
 template <typename T, bool Count>
 __global__ void __launch_bounds__(kWave, 4)
-k_render_fused(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
-               const cpx<double>* __restrict__ Ms, const cpx<double>* __restrict__ Ttab,
-               cpx<double>* __restrict__ L, int* __restrict__ nset, int2* __restrict__ owner,
-               QItem* __restrict__ q, int* __restrict__ ready, QueueCtl* __restrict__ ctl,
-               int n_slots, const VpLevel* __restrict__ lev, const int* __restrict__ vlev,
-               int maxL, long long wait_ticks, int* __restrict__ stall) {
-    __shared__ FusedShared<T> sh;
-    __shared__ QItem s_item;
-    __shared__ int s_slot, s_t0;
+k_down_persist(TreeView tv, PieceView pv, int p, const cpx<double>* __restrict__ M,
+               cpx<double>* __restrict__ L, int* __restrict__ nset,
+               const cpx<double>* __restrict__ Ttab, int2* __restrict__ owner,
+               const VpLevel* __restrict__ lev, int n_ent, int first_box, int total,
+               int* __restrict__ done, DownCtl* __restrict__ ctl, long long wait_ticks,
+               int* __restrict__ stall, unsigned long long* stats) {
+    __shared__ DownShared<T, 1> sh;
+    __shared__ int s_b, s_ok;
     const int lane = threadIdx.x;
     for (;;) {
-        // claim the next slot and wait until it holds an item
+        if (lane == 0) s_b = first_box + atomicAdd(&ctl->next, 1);
+        __syncthreads();
+        const int b = s_b;
+        if (b >= total) return;
+        // the level-table entry holding box b (entries are sorted by off)
+        int lo = 0, hi = n_ent - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (lev[mid].off <= b) lo = mid; else hi = mid - 1;
+        }
+        const VpLevel& e = lev[lo];
+        const int rel = b - e.off;
+        const long long ti = e.i0 + rel % e.wl, tj = e.j0 + rel / e.wl;
+        const int par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
         if (lane == 0) {
-            const int h = atomicAdd(&ctl->head, 1);
-            int slot = -1;
-            if (h < n_slots) {
+            int ok = 1;
+            if (ld_relaxed(&done[par]) == 0) {
+                // bounded wait: by the wall clock and by the number of polls
                 const long long t0 = wall_clock64();
-                for (int spins = 0;; ++spins) {
-                    if (ld_acquire(&ready[h])) {
-                        slot = h;
+                int nap = 1;
+                for (int polls = 1; ld_relaxed(&done[par]) == 0; ++polls) {
+                    if (polls >= kMaxPolls ||
+                        ((polls & 15) == 0 && wall_clock64() - t0 > wait_ticks)) {
+                        atomicOr(&ctl->error, 1);
+                        __hip_atomic_store(stall, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        ok = 0;
                         break;
                     }
-                    if ((spins & 15) == 15) {
-                        if (ld_acquire(&ctl->pending) == 0) break;  // nothing can arrive
-                        if (wall_clock64() - t0 > wait_ticks) {
-                            atomicOr(&ctl->error, 1);
-                            __hip_atomic_store(stall, 1, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_SYSTEM);
-                            break;
-                        }
-                    }
-                    __builtin_amdgcn_s_sleep(2);
+                    // back-off: 1, 2, 4, 8 and then 8 x 64 clocks between polls
+                    if (nap == 1) __builtin_amdgcn_s_sleep(1);
+                    else if (nap == 2) __builtin_amdgcn_s_sleep(2);
+                    else if (nap == 3) __builtin_amdgcn_s_sleep(4);
+                    else __builtin_amdgcn_s_sleep(8);
+                    nap = nap < 4 ? nap + 1 : 4;
                 }
             }
-            s_slot = slot;
-            if (slot >= 0) s_item = q[slot];
+            // acquire: the parent's outputs are read after the flag
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
         }
         __syncthreads();
-        const int slot = s_slot;
-        if (slot < 0) return;
-        const QItem it = s_item;
-        const VpLeaf& v = a.vleaf[it.vp];
-        bool quiet = false;
-        if (it.level > 0) {
-            quiet = down_call<double, Count>(sh.d, tv, pv, it.level, it.ti, it.tj, slot, it.parent,
-                                             p, M, L, nset, Ttab, owner, a.stats, lane);
-        }
+        if (!s_ok) return;
+        (void)down_body<T, Count, 1>(sh, tv, pv, e.level, ti, tj, b, par, p, M, L, nset, Ttab,
+                                     owner, stats, lane);
+        // publish the box's near set, expansion and owner (written by every
+        // lane of this one-wave block) with a release store of its flag
         __syncthreads();
-        if (quiet || it.level == v.L) {
-            // leaf: the box's pixels, from the tile-level edge tables
-            const int s = v.L - it.level;
-            const long long wl = v.wl;
-            const int hl = v.hl;
-            const long long c0 = min(max((it.ti << s) - v.i0, 0LL), wl);
-            const long long c1 = min(max(((it.ti + 1) << s) - v.i0, 0LL), wl);
-            const long long r0 = min(max((it.tj << s) - v.j0, 0LL), (long long)hl);
-            const long long r1 = min(max(((it.tj + 1) << s) - v.j0, 0LL), (long long)hl);
-            const int k_lo = a.edges[v.col_at + c0];
-            const int nx = a.edges[v.col_at + c1] - k_lo;
-            const int r_lo = a.edges[v.row_at + r1];
-            const int ny = max(a.edges[v.row_at + r0] - r_lo, 0);
-            tile_call<T, kWave, 1, Count>(sh.t, tv, pv, a, p, Ms, L, nset, owner, v, it.level,
-                                          it.ti, it.tj, slot, k_lo, nx, r_lo, ny, lane);
-        } else {
-            // queue the children that lie in the next level's rectangle
-            const VpLevel& e = lev[vlev[(size_t)it.vp * (maxL + 1) + it.level + 1]];
-            const long long cxi = 2 * it.ti + (lane & 1), cyi = 2 * it.tj + (lane >> 1);
-            const bool in = lane < 4 && cxi >= e.i0 && cxi < e.i0 + e.wl && cyi >= e.j0 &&
-                            cyi < e.j0 + e.hl;
-            const unsigned long long m = __ballot(in);
-            const int nc = __popcll(m);
-            if (lane == 0) {
-                s_t0 = atomicAdd(&ctl->tail, nc);
-                atomicAdd(&ctl->pending, nc);
-            }
-            __syncthreads();
-            const int pos = s_t0 + __popcll(m & ((1ULL << lane) - 1ULL));
-            if (in && pos >= n_slots) atomicOr(&ctl->error, 2);  // cannot happen: one slot per box
-            if (in && pos < n_slots) {
-                q[pos] = QItem{cxi, cyi, it.vp, it.level + 1, slot, 0};
-                // publish after this box's outputs and the item itself
-                __threadfence();
-                st_release(&ready[pos], 1);
-            }
-        }
-        __syncthreads();
-        if (lane == 0) atomicSub(&ctl->pending, 1);
+        if (lane == 0) st_release(&done[b], 1);
     }
 }
 
@@ -2116,12 +2044,24 @@ int tile_level(double side, const dc_viewport& vp, int tile_px) {
     return Lt;
 }
 
+// Start of a render: the roots' near sets, expansions and owners (blocks
+// 0..n-1), the done flags of the persistent downward pass (the n roots done,
+// every other box not; all blocks, a flag per thread) and the counters.
 __global__ void k_init_roots(int n, const VpLevel* __restrict__ roots, int p,
                              cpx<double>* __restrict__ L, int* __restrict__ nset,
-                             int2* __restrict__ owner, int* __restrict__ hv_ctl) {
+                             int2* __restrict__ owner, int* __restrict__ hv_ctl,
+                             int* __restrict__ done, int total, DownCtl* __restrict__ dctl) {
     const int v = blockIdx.x;
     // the counters of the heavy-tile queue (if any), cleared for this render
     if (v == 0 && hv_ctl != nullptr && threadIdx.x < 3) hv_ctl[threadIdx.x] = 0;
+    if (v == 0 && dctl != nullptr && threadIdx.x == 0) {
+        dctl->next = 0;
+        dctl->error = 0;
+    }
+    if (done != nullptr) {
+        const int i = v * blockDim.x + threadIdx.x;
+        if (i < total) done[i] = i < n ? 1 : 0;
+    }
     if (v >= n) return;
     const int own = roots[v].off;
     const int t = threadIdx.x;
@@ -2142,65 +2082,21 @@ long long wall_ticks_per_second() {
     return t;
 }
 
-// Waves of the fused render kernel that fit on the device at once (its grid).
-template <typename T>
-int fused_capacity(bool count) {
-    static int cap[2] = {0, 0};
-    int& c = cap[count ? 1 : 0];
+// Blocks of the persistent downward kernel that fit on the device at once
+// (its grid: more would only wait to start until the claims run out).
+template <typename T, bool Count>
+int down_persist_capacity() {
+    static int c = 0;
     if (c == 0) {
         int dev = 0, per_cu = 0;
         DC_HIP(hipGetDevice(&dev));
         hipDeviceProp_t prop;
         DC_HIP(hipGetDeviceProperties(&prop, dev));
-        if (count)
-            DC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_render_fused<T, true>), kWave, 0));
-        else
-            DC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_render_fused<T, false>), kWave, 0));
+        DC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(k_down_persist<T, Count>), kWave, 0));
         c = std::max(1, per_cu) * prop.multiProcessorCount;
     }
     return c;
-}
-
-// Fused launch of a planned render (k_fused_init + k_render_fused).
-template <typename T>
-void launch_fused(FmmState& f, const RenderPlan& pl, const dc_eval_opts& o, int out_dtype,
-                  char* scratch, bool timed, unsigned long long* stats, const TreeView& tv,
-                  const PieceView& pv, int p, const cpx<double>* M, const cpx<double>* Ms,
-                  const cpx<double>* Ttab, cpx<double>* TL, int* nset, int2* owner,
-                  const VpLevel* d_lev, const VpLeaf* d_leaf, hipStream_t st) {
-    // one persistent launch for the whole batch (levels and tiles)
-    const int n_slots = (int)pl.total_boxes;
-    QItem* q = reinterpret_cast<QItem*>(scratch + pl.queue_at);
-    int* ready = reinterpret_cast<int*>(scratch + pl.ready_at);
-    QueueCtl* ctl = reinterpret_cast<QueueCtl*>(scratch + pl.ctl_at);
-    const int* vlev = reinterpret_cast<const int*>(scratch + pl.vlev_at);
-    hipLaunchKernelGGL(k_fused_init, dim3((n_slots + 255) / 256), dim3(256), 0, st, pl.n,
-                       d_lev, vlev, pl.maxL, n_slots, p, TL, nset, owner, q, ready, ctl);
-    DC_HIP(hipGetLastError());
-    LeafArgs a{};
-    a.out_f64 = out_dtype == DC_OUT_F64;
-    a.near2 = o.near_fp64 * o.near_fp64;
-    a.stats = stats;
-    a.vleaf = d_leaf;
-    a.nvleaf = pl.n;
-    a.edges = reinterpret_cast<const int*>(scratch + pl.edges_at);
-    if (timed) DC_HIP(hipEventRecord(f.ev[2], st));
-    const int grid = std::min(n_slots, fused_capacity<T>(stats != nullptr));
-    // a wave waits for its item at most ~2 s (a whole render takes far less)
-    const long long wait = 2 * wall_ticks_per_second();
-    if (stats)
-        hipLaunchKernelGGL((k_render_fused<T, true>), dim3(grid), dim3(kWave),
-                           tile_coef_bytes(kWave, p), st, tv, pv,
-                           a, p, M, Ms, Ttab, TL, nset, owner, q, ready, ctl, n_slots, d_lev,
-                           vlev, pl.maxL, wait, f.stall_dev);
-    else
-        hipLaunchKernelGGL((k_render_fused<T, false>), dim3(grid), dim3(kWave),
-                           tile_coef_bytes(kWave, p), st, tv, pv,
-                           a, p, M, Ms, Ttab, TL, nset, owner, q, ready, ctl, n_slots, d_lev,
-                           vlev, pl.maxL, wait, f.stall_dev);
-    DC_HIP(hipGetLastError());
 }
 
 // Launch of a planned render (plan_render) with its scratch at `scratch`
@@ -2237,20 +2133,35 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     const cpx<double>* Ms = as_cpx(f.Ms64);
     const cpx<double>* Ttab = m2l_table_dev(f, p);
     if (timed) DC_HIP(hipEventRecord(f.ev[1], st));
-    bool fused = false;
-    if constexpr (kFusedRender) fused = o.tile_px <= 8;
-    if (fused) {
-        if constexpr (kFusedRender)
-            launch_fused<T>(f, pl, o, out_dtype, scratch, timed, stats, tv, pv, p, M, Ms, Ttab,
-                            TL, nset, owner, d_lev, d_leaf, st);
-    } else {
+    {
         const int nroots = pl.lev_begin[1] - pl.lev_begin[0];
         int* hv_ctl = o.tile_px <= 8 && pl.hv_flag_at > 0
                           ? reinterpret_cast<int*>(scratch + pl.hv_ctl_at) : nullptr;
-        hipLaunchKernelGGL(k_init_roots, dim3(nroots), dim3(kWave), 0, st, nroots, d_lev, p, TL,
-                           nset, owner, hv_ctl);
+        const int total = (int)pl.total_boxes;
+        int* done = reinterpret_cast<int*>(scratch + pl.done_at);
+        DownCtl* dctl = reinterpret_cast<DownCtl*>(scratch + pl.dctl_at);
+        const int init_blocks = std::max(nroots, (total + kWave - 1) / kWave);
+        hipLaunchKernelGGL(k_init_roots, dim3(init_blocks), dim3(kWave), 0, st, nroots, d_lev, p,
+                           TL, nset, owner, hv_ctl, kPersistentDown ? done : nullptr, total,
+                           kPersistentDown ? dctl : nullptr);
         DC_HIP(hipGetLastError());
-        for (int l = 1; l <= pl.maxL; ++l) {
+        if (kPersistentDown && total > nroots) {
+            const int n_ent = pl.lev_begin[pl.maxL + 1];
+            const long long wait = 2 * wall_ticks_per_second();
+            if (stats) {
+                const int grid = std::min(total - nroots, down_persist_capacity<T, true>());
+                hipLaunchKernelGGL((k_down_persist<T, true>), dim3(grid), dim3(kWave), 0, st, tv,
+                                   pv, p, M, TL, nset, Ttab, owner, d_lev, n_ent, nroots, total,
+                                   done, dctl, wait, f.stall_dev, stats);
+            } else {
+                const int grid = std::min(total - nroots, down_persist_capacity<T, false>());
+                hipLaunchKernelGGL((k_down_persist<T, false>), dim3(grid), dim3(kWave), 0, st, tv,
+                                   pv, p, M, TL, nset, Ttab, owner, d_lev, n_ent, nroots, total,
+                                   done, dctl, wait, f.stall_dev, stats);
+            }
+            DC_HIP(hipGetLastError());
+        }
+        for (int l = 1; !kPersistentDown && l <= pl.maxL; ++l) {
             DownLevel dl{};
             dl.stats = stats;
             dl.solve = 0;
@@ -2555,6 +2466,7 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
             }
             e.first_block = (int)fb;
             e.hl = (int)(rj1[v][l] - rj0[v][l] + 1);
+            e.level = l;
             fb += cnt;
             total += cnt;
             pl.vlev[(size_t)v * (maxL + 1) + l] = (int)pl.lev.size();
@@ -2627,13 +2539,11 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.tl_at = up256(pl.desc_bytes);
     pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
     pl.owner_at = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
-    const size_t nq = kFusedRender ? (size_t)total : 0;  // work queue of the fused kernel
-    pl.queue_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
-    pl.ready_at = up256(pl.queue_at + nq * sizeof(QItem));
-    pl.ctl_at = up256(pl.ready_at + nq * sizeof(int));
+    pl.done_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
+    pl.dctl_at = up256(pl.done_at + (size_t)total * sizeof(int));
     // queue of heavy tiles (it can hold every tile)
     const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;
-    pl.hv_ctl_at = up256(pl.ctl_at + sizeof(QueueCtl));
+    pl.hv_ctl_at = up256(pl.dctl_at + 64);
     pl.hv_list_at = up256(pl.hv_ctl_at + 3 * sizeof(int));
     pl.hv_flag_at = up256(pl.hv_list_at + nl * sizeof(int));
     pl.lists_at = up256(pl.hv_flag_at + nl);
