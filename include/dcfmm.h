@@ -161,6 +161,22 @@ int dc_set_boundary(dc_scene s, const double* u_plus_host,
 int dc_solve_densities(dc_scene s, const dc_solve_opts* o,
                        dc_solve_report* rep, void* stream);
 
+/* Sec. 5.4 (mixed conditions, Eq. neumann_mat): one-sided Dirichlet and
+ * Neumann data on closed curves, for the domain the curves enclose on their
+ * left (counter-clockwise loops: the left normal points into it).  At every
+ * node 1/2 u = G_H psi + F_H u, with psi the normal derivative of u along
+ * the outward normal (right normal).  neumann (host [N], 0 or 1) marks the
+ * Neumann nodes; values (host [3][N]) holds u* at Dirichlet nodes and psi*
+ * at Neumann nodes.  GMRES (Sec. 6.5.1; o->precond must be
+ * DC_PRECOND_NONE) solves for psi on the Dirichlet nodes and u on the
+ * Neumann nodes; the scene then holds sigma = psi and mu = u, so dc_render
+ * evaluates u(x) = int G psi + F u inside (the scene's two-sided colour data
+ * come back with the next dc_solve_densities, dc_set_densities or
+ * dc_set_boundary).  Every curve of the scene must belong to such a loop.
+ * Synchronous; errors as dc_solve_densities. */
+int dc_solve_mixed(dc_scene s, const int* neumann, const double* values,
+                   const dc_solve_opts* o, dc_solve_report* rep, void* stream);
+
 /* Densities sigma at the nodes, host [3][N].  Synchronous. */
 int dc_get_densities(dc_scene s, double* sigma_host);
 
@@ -223,6 +239,29 @@ int dc_render_noalloc(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o,
 int dc_render_batch(dc_scene s, const dc_viewport* vps, int n,
                     const dc_eval_opts* o, int out_dtype, void* const* outs_dev,
                     void* stream);
+
+/* Sec. 8 (anti-aliasing): the render of dc_render in which every pixel whose
+ * closed square meets a chord segment of the scene takes the mean of the
+ * representation at the centres of its aa x aa equal sub-squares (an
+ * area-weighted sum over one level of sub-cells, the paper's recursive
+ * area weighting near curves); every other pixel keeps its centre value.
+ * Pixel (r, k) covers [x0 + k pw, x0 + (k+1) pw] x [y1 - (r+1) ph, y1 - r ph]
+ * with x0 = cx - width/2, y1 = cy + height/2, pw = width/W, ph = height/H;
+ * its sub-square (i, j) is centred at (x0 + (k + (i + 1/2)/aa) pw,
+ * y1 - (r + (j + 1/2)/aa) ph).  The sub-square samples are rendered by the
+ * FMM with o (method FMM) as small viewports in one batched render, so
+ * unlike the paper's scheme the image size need not be a power of two.
+ * aa in 2..16.  rep (may be NULL) receives the number of anti-aliased
+ * pixels, of pixel blocks rendered at aa x aa samples and of samples.
+ * Synchronous (returns after out_dev is written); other arguments, errors
+ * and ownership as in dc_render. */
+typedef struct {
+    long long aa_pixels;   /* pixels replaced by sub-square means */
+    int blocks;            /* batched sub-viewports (blocks of edge pixels) */
+    long long samples;     /* sub-square samples rendered */
+} dc_aa_report;
+int dc_render_aa(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o, int aa,
+                 int out_dtype, void* out_dev, dc_aa_report* rep, void* stream);
 
 /* Render options chosen on the device against an accuracy target.  For each
  * tile size in tiles[0..n_tiles), orders p = p_min, p_min + p_step, ... up to

@@ -43,8 +43,10 @@ __all__ = [
     "bezier_point", "bezier_tangent", "curve_length", "arclength_to_param",
     "gauss_legendre", "interp_matrix", "Discretization", "discretize",
     "colour_at", "boundary_values", "chord_integrals", "self_segment_G",
-    "node_operator_rows", "assemble", "solve", "solve_stops",
+    "node_operator_rows", "assemble", "solve", "solve_stops", "hybrid_matrices",
+    "solve_mixed",
     "pixel_centres", "evaluate", "render", "TWO_PI",
+    "pixel_box", "segments_meet_box", "aa_edge_mask", "render_aa",
 ]
 
 
@@ -398,6 +400,50 @@ def solve(disc, u_plus, u_minus, workers=1, report=None):
     return sigma.T.copy(), mu
 
 
+def hybrid_matrices(disc):
+    """G_H = Ghat Pbar Pring^-1 and F_H = Fhat Pbar Pring^-1 (N x N each, the
+    self-segment rule of App. C.1, D.3, D.4 included), panel by panel."""
+    N, g, s = disc.N, disc.gl, disc.segs
+    GH = np.empty((N, N))
+    FH = np.empty((N, N))
+    for p in range(N // g):
+        cols = np.arange(p * s, (p + 1) * s)
+        G, F = node_operator_rows(disc, np.arange(N), cols)
+        GH[:, p * g:(p + 1) * g] = G @ disc.Pi
+        FH[:, p * g:(p + 1) * g] = F @ disc.Pi
+    return GH, FH
+
+
+def solve_mixed(disc, neumann, values):
+    """Mixed Dirichlet/Neumann conditions on closed curves (Sec. 5.4,
+    Eq. neumann_mat), for the domain the curves enclose on their left (the
+    left normal points into it, so F u is the double layer of Green's third
+    identity).  At every node i, 1/2 u_i = (G_H psi)_i + (F_H u)_i, with
+    psi the outward normal derivative.  neumann [N] bool marks the Neumann
+    nodes; values [3, N] holds u* at Dirichlet nodes and psi* at Neumann
+    nodes.  The unknowns psi_d (Dirichlet nodes) and u_n (Neumann nodes)
+    solve
+        G_H[:, d] psi_d + F_H[:, n] u_n - 1/2 u_n (rows n)
+            = 1/2 u*_d (rows d) - G_H[:, n] psi*_n - F_H[:, d] u*_d
+    by dense LU.  Returns psi [3, N] and u [3, N] (known and solved parts);
+    the interior field is evaluate(disc, psi, u, points)."""
+    neumann = np.asarray(neumann, bool)
+    dirichlet = ~neumann
+    values = np.asarray(values, float)
+    GH, FH = hybrid_matrices(disc)
+    A = np.where(dirichlet[None, :], GH, FH)
+    idx = np.nonzero(neumann)[0]
+    A[idx, idx] -= 0.5
+    known_psi = np.where(neumann[None, :], values, 0.0)
+    known_u = np.where(dirichlet[None, :], values, 0.0)
+    rhs = 0.5 * known_u - known_psi @ GH.T - known_u @ FH.T      # [3, N]
+    lu, piv = scipy.linalg.lu_factor(A)
+    x = scipy.linalg.lu_solve((lu, piv), rhs.T).T
+    psi = np.where(dirichlet[None, :], x, values)
+    u = np.where(neumann[None, :], x, values)
+    return psi, u
+
+
 def solve_stops(disc, left, right, workers=1, report=None):
     """Solve with colours given as stops along each curve (Sec. 5.3)."""
     up, um = boundary_values(disc, left, right)
@@ -422,7 +468,8 @@ _EVAL_STATE = {}
 def _eval_block(args):
     lo, hi = args
     st = _EVAL_STATE
-    return _evaluate_serial(st["pts"][lo:hi], st["p1"], st["p2"], st["ws"], st["wm"])
+    return _evaluate_serial(st["pts"][lo:hi], st["p1"], st["p2"], st["ws"], st["wm"],
+                            pt_chunk=st["pt_chunk"])
 
 
 def _evaluate_serial(pts, p1, p2, wsig, wmu, seg_chunk=8192, pt_chunk=64):
@@ -439,21 +486,24 @@ def _evaluate_serial(pts, p1, p2, wsig, wmu, seg_chunk=8192, pt_chunk=64):
     return out
 
 
-def evaluate(disc, sigma, mu, pts, workers=1):
+def evaluate(disc, sigma, mu, pts, workers=1, pt_chunk=64):
     """u_c(x) = sum_j kappa_j [int_j G sigma_bar_cj + int_j F mu_bar_cj] at the
-    points pts [n, 2]; returns [n, 3]."""
+    points pts [n, 2]; returns [n, 3].  pt_chunk points share one sweep over
+    the segments (the sums run over the segments in the same order for any
+    pt_chunk; larger chunks read the segments fewer times)."""
     pts = np.asarray(pts, dtype=float)
     wsig = (disc.interpolate(sigma) * disc.seg_kappa).T.copy()   # [S, 3]
     wmu = (disc.interpolate(mu) * disc.seg_kappa).T.copy()
     if workers > 1 and pts.shape[0] > 256:
-        _EVAL_STATE.update(pts=pts, p1=disc.seg_p1, p2=disc.seg_p2, ws=wsig, wm=wmu)
+        _EVAL_STATE.update(pts=pts, p1=disc.seg_p1, p2=disc.seg_p2, ws=wsig, wm=wmu,
+                           pt_chunk=pt_chunk)
         bounds = np.linspace(0, pts.shape[0], 4 * workers + 1).astype(int)
         jobs = [(bounds[i], bounds[i + 1]) for i in range(len(bounds) - 1)]
         with _pool(workers) as pool:
             parts = pool.map(_eval_block, jobs)
         _EVAL_STATE.clear()
         return np.concatenate(parts)
-    return _evaluate_serial(pts, disc.seg_p1, disc.seg_p2, wsig, wmu)
+    return _evaluate_serial(pts, disc.seg_p1, disc.seg_p2, wsig, wmu, pt_chunk=pt_chunk)
 
 
 def render(disc, sigma, mu, viewport, rows=None, cols=None, workers=1):
@@ -465,6 +515,83 @@ def render(disc, sigma, mu, viewport, rows=None, cols=None, workers=1):
     pts = np.stack([X.ravel(), Y.ravel()], axis=1)
     return evaluate(disc, sigma, mu, pts, workers=workers).reshape(
         len(rows), len(cols), 3)
+
+
+# --------------------------------------------------------------------------
+# Anti-aliasing (Sec. 8): area-weighted pixel values where curves cross
+# --------------------------------------------------------------------------
+def pixel_box(viewport, r, k):
+    """Closed square of pixel (row r, column k): [xa, xb] x [ya, yb] with
+    xa = x0 + k pw, xb = x0 + (k+1) pw, ya = y1 - (r+1) ph, yb = y1 - r ph,
+    x0 = cx - w/2, y1 = cy + h/2, pw = w/W, ph = h/H."""
+    cx, cy, w, h, W, H = viewport
+    x0, y1 = cx - 0.5 * w, cy + 0.5 * h
+    pw, ph = w / W, h / H
+    return x0 + k * pw, x0 + (k + 1) * pw, y1 - (r + 1) * ph, y1 - r * ph
+
+
+def segments_meet_box(p1, p2, xa, xb, ya, yb):
+    """For every chord p1 -> p2 (closed segment): does it meet the closed box
+    [xa, xb] x [ya, yb]?  Clips the parameter t in [0, 1] by the four half
+    planes (Liang-Barsky); the box is met when the interval stays nonempty."""
+    dx = p2[:, 0] - p1[:, 0]
+    dy = p2[:, 1] - p1[:, 1]
+    t0 = np.zeros(len(p1))
+    t1 = np.ones(len(p1))
+    ok = np.ones(len(p1), bool)
+    for p, q in ((-dx, p1[:, 0] - xa), (dx, xb - p1[:, 0]),
+                 (-dy, p1[:, 1] - ya), (dy, yb - p1[:, 1])):
+        zero = p == 0.0
+        ok &= ~(zero & (q < 0.0))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = q / np.where(zero, 1.0, p)
+        t0 = np.where(~zero & (p < 0.0), np.maximum(t0, r), t0)
+        t1 = np.where(~zero & (p > 0.0), np.minimum(t1, r), t1)
+        ok &= t0 <= t1
+    return ok
+
+
+def aa_edge_mask(disc, viewport):
+    """[H, W] bool: pixels whose closed square meets a chord segment."""
+    W, H = viewport[4], viewport[5]
+    mask = np.zeros((H, W), bool)
+    for r in range(H):
+        for k in range(W):
+            mask[r, k] = segments_meet_box(disc.seg_p1, disc.seg_p2,
+                                           *pixel_box(viewport, r, k)).any()
+    return mask
+
+
+def render_aa(disc, sigma, mu, viewport, aa, rows, cols, workers=1):
+    """Anti-aliased pixel values (Sec. 8) at pixels (rows[i], cols[i]): a pixel
+    whose square meets a chord takes the mean of u at the centres of its
+    aa x aa equal sub-squares (area weighting over one level of sub-cells),
+    (x0 + (k + (i+1/2)/aa) pw, y1 - (r + (j+1/2)/aa) ph); any other pixel
+    its centre value.  Returns [n, 3] and the edge flags [n]."""
+    cx, cy, w, h, W, H = viewport
+    x0, y1 = cx - 0.5 * w, cy + 0.5 * h
+    pw, ph = w / W, h / H
+    xs, ys = pixel_centres(viewport)
+    rows, cols = np.asarray(rows), np.asarray(cols)
+    edge = np.array([segments_meet_box(disc.seg_p1, disc.seg_p2,
+                                       *pixel_box(viewport, r, k)).any()
+                     for r, k in zip(rows, cols)], bool)
+    frac = (np.arange(aa) + 0.5) / aa
+    pts = []
+    for r, k, e in zip(rows, cols, edge):
+        if e:
+            sx = x0 + (k + frac[None, :]) * pw + 0.0 * frac[:, None]
+            sy = y1 - (r + frac[:, None]) * ph + 0.0 * frac[None, :]
+            pts.append(np.stack([sx.ravel(), sy.ravel()], axis=1))
+        else:
+            pts.append(np.array([[xs[k], ys[r]]]))
+    vals = evaluate(disc, sigma, mu, np.concatenate(pts), workers=workers)
+    out = np.empty((len(rows), 3))
+    at = 0
+    for i, p in enumerate(pts):
+        out[i] = vals[at:at + len(p)].mean(axis=0)
+        at += len(p)
+    return out, edge
 
 
 def default_workers():

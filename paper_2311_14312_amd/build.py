@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdcfmm.so")
-SOURCES = ["geometry.cpp", "tree.cpp", "api.cpp", "server.cpp", "autotune.cpp",
+SOURCES = ["geometry.cpp", "tree.cpp", "api.cpp", "server.cpp", "autotune.cpp", "aa.cpp",
            "kernels_direct.hip", "fmm.hip", "precond.hip"]
 ARCH = os.environ.get("DCFMM_ARCH", "gfx950")
 

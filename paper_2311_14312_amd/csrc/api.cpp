@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "aa.h"
 #include "autotune.h"
 #include "scene.h"
 
@@ -49,6 +50,7 @@ void upload_boundary(dc_scene s) {
     std::vector<double> mu(3 * (size_t)N);
     for (size_t i = 0; i < mu.size(); ++i) mu[i] = s->uplus[i] - s->uminus[i];
     s->d_mu.upload(mu);
+    s->mu_from_mixed = false;
     s->solved = false;
     s->seg_w_valid = false;
     if (s->fmm) fmm_invalidate(*s->fmm);
@@ -99,9 +101,21 @@ void ensure_block_inverse(dc_scene s, hipStream_t st) {
     s->dinv_valid = true;
 }
 
+// Mixed Dirichlet/Neumann data of dc_solve_mixed (device): flag [N] = 1 on
+// Neumann nodes; values [3][N] = u* on Dirichlet nodes, psi* on Neumann ones.
+struct MixedBC {
+    const int* neumann;
+    const double* values;
+};
+
 // Alg. 3 with GMRES (Sec. 6.5.1): three channels share every matvec; with
-// right preconditioning the Krylov space is built for A M^-1.
-int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStream_t st) {
+// right preconditioning the Krylov space is built for A M^-1.  With mixed
+// conditions (Eq. neumann_mat) the unknown x holds psi on Dirichlet nodes
+// and u on Neumann nodes, A x = G_H x_d + F_H x_n - x_n / 2 and
+// b = u*_d / 2 - G_H psi*_n - F_H u*_d (d, n: the parts on Dirichlet and
+// Neumann nodes, zero elsewhere); no preconditioner.
+int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStream_t st,
+                const MixedBC* mixed = nullptr) {
     const int N = s->geo.N;
     const size_t n3 = 3 * (size_t)N;
     const int m = std::max(1, std::min(o.max_iter, N));
@@ -116,20 +130,42 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     dev_small.alloc(3 * (size_t)kcap + 8);
     double* h1 = dev_h.p;
     double* h2 = dev_h.p + 3 * kcap;
-    const bool pre = o.precond == DC_PRECOND_BLOCK;
+    const bool pre = o.precond == DC_PRECOND_BLOCK && mixed == nullptr;
     DevBuf<double> z;
     if (pre) {
         ensure_block_inverse(s, st);
         z.alloc(n3);
     }
+    DevBuf<double> part_d, part_n;
+    if (mixed) {
+        part_d.alloc(n3);
+        part_n.alloc(n3);
+    }
+    // y = A v
+    auto apply_A = [&](const double* v, double* y) {
+        if (!mixed) {
+            apply_operator(s, v, nullptr, y, o.matvec, st);
+            return;
+        }
+        launch_mask_split(N, mixed->neumann, v, part_d.p, part_n.p, st);
+        apply_operator(s, part_d.p, part_n.p, y, o.matvec, st);
+        launch_axpby((int)n3, 1.0, y, -0.5, part_n.p, y, st);
+    };
 
-    // b = (u+ + u-)/2 - F_H mu
-    apply_operator(s, nullptr, s->d_mu.p, tmp.p, o.matvec, st);
-    launch_axpby((int)n3, 0.5, s->d_uplus.p, 0.5, s->d_uminus.p, b.p, st);
-    launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, b.p, st);
+    if (!mixed) {
+        // b = (u+ + u-)/2 - F_H mu
+        apply_operator(s, nullptr, s->d_mu.p, tmp.p, o.matvec, st);
+        launch_axpby((int)n3, 0.5, s->d_uplus.p, 0.5, s->d_uminus.p, b.p, st);
+        launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, b.p, st);
+    } else {
+        // known u on Dirichlet nodes (part_d), known psi on Neumann nodes (part_n)
+        launch_mask_split(N, mixed->neumann, mixed->values, part_d.p, part_n.p, st);
+        apply_operator(s, part_n.p, part_d.p, tmp.p, o.matvec, st);
+        launch_axpby((int)n3, 0.5, part_d.p, -1.0, tmp.p, b.p, st);
+    }
     // x0 = 1, r0 = b - A x0
     launch_fill((int)n3, 1.0, x.p, st);
-    apply_operator(s, x.p, nullptr, tmp.p, o.matvec, st);
+    apply_A(x.p, tmp.p);
     launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, w.p, st);
 
     std::vector<double> host(6 * (size_t)kcap + 8);
@@ -165,9 +201,9 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         double* vk = V.p + (size_t)k * n3;
         if (pre) {
             launch_block_apply(N, s->geo.P * s->geo.g, s->dinv.p, vk, z.p, st);
-            apply_operator(s, z.p, nullptr, w.p, o.matvec, st);
+            apply_A(z.p, w.p);
         } else {
-            apply_operator(s, vk, nullptr, w.p, o.matvec, st);
+            apply_A(vk, w.p);
         }
         // classical Gram-Schmidt, twice (CGS2), against V[0..k]
         launch_block_dots(V.p, k + 1, w.p, N, h1, st);
@@ -236,7 +272,7 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         DC_HIP(hipStreamSynchronize(st));
     }
     // True residual.
-    apply_operator(s, x.p, nullptr, tmp.p, o.matvec, st);
+    apply_A(x.p, tmp.p);
     launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, w.p, st);
     double rn[3];
     norms(w.p, rn);
@@ -246,7 +282,15 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         if (rep.rel_residual[c] > o.tol) rep.converged = 0;
     }
     s->d_sigma.alloc(n3);
-    DC_HIP(hipMemcpyAsync(s->d_sigma.p, x.p, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (!mixed) {
+        DC_HIP(hipMemcpyAsync(s->d_sigma.p, x.p, n3 * sizeof(double), hipMemcpyDeviceToDevice,
+                              st));
+    } else {
+        // psi = x on Dirichlet nodes, psi* on Neumann nodes; u = u* on
+        // Dirichlet nodes, x on Neumann nodes (the double-layer density)
+        s->d_mu.alloc(n3);
+        launch_mask_merge(N, mixed->neumann, x.p, mixed->values, s->d_sigma.p, s->d_mu.p, st);
+    }
     DC_HIP(hipStreamSynchronize(st));
     s->solved = true;
     s->seg_w_valid = false;
@@ -378,8 +422,38 @@ int dc_solve_densities(dc_scene s, const dc_solve_opts* o, dc_solve_report* rep,
         DC_REQUIRE(o->precond == DC_PRECOND_NONE || o->precond == DC_PRECOND_BLOCK,
                    "bad preconditioner");
         std::memset(rep, 0, sizeof(*rep));
+        if (s->mu_from_mixed) upload_boundary(s);  // two-sided data again
         const auto t0 = std::chrono::steady_clock::now();
         rc = gmres_solve(s, *o, *rep, as_stream(stream));
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc != DC_OK) g_last_error = "GMRES did not reach the tolerance";
+    });
+    return g != DC_OK ? g : rc;
+}
+
+int dc_solve_mixed(dc_scene s, const int* neumann, const double* values,
+                   const dc_solve_opts* o, dc_solve_report* rep, void* stream) {
+    int rc = DC_OK;
+    int g = guarded([&] {
+        DC_REQUIRE(s && neumann && values && o && rep, "null argument");
+        check_not_served(s);
+        check_eval(&o->matvec);
+        DC_REQUIRE(o->tol > 0 && o->max_iter >= 1, "bad GMRES options");
+        DC_REQUIRE(o->precond == DC_PRECOND_NONE, "mixed conditions take no preconditioner");
+        const int N = s->geo.N;
+        std::vector<int> flag(neumann, neumann + N);
+        for (int v : flag) DC_REQUIRE(v == 0 || v == 1, "neumann flags must be 0 or 1");
+        std::vector<double> vals(values, values + 3 * (size_t)N);
+        for (double v : vals) DC_REQUIRE(std::isfinite(v), "non-finite boundary value");
+        std::memset(rep, 0, sizeof(*rep));
+        DevBuf<int> d_flag;
+        DevBuf<double> d_vals;
+        d_flag.upload(flag);
+        d_vals.upload(vals);
+        const MixedBC mixed{d_flag.p, d_vals.p};
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = gmres_solve(s, *o, *rep, as_stream(stream), &mixed);
+        s->mu_from_mixed = true;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (rc != DC_OK) g_last_error = "GMRES did not reach the tolerance";
     });
@@ -401,6 +475,7 @@ int dc_set_densities(dc_scene s, const double* sigma) {
         check_not_served(s);
         const size_t n3 = 3 * (size_t)s->geo.N;
         for (size_t i = 0; i < n3; ++i) DC_REQUIRE(std::isfinite(sigma[i]), "non-finite density");
+        if (s->mu_from_mixed) upload_boundary(s);  // two-sided data again
         std::vector<double> v(sigma, sigma + n3);
         s->d_sigma.upload(v);
         s->solved = true;
@@ -477,6 +552,24 @@ int dc_render_batch(dc_scene s, const dc_viewport* vps, int n, const dc_eval_opt
         }
         DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
         fmm_render_batch(*s, vps, n, *o, out_dtype, outs, as_stream(stream));
+    });
+}
+
+int dc_render_aa(dc_scene s, const dc_viewport* vp, const dc_eval_opts* o, int aa,
+                 int out_dtype, void* out, dc_aa_report* rep, void* stream) {
+    return guarded([&] {
+        DC_REQUIRE(s && vp && out, "null argument");
+        check_eval(o);
+        check_served_opts(s, o);
+        DC_REQUIRE(o->method == DC_METHOD_FMM, "dc_render_aa is an FMM path");
+        DC_REQUIRE(aa >= 2 && aa <= 16, "aa must be in 2..16");
+        DC_REQUIRE(s->solved, "render needs densities (solve or set them first)");
+        DC_REQUIRE(vp->W >= 1 && vp->H >= 1 && vp->width > 0 && vp->height > 0 &&
+                       std::isfinite(vp->cx) && std::isfinite(vp->cy) &&
+                       std::isfinite(vp->width) && std::isfinite(vp->height),
+                   "bad viewport");
+        DC_REQUIRE(out_dtype == DC_OUT_F32 || out_dtype == DC_OUT_F64, "bad out_dtype");
+        render_aa(*s, *vp, *o, aa, out_dtype, out, rep, as_stream(stream));
     });
 }
 

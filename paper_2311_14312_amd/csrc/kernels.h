@@ -59,6 +59,12 @@ void launch_combine(const double* V, int k, const double* y, int kcap, double* x
 void launch_axpby(int n, double a, const double* x, double b, const double* y, double* out,
                   hipStream_t st);
 void launch_fill(int n, double v, double* out, hipStream_t st);
+// [3][N] vectors and a per-node flag [N]: a = v off the flagged nodes, b = v
+// on them (zero elsewhere); out0 = flagged ? y : x, out1 = flagged ? x : y.
+void launch_mask_split(int N, const int* flag, const double* v, double* a, double* b,
+                       hipStream_t st);
+void launch_mask_merge(int N, const int* flag, const double* x, const double* y, double* out0,
+                       double* out1, hipStream_t st);
 
 // ------------------------------------------------- block-Jacobi preconditioner
 // D[c] = diagonal block of curve c (n = P g rows), row-major.

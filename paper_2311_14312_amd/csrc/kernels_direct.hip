@@ -214,6 +214,29 @@ __global__ void __launch_bounds__(kNT) k_fill(int n, double v, double* __restric
     if (i < n) out[i] = v;
 }
 
+// v [3][N] split by a per-node flag: a = v where flag == 0, b = v where
+// flag != 0 (zero elsewhere).
+__global__ void __launch_bounds__(kNT)
+k_mask_split(int N, const int* __restrict__ flag, const double* __restrict__ v,
+             double* __restrict__ a, double* __restrict__ b) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= 3 * N) return;
+    const bool f = flag[i % N] != 0;
+    a[i] = f ? 0.0 : v[i];
+    b[i] = f ? v[i] : 0.0;
+}
+
+// out0 = x where flag == 0 else y;  out1 = y where flag == 0 else x.
+__global__ void __launch_bounds__(kNT)
+k_mask_merge(int N, const int* __restrict__ flag, const double* __restrict__ x,
+             const double* __restrict__ y, double* __restrict__ out0, double* __restrict__ out1) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= 3 * N) return;
+    const bool f = flag[i % N] != 0;
+    out0[i] = f ? y[i] : x[i];
+    out1[i] = f ? x[i] : y[i];
+}
+
 inline unsigned blocks(long long n) { return (unsigned)((n + kNT - 1) / kNT); }
 
 }  // namespace
@@ -274,6 +297,21 @@ void launch_axpby(int n, double a, const double* x, double b, const double* y, d
                   hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_axpby, dim3(blocks(n)), dim3(kNT), 0, st, n, a, x, b, y, out);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_mask_split(int N, const int* flag, const double* v, double* a, double* b,
+                       hipStream_t st) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_mask_split, dim3(blocks(3LL * N)), dim3(kNT), 0, st, N, flag, v, a, b);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_mask_merge(int N, const int* flag, const double* x, const double* y, double* out0,
+                       double* out1, hipStream_t st) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_mask_merge, dim3(blocks(3LL * N)), dim3(kNT), 0, st, N, flag, x, y,
+                       out0, out1);
     DC_HIP(hipGetLastError());
 }
 

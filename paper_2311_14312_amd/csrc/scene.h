@@ -24,6 +24,9 @@ struct dc_scene_s {
     // Boundary data and densities (device, [3][N]).
     dc::DevBuf<double> d_uplus, d_uminus, d_mu, d_sigma;
     bool solved = false;
+    // d_mu holds the boundary values u of a mixed solve (dc_solve_mixed)
+    // instead of u+ - u-
+    bool mu_from_mixed = false;
     // Segment weights of the current densities for the direct path [6][S].
     dc::DevBuf<double> seg_w;
     bool seg_w_valid = false;

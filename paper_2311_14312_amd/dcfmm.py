@@ -116,6 +116,10 @@ class TuneReport(C.Structure):
                 ("tile_err", C.c_double * 4), ("tile_ms", C.c_double * 4)]
 
 
+class AaReport(C.Structure):
+    _fields_ = [("aa_pixels", C.c_longlong), ("blocks", C.c_int), ("samples", C.c_longlong)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("eval", EvalOpts), ("out_dtype", C.c_int), ("n_streams", C.c_int),
                 ("max_batch", C.c_int), ("max_batch_pixels", C.c_longlong),
@@ -158,10 +162,14 @@ def _load():
         "dc_set_boundary": (I, [P, dp, dp]),
         "dc_solve_densities": (I, [P, C.POINTER(SolveOpts), C.POINTER(SolveReport), V]),
         "dc_get_densities": (I, [P, dp]),
+        "dc_solve_mixed": (I, [P, C.POINTER(C.c_int), dp, C.POINTER(SolveOpts),
+                               C.POINTER(SolveReport), V]),
         "dc_set_densities": (I, [P, dp]),
         "dc_apply_operator": (I, [P, V, V, I, C.POINTER(EvalOpts), V]),
         "dc_render": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, V, V]),
         "dc_render_noalloc": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, V, V]),
+        "dc_render_aa": (I, [P, C.POINTER(Viewport), C.POINTER(EvalOpts), I, I, V,
+                             C.POINTER(AaReport), V]),
         "dc_render_batch": (I, [P, C.POINTER(Viewport), I, C.POINTER(EvalOpts), I,
                                 C.POINTER(V), V]),
         "dc_eval_points": (I, [P, V, I, C.POINTER(EvalOpts), I, V, V]),
@@ -301,6 +309,25 @@ class Scene:
                 "true_rel_residual": list(rep.true_rel_residual),
                 "seconds": rep.seconds, "converged": bool(rep.converged), "rc": rc}
 
+    def solve_mixed(self, neumann, values, tol=1e-10, max_iter=1000, raise_on_fail=False,
+                    **ev):
+        """dc_solve_mixed: neumann [N] flags, values [3, N] (u* or psi*)."""
+        fl = np.ascontiguousarray(neumann, dtype=np.int32)
+        vals = _f64(values)
+        if fl.shape != (self.N,) or vals.shape != (3, self.N):
+            raise ValueError("expected neumann [N] and values [3, N]")
+        o = SolveOpts()
+        o.tol, o.max_iter, o.matvec = tol, max_iter, eval_opts(**ev)
+        o.precond = 0
+        rep = SolveReport()
+        allow = () if raise_on_fail else (DC_ERR_NOT_CONVERGED,)
+        rc = _check(_lib.dc_solve_mixed(self._h, fl.ctypes.data_as(C.POINTER(C.c_int)),
+                                        _ptr(vals), C.byref(o), C.byref(rep), _stream()),
+                    allow)
+        return {"iters": list(rep.iters), "rel_residual": list(rep.rel_residual),
+                "true_rel_residual": list(rep.true_rel_residual),
+                "seconds": rep.seconds, "converged": bool(rep.converged), "rc": rc}
+
     def densities(self):
         out = np.empty((3, self.N))
         _check(_lib.dc_get_densities(self._h, _ptr(out)))
@@ -352,6 +379,22 @@ class Scene:
         _check(_lib.dc_render_noalloc(self._h, C.byref(vp), C.byref(o), code,
                                       C.c_void_p(out.data_ptr()), _stream()))
         return out
+
+    def render_aa(self, viewport, aa=4, out=None, out_dtype=None, **ev):
+        """dc_render_aa: anti-aliased image [H, W, 3] and its report."""
+        import torch
+        cx, cy, w, h, W, H = viewport
+        vp = Viewport(float(cx), float(cy), float(w), float(h), int(W), int(H))
+        if out is None:
+            out = torch.empty((int(H), int(W), 3), device="cuda",
+                              dtype=out_dtype or torch.float32)
+        assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == (H, W, 3)
+        code = {torch.float32: OUT_F32, torch.float64: OUT_F64}[out.dtype]
+        o = eval_opts(**ev)
+        r = AaReport()
+        _check(_lib.dc_render_aa(self._h, C.byref(vp), C.byref(o), int(aa), code,
+                                 C.c_void_p(out.data_ptr()), C.byref(r), _stream()))
+        return out, {k: getattr(r, k) for k, _ in AaReport._fields_}
 
     def render_batch(self, viewports, outs=None, out_dtype=None, **ev):
         """Images of several viewports of this scene in one batched render."""

@@ -388,3 +388,115 @@ def test_tiny_config_lu_residual():
     rep = {}
     oracle.solve_stops(disc, sc["left"], sc["right"], report=rep)
     assert max(rep["rel_residual"]) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Anti-aliasing (Sec. 8): edge pixels and area-weighted values
+# --------------------------------------------------------------------------
+def test_segment_box_test_by_hand():
+    box = (0.0, 1.0, 0.0, 1.0)
+    seg = lambda a, b: oracle.segments_meet_box(np.array([a], float), np.array([b], float),
+                                                *box)[0]
+    assert seg((0.2, 0.2), (0.8, 0.7))          # inside
+    assert seg((-1.0, 0.5), (2.0, 0.5))         # crossing
+    assert seg((0.5, -1.0), (0.5, 0.0))         # ends on the bottom edge (closed box)
+    assert seg((1.5, 0.5), (0.5, 1.5))          # touches the corner (1, 1) region
+    assert seg((2.0, 0.0), (0.0, 2.0))          # passes exactly through the corner (1, 1)
+    assert not seg((2.0, 0.1), (0.1, 2.0))      # passes just outside that corner
+    assert not seg((-1.0, -0.5), (3.0, -0.1))   # below
+    assert not seg((1.2, 0.2), (1.2, 0.8))      # vertical, right of the box
+
+
+def _straight_chord_scene(y=0.3, half=10.0):
+    a, b = np.array([-half, y]), np.array([half, y])
+    ctrl = np.array([[a, a + (b - a) / 3, a + 2 * (b - a) / 3, b]])
+    disc = oracle.discretize(ctrl, 4, 16, 80)
+    sigma = np.zeros((3, disc.N))
+    mu = np.ones((3, disc.N))
+    return disc, sigma, mu
+
+
+def test_aa_pixel_split_by_a_straight_chord():
+    """A long straight chord (kappa = 1) carrying only a unit double layer
+    jumps from -1/2 below to +1/2 above (left normal up).  With 4 x 4
+    sub-squares and the chord a quarter pixel below the top of pixel row 1,
+    one sub-row lies above and three below: the anti-aliased value is
+    (1/2 - 3/2) / 4 = -1/4, while rows that the chord does not meet keep
+    their centre value (+1/2 above, -1/2 below)."""
+    disc, sigma, mu = _straight_chord_scene()
+    ph = 0.0025
+    top = 0.3 + 1.25 * ph
+    vp = (0.0, top - 2 * ph, 4 * ph, 4 * ph, 4, 4)
+    rows, cols = np.repeat(np.arange(4), 4), np.tile(np.arange(4), 4)
+    vals, edge = oracle.render_aa(disc, sigma, mu, vp, 4, rows, cols)
+    assert np.array_equal(edge, rows == 1)
+    np.testing.assert_allclose(vals[rows == 1], -0.25, atol=1e-3)
+    np.testing.assert_allclose(vals[rows == 0], 0.5, atol=1e-3)
+    np.testing.assert_allclose(vals[rows >= 2], -0.5, atol=1e-3)
+    # pixels the chord does not meet are the plain render's centre values
+    plain = oracle.render(disc, sigma, mu, vp).reshape(-1, 3)
+    assert np.array_equal(vals[rows != 1], plain[rows != 1])
+    assert np.array_equal(oracle.aa_edge_mask(disc, vp), (np.arange(4) == 1)[:, None] &
+                          np.ones((1, 4), bool))
+
+
+def test_aa_value_converges_to_the_pixel_area_average():
+    """On a pixel crossed by the chord at a slant the sub-square mean is a
+    midpoint rule for the pixel's area average: it converges as aa grows
+    (the aa = 16 and aa = 8 values differ by far less than aa = 4 and 2)."""
+    a, b = np.array([-3.0, -2.9]), np.array([3.0, 3.1])
+    ctrl = np.array([[a, a + (b - a) / 3, a + 2 * (b - a) / 3, b]])
+    disc = oracle.discretize(ctrl, 4, 16, 80)
+    sigma = np.zeros((3, disc.N))
+    mu = np.ones((3, disc.N))
+    vp = (0.0, 0.1, 0.01, 0.01, 1, 1)
+    v = {aa: oracle.render_aa(disc, sigma, mu, vp, aa, [0], [0])[0][0, 0] for aa in (2, 4, 8, 16)}
+    assert abs(v[16] - v[8]) < 0.5 * abs(v[4] - v[2]) + 1e-12
+    # the line y = x + 0.1 through the pixel's centre splits it in halves
+    assert abs(v[16]) < 0.05
+
+
+# --------------------------------------------------------------------------
+# Mixed Dirichlet/Neumann conditions on a closed curve (Sec. 5.4)
+# --------------------------------------------------------------------------
+def _square_mixed(P):
+    """u = x^2 - y^2 (harmonic) inside the CCW square [0.2, 0.8]^2: Dirichlet
+    data on the bottom and left edges, Neumann data (outward normal
+    derivative) on the right and top edges; channel c scaled by 1, 2, -1."""
+    V = np.array([[0.2, 0.2], [0.8, 0.2], [0.8, 0.8], [0.2, 0.8]])
+    disc = oracle.discretize(scenegen.polygon_ctrl(V), P, 16, 80)
+    q = disc.node_xy
+    edge = np.arange(disc.N) // (P * 16)          # bottom, right, top, left
+    n_out = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])[edge]
+    u = q[:, 0] ** 2 - q[:, 1] ** 2
+    psi = 2 * q[:, 0] * n_out[:, 0] - 2 * q[:, 1] * n_out[:, 1]
+    neumann = (edge == 1) | (edge == 2)
+    vals = np.where(neumann, psi, u)
+    corner = np.min(np.hypot(q[:, None, 0] - V[None, :, 0], q[:, None, 1] - V[None, :, 1]),
+                    axis=1)
+    return disc, neumann, np.stack([vals, 2 * vals, -vals]), u, psi, corner > 0.1
+
+
+def test_mixed_conditions_reproduce_a_harmonic_field():
+    """The field from the solved psi and u matches x^2 - y^2 inside; the
+    solved boundary values match u on the Neumann part and the normal
+    derivative on the Dirichlet part (away from the corners); all of it
+    converges as the panels are refined."""
+    pts = np.array([[0.5, 0.5], [0.35, 0.6], [0.65, 0.4], [0.3, 0.3], [0.7, 0.7]])
+    want = pts[:, 0] ** 2 - pts[:, 1] ** 2
+    errs = []
+    for P in (4, 8):
+        disc, neumann, vals, u, psi, away = _square_mixed(P)
+        ps, us = oracle.solve_mixed(disc, neumann, vals)
+        f = oracle.evaluate(disc, ps, us, pts)
+        e_in = max(np.abs(f[:, 0] - want).max(), np.abs(f[:, 1] / 2 - want).max(),
+                   np.abs(-f[:, 2] - want).max())
+        e_u = np.abs(us[0][neumann & away] - u[neumann & away]).max()
+        e_psi = np.abs(ps[0][~neumann & away] - psi[~neumann & away]).max()
+        # the known parts are returned unchanged
+        assert np.array_equal(us[:, ~neumann], vals[:, ~neumann])
+        assert np.array_equal(ps[:, neumann], vals[:, neumann])
+        errs.append((e_in, e_u, e_psi))
+    assert errs[0][0] < 2e-6 and errs[1][0] < 0.5 * errs[0][0]
+    assert errs[0][1] < 1e-5 and errs[1][1] < 0.5 * errs[0][1]
+    assert errs[0][2] < 5e-4 and errs[1][2] < 0.5 * errs[0][2]
