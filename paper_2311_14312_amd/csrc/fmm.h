@@ -90,6 +90,8 @@ struct RenderPlan {
     size_t owner_at = 0, scratch_bytes = 0;
     // per-box done flags and the claim counter of the persistent downward pass
     size_t done_at = 0, dctl_at = 0;
+    // own incoming terms and quiet flags of the split downward pass
+    size_t c_at = 0, quiet_at = 0;
     // queue of heavy small tiles (k_tile_scan, k_tile_big; 8-pixel tiles)
     size_t hv_ctl_at = 0, hv_list_at = 0, hv_flag_at = 0;
     // first-round traversal lists of light small tiles (k_tile_scan -> k_tile)

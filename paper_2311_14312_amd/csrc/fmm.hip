@@ -371,7 +371,12 @@ struct DownShared {
 // par) by one wave.  Writes nset[own] (unless the parent is quiet) and,
 // unless the box is quiet (render only, owner != nullptr), L[own]; returns
 // whether it was quiet.  Near sets hold -1 for cells without pieces.
-template <typename T, bool Count, int E = 1>
+// Split (render only): the near sets of every box are already in nset
+// (k_near_all), owner is unused, and only the box's own incoming terms,
+// M2L and P2L without the parent's L2L, are written to L[own] (k_down_l2l
+// adds the parent's share level by level); returns whether the box is
+// quiet, writing nothing then.
+template <typename T, bool Count, int E = 1, bool Split = false>
 __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceView& pv, int l,
                           long long ti, long long tj, int own, int par, int p,
                           const cpx<double>* __restrict__ M, cpx<double>* __restrict__ L,
@@ -379,7 +384,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                           int2* __restrict__ owner, unsigned long long* stats, int lane) {
     // Render: the children of a quiet box are quiet (below); they record the
     // owner and leave without using the parent's near set.
-    const int2 po = owner != nullptr ? owner[par] : make_int2(par, 0);
+    const int2 po = (!Split && owner != nullptr) ? owner[par] : make_int2(par, 0);
     int pn = -1;
     if (lane < 9) {
         pn = nset[(size_t)par * 9 + lane];
@@ -392,15 +397,18 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     // Render: a parent's near set without pieces (every cell -1) makes the
     // box quiet (see below) before anything else is loaded; its own near
     // set is then empty too.
-    if (owner != nullptr && __ballot(pn >= 0) == 0) {
+    if (Split && __ballot(pn >= 0) == 0) return true;
+    if (!Split && owner != nullptr && __ballot(pn >= 0) == 0) {
         if (lane < 9) nset[(size_t)own * 9 + lane] = -1;
         if (lane == 0) owner[own] = po;
         return true;
     }
     // the parent's expansion for L2L, loaded while the near set is resolved
-    for (int i = lane; i < 3 * (p + 1); i += kWave) {
-        const cpx<double> v = L[(size_t)par * 3 * (p + 1) + i];
-        sh.ploc()[i] = to_c<T>(v.re, v.im);
+    if constexpr (!Split) {
+        for (int i = lane; i < 3 * (p + 1); i += kWave) {
+            const cpx<double> v = L[(size_t)par * 3 * (p + 1) + i];
+            sh.ploc()[i] = to_c<T>(v.re, v.im);
+        }
     }
     __syncthreads();
     // Metadata of the parent's near set, loaded once by lanes 0..8; it
@@ -429,7 +437,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     // near set N(own): the 3 x 3 positions around own at level l, each the
     // deepest source box at level <= l covering it, or -1 where that box
     // holds no pieces (its subtree adds nothing to any list)
-    if (lane < 9) {
+    if (!Split && lane < 9) {
         const long long px = ti + (lane % 3) - 1, py = tj + (lane / 3) - 1;
         int c = -1;
         const long long lim = 1LL << l;
@@ -451,14 +459,14 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     // ancestor's, which it records instead of translating it (the L2L
     // translation of a truncated expansion is exact, so evaluating the
     // ancestor's expansion at a pixel gives the same value).
-    if (owner != nullptr) {
+    if (Split || owner != nullptr) {
         bool quiet = true;
         for (int s = 0; s < 9; ++s) quiet = quiet && (sh.PN[s] < 0 || sh.PN2[s] == 0);
         if (quiet) {
-            if (lane == 0) owner[own] = po;
+            if (!Split && lane == 0) owner[own] = po;
             return true;
         }
-        if (lane == 0) owner[own] = make_int2(own, l);
+        if (!Split && lane == 0) owner[own] = make_int2(own, l);
     }
     const int P1 = p + 1;
     const int ngrp = kWave / P1;
@@ -473,7 +481,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     cpx<T> gacc[3] = {{0, 0}, {0, 0}, {0, 0}};  // every group: its share
     // incoming-from-incoming from the parent (Eq. i-f-i), scaled:
     //   Lt_k = 2^{-k} sum_{m>=k} C(m,k) z0^{m-k} Lt'_m, z0 = (c - c')/r'
-    if (klane) {
+    if (!Split && klane) {
         const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
         const cpx<T>* src = sh.ploc();
         cpx<T> pw = {1, 0};
@@ -1151,6 +1159,136 @@ __device__ inline int xcd_block(int b, int nb) {
     return x * q + min(x, rmd) + b / kXcd;
 }
 
+// ------------------------------------------- split render downward pass
+// The render's downward pass in three steps whose launches do not depend on
+// the tree depth: near sets of every target box of every level at once
+// (k_near_all), each box's own incoming terms (M2L over its interaction
+// list and P2L over its bigger separated list, from its parent's near set)
+// at once (k_down_contrib), then one light launch per level adding the
+// parent's translated expansion (L2L) and recording the owners of quiet
+// boxes (k_down_l2l).  Coarse levels, whose few boxes each run a long chain
+// of dependent loads, then overlap with the finer ones in one launch.
+
+// Level-table entry, cell and parent of global box b (entries sorted by off).
+__device__ inline const VpLevel& box_entry(const VpLevel* __restrict__ lev, int n_ent, int b,
+                                           long long& ti, long long& tj, int& par) {
+    int lo = 0, hi = n_ent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lev[mid].off <= b) lo = mid; else hi = mid - 1;
+    }
+    const VpLevel& e = lev[lo];
+    const int rel = b - e.off;
+    ti = e.i0 + rel % e.wl;
+    tj = e.j0 + rel / e.wl;
+    par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
+    return e;
+}
+
+// Near set of box b, cell s (one thread each): the deepest source box at a
+// level <= l covering the cell, found by descending the source tree from
+// its root along the cell's path, or -1 where that box holds no pieces or
+// the cell lies outside the root.  (The same sets as the level-by-level
+// construction of down_body.)
+__global__ void __launch_bounds__(256)
+k_near_all(TreeView tv, const VpLevel* __restrict__ lev, int n_ent, int total,
+           int* __restrict__ nset) {
+    const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= 9LL * total) return;
+    const int b = (int)(gi / 9), s = (int)(gi - 9LL * b);
+    long long ti, tj;
+    int par;
+    const VpLevel& e = box_entry(lev, n_ent, b, ti, tj, par);
+    const int l = e.level;
+    const long long px = ti + (s % 3) - 1, py = tj + (s / 3) - 1;
+    const long long lim = 1LL << l;
+    int c = -1;
+    if (px >= 0 && py >= 0 && px < lim && py < lim) {
+        c = 0;
+        for (int d = 0; d < l; ++d) {
+            const int ch = tv.child[c];
+            if (ch < 0) break;  // a coarser leaf covers the cell
+            const int sh = l - d - 1;
+            const int q = (int)((px >> sh) & 1) + 2 * (int)((py >> sh) & 1);
+            if (!((tv.cmask[c] >> q) & 1)) {
+                c = -1;  // that child holds no pieces
+                break;
+            }
+            c = ch + q;
+        }
+        if (c >= 0 && tv.npc[c] == 0) c = -1;
+    }
+    nset[(size_t)b * 9 + s] = c;
+}
+
+// Own incoming terms of every non-root target box (one wave each): C[b] =
+// M2L + P2L from its parent's near set; quiet[b] = 1 (and C[b] unwritten)
+// when that near set holds no pieces.
+template <typename T, bool Count>
+__global__ void __launch_bounds__(kWave, 4)
+k_down_contrib(TreeView tv, PieceView pv, int p, const cpx<double>* __restrict__ M,
+               cpx<double>* __restrict__ C, int* __restrict__ nset,
+               const cpx<double>* __restrict__ Ttab, const VpLevel* __restrict__ lev, int n_ent,
+               int first_box, unsigned char* __restrict__ quiet, unsigned long long* stats) {
+    __shared__ DownShared<T, 1> sh;
+    const int lane = threadIdx.x;
+    const int b = first_box + xcd_block((int)blockIdx.x, (int)gridDim.x);
+    long long ti, tj;
+    int par;
+    const VpLevel& e = box_entry(lev, n_ent, b, ti, tj, par);
+    const bool q = down_body<T, Count, 1, true>(sh, tv, pv, e.level, ti, tj, b, par, p, M, C,
+                                                nset, Ttab, nullptr, stats, lane);
+    if (lane == 0) quiet[b] = q ? 1 : 0;
+}
+
+// One level of the split pass (one wave per box, lane k = coefficient k):
+// L[b] = C[b] + L2L(L[parent]) (Eq. i-f-i, scaled; the same recurrence as
+// down_body's) with owner[b] = (b, l); a quiet box records its parent's
+// owner instead (the nearest ancestor that is not quiet).
+template <typename T>
+__global__ void __launch_bounds__(kWave)
+k_down_l2l(DownLevel dl, int p, const cpx<double>* __restrict__ C, cpx<double>* __restrict__ L,
+           const unsigned char* __restrict__ quiet, int2* __restrict__ owner) {
+    __shared__ cpx<T> pl[3 * (DC_P_MAX + 1)];
+    const VpLevel& e = find_entry(dl.vl, dl.nvl, (int)blockIdx.x);
+    const int bb = (int)blockIdx.x - e.first_block;
+    const long long ti = e.i0 + bb % e.wl, tj = e.j0 + bb / e.wl;
+    const int own = e.off + bb;
+    const int par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
+    const int lane = threadIdx.x;
+    const int2 po = owner[par];
+    if (po.x != par || quiet[own]) {
+        if (lane == 0) owner[own] = po;
+        return;
+    }
+    if (lane == 0) owner[own] = make_int2(own, dl.l);
+    const int P1 = p + 1;
+    for (int i = lane; i < 3 * P1; i += kWave) {
+        const cpx<double> v = L[(size_t)par * 3 * P1 + i];
+        pl[i] = to_c<T>(v.re, v.im);
+    }
+    __syncthreads();
+    const int k = lane;
+    if (k > p) return;
+    cpx<T> acc[3];
+    for (int ch = 0; ch < 3; ++ch) {
+        const cpx<double> c = C[((size_t)own * P1 + k) * 3 + ch];
+        acc[ch] = to_c<T>(c.re, c.im);
+    }
+    const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
+    cpx<T> pw = {1, 0};
+    T binom = 1;
+    const T sc = (T)ldexp(1.0, -k);
+    for (int m = k; m <= p; ++m) {
+        const cpx<T> f = cscale(pw, binom * sc);
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, pl[m * 3 + ch]));
+        binom = binom * (T)(m + 1) * recip<T>(m + 1 - k);
+        pw = cmul(pw, z0);
+    }
+    cpx<double>* out = L + ((size_t)own * P1 + k) * 3;
+    for (int ch = 0; ch < 3; ++ch) out[ch] = {(double)acc[ch].re, (double)acc[ch].im};
+}
+
 struct Rgb {
     double v[3];
 };
@@ -1228,6 +1366,9 @@ constexpr int kDeepBoxes = 2048;  // render levels below this many boxes use k_d
 // Render downward pass: one persistent launch over every level (else one
 // k_down launch per level).
 constexpr bool kPersistentDown = false;
+// Render downward pass split into near sets, own incoming terms and a
+// per-level L2L (else one k_down launch per level).
+constexpr bool kSplitDown = true;
 
 template <typename T, int PX>
 struct TileTargets {
@@ -2161,7 +2302,33 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
             }
             DC_HIP(hipGetLastError());
         }
-        for (int l = 1; !kPersistentDown && l <= pl.maxL; ++l) {
+        if (kSplitDown && !kPersistentDown && total > nroots) {
+            const int n_ent = pl.lev_begin[pl.maxL + 1];
+            cpx<double>* C = reinterpret_cast<cpx<double>*>(scratch + pl.c_at);
+            unsigned char* quiet = reinterpret_cast<unsigned char*>(scratch + pl.quiet_at);
+            hipLaunchKernelGGL(k_near_all, dim3((unsigned)((9LL * total + 255) / 256)), dim3(256),
+                               0, st, tv, d_lev, n_ent, total, nset);
+            DC_HIP(hipGetLastError());
+            if (stats)
+                hipLaunchKernelGGL((k_down_contrib<T, true>), dim3(total - nroots), dim3(kWave), 0,
+                                   st, tv, pv, p, M, C, nset, Ttab, d_lev, n_ent, nroots, quiet,
+                                   stats);
+            else
+                hipLaunchKernelGGL((k_down_contrib<T, false>), dim3(total - nroots), dim3(kWave),
+                                   0, st, tv, pv, p, M, C, nset, Ttab, d_lev, n_ent, nroots, quiet,
+                                   stats);
+            DC_HIP(hipGetLastError());
+            for (int l = 1; l <= pl.maxL; ++l) {
+                DownLevel dl{};
+                dl.l = l;
+                dl.vl = d_lev + pl.lev_begin[l];
+                dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
+                hipLaunchKernelGGL((k_down_l2l<T>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st, dl,
+                                   p, C, TL, quiet, owner);
+                DC_HIP(hipGetLastError());
+            }
+        }
+        for (int l = 1; !kPersistentDown && !kSplitDown && l <= pl.maxL; ++l) {
             DownLevel dl{};
             dl.stats = stats;
             dl.solve = 0;
@@ -2539,7 +2706,9 @@ void plan_render(const FmmState& f, const dc_viewport* vps, int n, int tile_px, 
     pl.tl_at = up256(pl.desc_bytes);
     pl.nset_at = up256(pl.tl_at + (size_t)total * (p + 1) * 3 * sizeof(cpx<double>));
     pl.owner_at = up256(pl.nset_at + (size_t)total * 9 * sizeof(int));
-    pl.done_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
+    pl.c_at = up256(pl.owner_at + (size_t)total * sizeof(int2));
+    pl.quiet_at = up256(pl.c_at + (kSplitDown ? (size_t)total * (p + 1) * 3 * sizeof(cpx<double>) : 0));
+    pl.done_at = up256(pl.quiet_at + (kSplitDown ? (size_t)total : 0));
     pl.dctl_at = up256(pl.done_at + (size_t)total * sizeof(int));
     // queue of heavy tiles (it can hold every tile)
     const size_t nl = tile_px <= 8 ? (size_t)pl.leaf_blocks : 0;

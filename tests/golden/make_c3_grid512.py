@@ -49,7 +49,7 @@ def main():
         t0 = time.time()
         rr, cc = np.meshgrid(rows[b0:b0 + BLOCK], cols, indexing="ij")
         pts = np.stack([xs[cc.ravel()], ys[rr.ravel()]], axis=1)
-        vals = oracle.evaluate(disc, sigma, up - um, pts, workers=workers)
+        vals = oracle.evaluate(disc, sigma, up - um, pts, workers=workers, pt_chunk=256)
         np.save(path + ".tmp.npy", vals.reshape(len(rr), len(cols), 3))
         os.replace(path + ".tmp.npy", path)
         print(f"grid rows {b0}..{b0 + len(rr) - 1}: {time.time() - t0:.1f} s", flush=True)
