@@ -17,7 +17,9 @@
  *    +90 degrees) points to, so u+ = left colour, u- = right colour
  *    (Sec. 5.3, Eq. int_S_dbnd_twoside).
  *  - Nodes are numbered curve-major, then panel, then GL node in increasing
- *    parameter: i = (c*P + p)*g + k.  Densities are [3][N] (channel-major).
+ *    parameter: i = (c*P + p)*g + k, or i = panel*g + k for a scene made
+ *    from a panel list (panels listed curve by curve, in order along each).
+ *    Densities are [3][N] (channel-major).
  *  - Pixels: row r, column k of a W x H viewport with centre (cx, cy) and
  *    size (width, height) sit at x = cx - width/2 + (k+1/2) width/W,
  *    y = cy + height/2 - (r+1/2) height/H.  Images are [H][W][3], row 0 at
@@ -176,6 +178,82 @@ int dc_solve_densities(dc_scene s, const dc_solve_opts* o,
  * Synchronous; errors as dc_solve_densities. */
 int dc_solve_mixed(dc_scene s, const int* neumann, const double* values,
                    const dc_solve_opts* o, dc_solve_report* rep, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Adaptive subdivision with local re-solve (Sec. 7: Alg. 5, 6, 7).
+ *
+ * A panel is the piece of curve c between normalised arc lengths lo < hi;
+ * it carries g GL nodes and s chord segments like the equal panels of
+ * dc_scene_create.
+ *
+ * dc_scene_create_panels: a scene from an explicit panel list (host arrays
+ * [n_panels]: panel_curve, panel_lo, panel_hi; panels listed curve by
+ * curve, in order along each, not overlapping); opts->panels_per_curve is
+ * ignored.  Otherwise as dc_scene_create.
+ *
+ * dc_scene_panels: the scene's panel count, and its panel list when the
+ * arrays (host, [n_panels] each) are not null.  Synchronous.
+ *
+ * dc_panel_tails: tails[k] (host [n_panels]) = max over the colour channels
+ * of |a_{g-1}|, the highest coefficient of the Legendre expansion of the
+ * density on panel k, a_k = (2k+1)/2 sum_i w_i sigma_i P_k(x_i) (Alg. 5's
+ * test).  Needs densities.  Synchronous.
+ *
+ * dc_refine: rounds of Alg. 7 on a solved scene made from colour stops
+ * (not after dc_set_boundary or dc_solve_mixed).  Each round cuts every
+ * panel whose tail exceeds eps2, whose arc length is at least eps1 and one
+ * of whose chords meets the viewport (viewport[2] <= 0: anywhere) at its
+ * arc-length midpoint (Alg. 5); builds the new scene (same options and
+ * colour stops); starts from the old densities interpolated to the new
+ * nodes (Sec. 7.1.1); with local = 1 labels the re-solving curves --
+ * the cut curves and every curve S_b with max - min of G_H rho over S_b
+ * above ratio times that over S_a, rho = 1 on a cut curve S_a (Sec.
+ * 7.1.4) -- and solves only for their densities, the other curves' held
+ * (Eq. local_resolve_mat, with b = (u+ + u-)/2 - F_H mu computed at the new
+ * nodes); local = 0 re-solves every curve.  Rounds stop when no panel is
+ * cut or after max_rounds.  *out receives the refined scene (the caller
+ * destroys it), or NULL when the first round cut nothing; s is unchanged.
+ * resolved (host [n_curves], may be NULL) receives the last round's labels
+ * (1 = re-solved).  Synchronous.  DC_ERR_NOT_CONVERGED when a re-solve
+ * missed the tolerance (*out is still set). */
+typedef struct {
+    double eps2;          /* Legendre tail threshold (density units) */
+    double eps1;          /* shortest panel that may be cut (arc length) */
+    double viewport[4];   /* cx, cy, width, height of the region to refine */
+    double ratio;         /* re-solving rule of label_curves (0.9) */
+    int max_rounds;       /* rounds of Alg. 7 at most */
+    int local;            /* 1: local re-solve (Alg. 6); 0: every curve */
+    dc_solve_opts solve;  /* GMRES of the re-solves */
+} dc_refine_opts;
+
+typedef struct {
+    int rounds;            /* rounds that cut panels */
+    int panels_cut;        /* panels cut, all rounds */
+    int n_panels;          /* panels of the refined scene */
+    int curves_resolved;   /* re-solving curves, summed over the rounds */
+    int iters;             /* GMRES steps (largest channel), summed */
+    int converged;         /* every re-solve met the tolerance */
+    double rel_residual;   /* largest true relative residual of a re-solve */
+    double seconds;        /* wall time */
+    double label_seconds;  /* of which labelling the re-solving curves */
+    double solve_seconds;  /* of which GMRES */
+} dc_refine_report;
+
+/* eps2 = 1, eps1 = 0, whole scene, ratio 0.9, one round, local; the solve
+ * options: tol 1e-10, 500 steps, block preconditioner, FMM FP64 p = 20. */
+void dc_default_refine_opts(dc_refine_opts* o);
+int dc_scene_create_panels(const double* ctrl, int n_curves,
+                           const double* left_rgb, const double* right_rgb,
+                           int n_stops, const int* panel_curve,
+                           const double* panel_lo, const double* panel_hi,
+                           int n_panels, const dc_scene_opts* opts,
+                           dc_scene* out);
+int dc_scene_panels(dc_scene s, int* n_panels, int* panel_curve,
+                    double* panel_lo, double* panel_hi);
+int dc_panel_tails(dc_scene s, double* tails_host, void* stream);
+int dc_refine(dc_scene s, const dc_refine_opts* o, dc_scene* out,
+              dc_refine_report* rep, unsigned char* resolved_host,
+              void* stream);
 
 /* Densities sigma at the nodes, host [3][N].  Synchronous. */
 int dc_get_densities(dc_scene s, double* sigma_host);

@@ -7,3 +7,4 @@ shares no code with the GPU library (which is written in C++/HIP); the two
 meet only through the seeded input arrays of ``scenegen``.
 """
 from .dcoracle import *  # noqa: F401,F403
+from . import adaptive  # noqa: F401

@@ -164,10 +164,27 @@ class Discretization:
     seg_kappa: np.ndarray    # [S] arc length / chord length (App. A)
     curve_len: np.ndarray    # [n] total arc length per curve
     Pi: np.ndarray           # [s, g] interpolation matrix
+    # Panels of unequal length (adaptive subdivision, Sec. 7): the curve of
+    # each panel and its normalised arc-length range; None for P equal
+    # panels per curve (panels above).
+    panel_curve: np.ndarray | None = None
+    panel_lo: np.ndarray | None = None
+    panel_hi: np.ndarray | None = None
 
     @property
     def N(self):
         return self.node_xy.shape[0]
+
+    def panel_curve_of(self):
+        """Curve of every panel [N / g]."""
+        if self.panel_curve is not None:
+            return np.asarray(self.panel_curve)
+        return np.repeat(np.arange(self.n_curves), self.panels)
+
+    @property
+    def node_curve(self):
+        """Curve of every node [N]."""
+        return np.repeat(self.panel_curve_of(), self.gl)
 
     @property
     def S(self):
@@ -258,9 +275,9 @@ def boundary_values(disc, left, right):
     (right colour) at every node, each [3, N]."""
     up = np.empty((3, disc.N))
     um = np.empty((3, disc.N))
-    per = disc.panels * disc.gl
+    node_curve = disc.node_curve
     for c in range(disc.n_curves):
-        sl = slice(c * per, (c + 1) * per)
+        sl = node_curve == c
         up[:, sl] = colour_at(left[c], disc.node_lam[sl])
         um[:, sl] = colour_at(right[c], disc.node_lam[sl])
     return up, um

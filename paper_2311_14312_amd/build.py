@@ -15,6 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdcfmm.so")
 SOURCES = ["geometry.cpp", "tree.cpp", "api.cpp", "server.cpp", "autotune.cpp", "aa.cpp",
+           "refine.cpp", "refine_kernels.hip",
            "kernels_direct.hip", "fmm.hip", "precond.hip"]
 ARCH = os.environ.get("DCFMM_ARCH", "gfx950")
 

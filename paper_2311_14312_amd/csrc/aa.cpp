@@ -55,6 +55,8 @@ k_aa_combine(int n, const AaItem* __restrict__ items, const SubVp* __restrict__ 
     }
 }
 
+}  // namespace
+
 // Does the closed segment a + t (b - a), t in [0, 1], meet the closed box
 // [xa, xb] x [ya, yb]?  (Liang-Barsky clipping.)
 bool segment_meets_box(double ax, double ay, double bx, double by, double xa, double xb,
@@ -76,8 +78,6 @@ bool segment_meets_box(double ax, double ay, double bx, double by, double xa, do
     }
     return true;
 }
-
-}  // namespace
 
 void aa_edge_pixels(const Geometry& G, const dc_viewport& vp, std::vector<unsigned char>& mask) {
 #pragma clang fp contract(off)

@@ -7,6 +7,11 @@
 
 namespace dc {
 
+// Does the closed segment a + t (b - a), t in [0, 1], meet the closed box
+// [xa, xb] x [ya, yb]?
+bool segment_meets_box(double ax, double ay, double bx, double by, double xa, double xb,
+                       double ya, double yb);
+
 // mask[r * W + k] = 1 when the closed square of pixel (r, k) meets a chord
 // segment of the scene (closed segment), else 0.
 void aa_edge_pixels(const Geometry& G, const dc_viewport& vp, std::vector<unsigned char>& mask);

@@ -8,6 +8,7 @@
 #include "aa.h"
 #include "autotune.h"
 #include "scene.h"
+#include "solve.h"
 
 using namespace dc;
 
@@ -17,7 +18,7 @@ thread_local std::string g_last_error;
 
 void dc::set_last_error(const std::string& msg) { g_last_error = msg; }
 
-namespace {
+namespace dc {
 
 void check_eval(const dc_eval_opts* o) {
     DC_REQUIRE(o != nullptr, "null eval options");
@@ -80,20 +81,44 @@ void apply_operator(dc_scene s, const double* x, const double* mu, double* y,
     }
 }
 
-// Inverted diagonal blocks of the curves (computed once per scene).
+// Inverted diagonal blocks of the preconditioner (computed once per scene):
+// runs of consecutive panels of one curve of at most 512 nodes, i.e. one
+// block per curve unless the curve has more panels than fit.
 void ensure_block_inverse(dc_scene s, hipStream_t st) {
     if (s->dinv_valid) return;
     const Geometry& G = s->geo;
-    const int n = G.P * G.g;
-    s->dinv.alloc((size_t)G.n_curves * n * n);
+    const int g = G.g, cap = std::max(1, 512 / g), np = G.n_panels();
+    std::vector<int> panel_blk(np), node0, nn;
+    std::vector<long long> doff;
+    long long off = 0;
+    int maxp = 0;
+    for (int k = 0; k < np;) {
+        int e = k + 1;
+        while (e < np && e - k < cap && G.panel_curve[e] == G.panel_curve[k]) ++e;
+        for (int q = k; q < e; ++q) panel_blk[q] = (int)node0.size();
+        const long long n = (long long)(e - k) * g;
+        node0.push_back(k * g);
+        nn.push_back((int)n);
+        doff.push_back(off);
+        off += n * n;
+        maxp = std::max(maxp, e - k);
+        k = e;
+    }
+    s->blk_panel.upload(panel_blk);
+    s->blk_node0.upload(node0);
+    s->blk_n.upload(nn);
+    s->blk_doff.upload(doff);
+    s->blk_count = (int)node0.size();
+    s->blk_max_panels = maxp;
+    s->dinv.alloc((size_t)off);
     DevBuf<int> perm, flag;
-    perm.alloc((size_t)G.n_curves * n);
+    perm.alloc((size_t)G.N);
     flag.alloc(1);
     const int zero = 0;
     DC_HIP(hipMemcpy(flag.p, &zero, sizeof(int), hipMemcpyHostToDevice));
-    launch_curve_blocks(s->nodes(), G.P, G.g, G.s, s->segs(), s->seg_ell.p, s->seg_kappa.p,
-                        s->Pi.p, s->dinv.p, st);
-    launch_invert_blocks(G.n_curves, n, s->dinv.p, perm.p, flag.p, st);
+    launch_curve_blocks(s->nodes(), g, G.s, s->segs(), s->seg_ell.p, s->seg_kappa.p, s->Pi.p,
+                        s->blocks(), s->dinv.p, st);
+    launch_invert_blocks(s->blocks(), s->dinv.p, perm.p, flag.p, st);
     int singular = 0;
     DC_HIP(hipMemcpyAsync(&singular, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     DC_HIP(hipStreamSynchronize(st));
@@ -101,21 +126,18 @@ void ensure_block_inverse(dc_scene s, hipStream_t st) {
     s->dinv_valid = true;
 }
 
-// Mixed Dirichlet/Neumann data of dc_solve_mixed (device): flag [N] = 1 on
-// Neumann nodes; values [3][N] = u* on Dirichlet nodes, psi* on Neumann ones.
-struct MixedBC {
-    const int* neumann;
-    const double* values;
-};
-
 // Alg. 3 with GMRES (Sec. 6.5.1): three channels share every matvec; with
 // right preconditioning the Krylov space is built for A M^-1.  With mixed
 // conditions (Eq. neumann_mat) the unknown x holds psi on Dirichlet nodes
 // and u on Neumann nodes, A x = G_H x_d + F_H x_n - x_n / 2 and
 // b = u*_d / 2 - G_H psi*_n - F_H u*_d (d, n: the parts on Dirichlet and
-// Neumann nodes, zero elsewhere); no preconditioner.
+// Neumann nodes, zero elsewhere); no preconditioner.  With a local re-solve
+// (Eq. local_resolve_mat) the rows of the constrained nodes become the
+// identity and their right-hand side the fixed values: the Krylov vectors
+// stay zero there, so GMRES runs on (G_H)_rr with b_r - (G_H)_rc sigma_c.
+// A given initial guess replaces x0 = 1 (the warm start of Sec. 7.1.1).
 int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStream_t st,
-                const MixedBC* mixed = nullptr) {
+                const MixedBC* mixed, const LocalSolve* local) {
     const int N = s->geo.N;
     const size_t n3 = 3 * (size_t)N;
     const int m = std::max(1, std::min(o.max_iter, N));
@@ -142,9 +164,11 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         part_n.alloc(n3);
     }
     // y = A v
+    const unsigned char* cmask = local ? local->cmask : nullptr;
     auto apply_A = [&](const double* v, double* y) {
         if (!mixed) {
             apply_operator(s, v, nullptr, y, o.matvec, st);
+            if (cmask) launch_select(N, cmask, v, y, y, st);
             return;
         }
         launch_mask_split(N, mixed->neumann, v, part_d.p, part_n.p, st);
@@ -157,14 +181,18 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         apply_operator(s, nullptr, s->d_mu.p, tmp.p, o.matvec, st);
         launch_axpby((int)n3, 0.5, s->d_uplus.p, 0.5, s->d_uminus.p, b.p, st);
         launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, b.p, st);
+        if (cmask) launch_select(N, cmask, local->x0, b.p, b.p, st);
     } else {
         // known u on Dirichlet nodes (part_d), known psi on Neumann nodes (part_n)
         launch_mask_split(N, mixed->neumann, mixed->values, part_d.p, part_n.p, st);
         apply_operator(s, part_n.p, part_d.p, tmp.p, o.matvec, st);
         launch_axpby((int)n3, 0.5, part_d.p, -1.0, tmp.p, b.p, st);
     }
-    // x0 = 1, r0 = b - A x0
-    launch_fill((int)n3, 1.0, x.p, st);
+    // x0 = 1 (or the given guess), r0 = b - A x0
+    if (local && local->x0)
+        DC_HIP(hipMemcpyAsync(x.p, local->x0, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+        launch_fill((int)n3, 1.0, x.p, st);
     apply_A(x.p, tmp.p);
     launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, w.p, st);
 
@@ -200,7 +228,8 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     for (int k = 0; k < m && (active[0] || active[1] || active[2]); ++k) {
         double* vk = V.p + (size_t)k * n3;
         if (pre) {
-            launch_block_apply(N, s->geo.P * s->geo.g, s->dinv.p, vk, z.p, st);
+            launch_block_apply(N, s->geo.g, s->blocks(), s->dinv.p, vk, z.p, st);
+            if (cmask) launch_select(N, cmask, vk, z.p, z.p, st);
             apply_A(z.p, w.p);
         } else {
             apply_A(vk, w.p);
@@ -264,7 +293,8 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
             // x += M^-1 (V y)
             launch_fill((int)n3, 0.0, tmp.p, st);
             launch_combine(V.p, kmax, dy.p, kcap, tmp.p, N, st);
-            launch_block_apply(N, s->geo.P * s->geo.g, s->dinv.p, tmp.p, z.p, st);
+            launch_block_apply(N, s->geo.g, s->blocks(), s->dinv.p, tmp.p, z.p, st);
+            if (cmask) launch_select(N, cmask, tmp.p, z.p, z.p, st);
             launch_axpby((int)n3, 1.0, x.p, 1.0, z.p, x.p, st);
         } else {
             launch_combine(V.p, kmax, dy.p, kcap, x.p, N, st);
@@ -298,7 +328,53 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     return rep.converged ? DC_OK : DC_ERR_NOT_CONVERGED;
 }
 
-}  // namespace
+std::unique_ptr<dc_scene_s> make_scene(const double* ctrl, int n_curves, const double* left_rgb,
+                                       const double* right_rgb, int n_stops,
+                                       const dc_scene_opts* opts, const int* panel_curve,
+                                       const double* panel_lo, const double* panel_hi,
+                                       int n_panels) {
+    auto s = std::make_unique<dc_scene_s>();
+    s->opts = *opts;
+    if (panel_curve == nullptr)
+        discretize(ctrl, n_curves, opts->panels_per_curve, opts->gl_per_panel,
+                   opts->segs_per_panel, s->geo);
+    else
+        discretize_panels(ctrl, n_curves, panel_curve, panel_lo, panel_hi, n_panels,
+                          opts->gl_per_panel, opts->segs_per_panel, s->geo);
+    boundary_from_stops(s->geo, left_rgb, right_rgb, n_stops, s->uplus, s->uminus);
+    s->ctrl.assign(ctrl, ctrl + (size_t)n_curves * 8);
+    s->left_rgb.assign(left_rgb, left_rgb + (size_t)n_curves * n_stops * 3);
+    s->right_rgb.assign(right_rgb, right_rgb + (size_t)n_curves * n_stops * 3);
+    s->n_stops = n_stops;
+    s->boundary_from_stops = true;
+    build_tree(s->geo, opts->leaf_max, opts->max_depth, opts->domain, s->tree);
+    const Geometry& G = s->geo;
+    std::vector<double> tx(G.S), ty(G.S), len(G.S);
+    for (int j = 0; j < G.S; ++j) {
+        const double ax = G.seg_x1[j] - G.seg_x0[j], ay = G.seg_y1[j] - G.seg_y0[j];
+        len[j] = std::hypot(ax, ay);
+        tx[j] = ax / len[j];
+        ty[j] = ay / len[j];
+    }
+    s->seg_x0.upload(G.seg_x0);
+    s->seg_y0.upload(G.seg_y0);
+    s->seg_tx.upload(tx);
+    s->seg_ty.upload(ty);
+    s->seg_len.upload(len);
+    s->seg_ell.upload(G.seg_ell);
+    s->seg_kappa.upload(G.seg_kappa);
+    s->node_x.upload(G.node_x);
+    s->node_y.upload(G.node_y);
+    s->node_tstar.upload(G.node_tstar);
+    s->node_self.upload(G.node_self);
+    s->Pi.upload(G.Pi);
+    s->panel_curve.upload(G.panel_curve);
+    upload_boundary(s.get());
+    s->fmm = fmm_create(*s);
+    return s;
+}
+
+}  // namespace dc
 
 extern "C" {
 
@@ -330,35 +406,38 @@ int dc_scene_create(const double* ctrl, int n_curves, const double* left_rgb,
     return guarded([&] {
         DC_REQUIRE(ctrl && left_rgb && right_rgb && opts && out, "null argument");
         *out = nullptr;
-        auto s = std::make_unique<dc_scene_s>();
-        s->opts = *opts;
-        discretize(ctrl, n_curves, opts->panels_per_curve, opts->gl_per_panel,
-                   opts->segs_per_panel, s->geo);
-        boundary_from_stops(s->geo, left_rgb, right_rgb, n_stops, s->uplus, s->uminus);
-        build_tree(s->geo, opts->leaf_max, opts->max_depth, opts->domain, s->tree);
+        *out = make_scene(ctrl, n_curves, left_rgb, right_rgb, n_stops, opts, nullptr, nullptr,
+                          nullptr, 0)
+                   .release();
+    });
+}
+
+int dc_scene_create_panels(const double* ctrl, int n_curves, const double* left_rgb,
+                           const double* right_rgb, int n_stops, const int* panel_curve,
+                           const double* panel_lo, const double* panel_hi, int n_panels,
+                           const dc_scene_opts* opts, dc_scene* out) {
+    return guarded([&] {
+        DC_REQUIRE(ctrl && left_rgb && right_rgb && panel_curve && panel_lo && panel_hi && opts &&
+                       out,
+                   "null argument");
+        *out = nullptr;
+        *out = make_scene(ctrl, n_curves, left_rgb, right_rgb, n_stops, opts, panel_curve,
+                          panel_lo, panel_hi, n_panels)
+                   .release();
+    });
+}
+
+int dc_scene_panels(dc_scene s, int* n_panels, int* panel_curve, double* panel_lo,
+                    double* panel_hi) {
+    return guarded([&] {
+        DC_REQUIRE(s && n_panels, "null argument");
         const Geometry& G = s->geo;
-        std::vector<double> tx(G.S), ty(G.S), len(G.S);
-        for (int j = 0; j < G.S; ++j) {
-            const double ax = G.seg_x1[j] - G.seg_x0[j], ay = G.seg_y1[j] - G.seg_y0[j];
-            len[j] = std::hypot(ax, ay);
-            tx[j] = ax / len[j];
-            ty[j] = ay / len[j];
+        *n_panels = G.n_panels();
+        for (int k = 0; k < G.n_panels(); ++k) {
+            if (panel_curve) panel_curve[k] = G.panel_curve[k];
+            if (panel_lo) panel_lo[k] = G.panel_lo[k];
+            if (panel_hi) panel_hi[k] = G.panel_hi[k];
         }
-        s->seg_x0.upload(G.seg_x0);
-        s->seg_y0.upload(G.seg_y0);
-        s->seg_tx.upload(tx);
-        s->seg_ty.upload(ty);
-        s->seg_len.upload(len);
-        s->seg_ell.upload(G.seg_ell);
-        s->seg_kappa.upload(G.seg_kappa);
-        s->node_x.upload(G.node_x);
-        s->node_y.upload(G.node_y);
-        s->node_tstar.upload(G.node_tstar);
-        s->node_self.upload(G.node_self);
-        s->Pi.upload(G.Pi);
-        upload_boundary(s.get());
-        s->fmm = fmm_create(*s);
-        *out = s.release();
     });
 }
 
@@ -408,6 +487,7 @@ int dc_set_boundary(dc_scene s, const double* up, const double* um) {
             DC_REQUIRE(std::isfinite(up[i]) && std::isfinite(um[i]), "non-finite boundary value");
         s->uplus.assign(up, up + n3);
         s->uminus.assign(um, um + n3);
+        s->boundary_from_stops = false;
         upload_boundary(s);
     });
 }
@@ -424,7 +504,7 @@ int dc_solve_densities(dc_scene s, const dc_solve_opts* o, dc_solve_report* rep,
         std::memset(rep, 0, sizeof(*rep));
         if (s->mu_from_mixed) upload_boundary(s);  // two-sided data again
         const auto t0 = std::chrono::steady_clock::now();
-        rc = gmres_solve(s, *o, *rep, as_stream(stream));
+        rc = gmres_solve(s, *o, *rep, as_stream(stream), nullptr, nullptr);
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (rc != DC_OK) g_last_error = "GMRES did not reach the tolerance";
     });
@@ -452,7 +532,7 @@ int dc_solve_mixed(dc_scene s, const int* neumann, const double* values,
         d_vals.upload(vals);
         const MixedBC mixed{d_flag.p, d_vals.p};
         const auto t0 = std::chrono::steady_clock::now();
-        rc = gmres_solve(s, *o, *rep, as_stream(stream), &mixed);
+        rc = gmres_solve(s, *o, *rep, as_stream(stream), &mixed, nullptr);
         s->mu_from_mixed = true;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (rc != DC_OK) g_last_error = "GMRES did not reach the tolerance";

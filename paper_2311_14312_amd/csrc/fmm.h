@@ -131,6 +131,9 @@ struct FmmState {
     bool up_valid = false;
     unsigned long long gen = 0;
     int up_p = -1, up_prec = -1;
+    // Count of upward passes run (a captured render graph reads the
+    // expansion buffers of one of them).
+    unsigned long long up_epoch = 0;
     // Render of the dc_render / dc_render_batch calls: plan, descriptor
     // staging and device scratch (see RenderPlan).
     // The staging is a ring, so the host can plan the next render while the
@@ -193,8 +196,7 @@ struct RenderGraph {
     dc_eval_opts o{};
     int out_dtype = 0;
     unsigned long long gen = 0;
-    const void* M64 = nullptr;   // the resident expansion buffers the
-    const void* Ms64 = nullptr;  // captured launches read
+    unsigned long long up_epoch = 0;  // upward pass whose buffers the launches read
     RenderPlan plan;
     void* stage = nullptr;
     DevBuf<char> scratch;

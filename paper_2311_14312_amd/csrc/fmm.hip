@@ -2264,6 +2264,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     if (timed) DC_HIP(hipEventRecord(f.ev[0], st));
     if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
         upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st);
+        ++f.up_epoch;
         f.up_valid = true;
         f.up_p = p;
         f.up_prec = (int)sizeof(T);
@@ -2747,6 +2748,7 @@ void fmm_prepare(dc_scene_s& s, const dc_eval_opts& o, hipStream_t st) {
     const int prec = o.precision == DC_PREC_F32 ? 4 : 8;
     if (!f.up_valid || f.up_p != o.p || f.up_prec != prec) {
         upward(s, f, s.d_sigma.p, s.d_mu.p, o.p, prec == 4, st);
+        ++f.up_epoch;
         f.up_valid = true;
         f.up_p = o.p;
         f.up_prec = prec;
@@ -2784,8 +2786,7 @@ std::unique_ptr<RenderGraph> fmm_graph_create(dc_scene_s& s, const dc_viewport* 
             (void)f.aux_stream();
         }
         g->gen = f.gen;
-        g->M64 = f.M64.p;
-        g->Ms64 = f.Ms64.p;
+        g->up_epoch = f.up_epoch;
         DC_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         try {
             if (o.precision == DC_PREC_F32)
@@ -2815,8 +2816,7 @@ void fmm_graph_launch(RenderGraph& g, hipStream_t st) {
     fmm_check_stall(f);
     const int prec = g.o.precision == DC_PREC_F32 ? 4 : 8;
     DC_REQUIRE(f.gen == g.gen, "the scene's densities changed since the render graph was made");
-    DC_REQUIRE(f.up_valid && f.up_p == g.o.p && f.up_prec == prec && f.M64.p == g.M64 &&
-                   f.Ms64.p == g.Ms64,
+    DC_REQUIRE(f.up_valid && f.up_p == g.o.p && f.up_prec == prec && f.up_epoch == g.up_epoch,
                "the scene's resident expansions were rebuilt since the render graph was made "
                "(make the graph again)");
     DC_HIP(hipGraphLaunch(g.exec, st));

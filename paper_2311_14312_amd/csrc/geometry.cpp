@@ -233,6 +233,109 @@ void discretize(const double* ctrl, int n_curves, int P, int g, int s, Geometry&
         }
     }
     G.Pi = interp_matrix(g, s);
+    G.panel_curve.resize((size_t)n_curves * P);
+    G.panel_lo.resize((size_t)n_curves * P);
+    G.panel_hi.resize((size_t)n_curves * P);
+    for (int c = 0; c < n_curves; ++c)
+        for (int p = 0; p < P; ++p) {
+            G.panel_curve[(size_t)c * P + p] = c;
+            G.panel_lo[(size_t)c * P + p] = (double)p / P;
+            G.panel_hi[(size_t)c * P + p] = (double)(p + 1) / P;
+        }
+}
+
+void discretize_panels(const double* ctrl, int n_curves, const int* pc, const double* lo,
+                       const double* hi, int n_panels, int g, int s, Geometry& G) {
+    DC_REQUIRE(n_curves > 0 && n_panels > 0, "need curves and panels");
+    DC_REQUIRE(g >= 1 && s >= g, "need g >= 1 and s >= g");
+    DC_REQUIRE((long long)n_panels * s < (1LL << 31), "too many segments");
+    check_finite(ctrl, (size_t)n_curves * 8, "ctrl");
+    check_finite(lo, (size_t)n_panels, "panel_lo");
+    check_finite(hi, (size_t)n_panels, "panel_hi");
+    for (int k = 0; k < n_panels; ++k) {
+        DC_REQUIRE(pc[k] >= 0 && pc[k] < n_curves, "panel curve out of range");
+        DC_REQUIRE(lo[k] >= 0.0 && hi[k] <= 1.0 && lo[k] < hi[k], "panel range outside [0, 1]");
+        if (k > 0) DC_REQUIRE(pc[k] > pc[k - 1] || (pc[k] == pc[k - 1] && lo[k] >= hi[k - 1]),
+                              "panels must be listed curve by curve, in order along each");
+    }
+    G.n_curves = n_curves;
+    G.P = 0;
+    G.g = g;
+    G.s = s;
+    G.N = n_panels * g;
+    G.S = n_panels * s;
+    std::vector<double> xg, wg;
+    gauss_legendre(g, xg, wg);
+    G.gl_x = xg;
+    G.node_x.resize(G.N);
+    G.node_y.resize(G.N);
+    G.node_lam.resize(G.N);
+    G.node_self.resize(G.N);
+    G.node_tstar.resize(G.N);
+    G.seg_x0.resize(G.S);
+    G.seg_y0.resize(G.S);
+    G.seg_x1.resize(G.S);
+    G.seg_y1.resize(G.S);
+    G.seg_ell.resize(G.S);
+    G.seg_kappa.resize(G.S);
+    G.curve_len.assign(n_curves, 0.0);
+    G.panel_curve.assign(pc, pc + n_panels);
+    G.panel_lo.assign(lo, lo + n_panels);
+    G.panel_hi.assign(hi, hi + n_panels);
+    std::vector<int> jloc(g);
+    std::vector<double> tstar(g);
+    for (int k = 0; k < g; ++k) {
+        // self segment: tau_j <= x_k < tau_{j+1}, tau_j = -1 + 2j/s (App. C.1)
+        int j = (int)std::floor((xg[k] + 1.0) * s / 2.0);
+        j = std::min(std::max(j, 0), s - 1);
+        jloc[k] = j;
+        tstar[k] = (xg[k] - (-1.0 + 2.0 * j / s)) / (2.0 / s);
+    }
+    std::vector<double> ex(s + 1), ey(s + 1);
+    int cur = -1;
+    ArcTable tab;
+    for (int panel = 0; panel < n_panels; ++panel) {
+        const int c = pc[panel];
+        const double* cc = ctrl + (size_t)c * 8;
+        if (c != cur) {
+            tab = build_arc_table(cc);
+            DC_REQUIRE(tab.total > 0.0 && std::isfinite(tab.total), "zero-length curve");
+            G.curve_len[c] = tab.total;
+            cur = c;
+        }
+        const double L = tab.total, a = lo[panel], w = hi[panel] - lo[panel];
+        for (int k = 0; k < g; ++k) {
+            const double lam = a + w * (0.5 * (xg[k] + 1.0));
+            const double t = param_at_length(cc, tab, L * lam);
+            const int i = panel * g + k;
+            bezier(cc, t, G.node_x[i], G.node_y[i]);
+            G.node_lam[i] = lam;
+            G.node_self[i] = panel * s + jloc[k];
+            G.node_tstar[i] = tstar[k];
+        }
+        for (int j = 0; j <= s; ++j) {
+            const double t = param_at_length(cc, tab, L * (a + w * ((double)j / s)));
+            bezier(cc, t, ex[j], ey[j]);
+        }
+        const double ell = L * w / s;
+        for (int j = 0; j < s; ++j) {
+            const int q = panel * s + j;
+            G.seg_x0[q] = ex[j];
+            G.seg_y0[q] = ey[j];
+            G.seg_x1[q] = ex[j + 1];
+            G.seg_y1[q] = ey[j + 1];
+            const double chord = std::hypot(ex[j + 1] - ex[j], ey[j + 1] - ey[j]);
+            DC_REQUIRE(chord > 0.0, "degenerate (zero-length) chord segment");
+            G.seg_ell[q] = ell;
+            G.seg_kappa[q] = ell / chord;
+        }
+    }
+    for (int c = 0; c < n_curves; ++c)
+        if (G.curve_len[c] == 0.0) {
+            const ArcTable t2 = build_arc_table(ctrl + (size_t)c * 8);
+            G.curve_len[c] = t2.total;
+        }
+    G.Pi = interp_matrix(g, s);
 }
 
 // Colour piecewise linear in normalised arc length through stops at
@@ -252,9 +355,8 @@ void boundary_from_stops(const Geometry& G, const double* left, const double* ri
     check_finite(right, (size_t)G.n_curves * n_stops * 3, "right_rgb");
     up.assign((size_t)3 * G.N, 0.0);
     um.assign((size_t)3 * G.N, 0.0);
-    const int per = G.P * G.g;
     for (int i = 0; i < G.N; ++i) {
-        const int c = i / per;
+        const int c = G.panel_curve[i / G.g];
         for (int ch = 0; ch < 3; ++ch) {
             up[(size_t)ch * G.N + i] = colour(left + (size_t)c * n_stops * 3, n_stops, ch, G.node_lam[i]);
             um[(size_t)ch * G.N + i] = colour(right + (size_t)c * n_stops * 3, n_stops, ch, G.node_lam[i]);

@@ -67,14 +67,25 @@ void launch_mask_merge(int N, const int* flag, const double* x, const double* y,
                        double* out1, hipStream_t st);
 
 // ------------------------------------------------- block-Jacobi preconditioner
-// D[c] = diagonal block of curve c (n = P g rows), row-major.
-void launch_curve_blocks(const NodesView& nodes, int P, int g, int s, const ChordsView& segs,
-                         const double* ell, const double* kappa, const double* Pi, double* D,
-                         hipStream_t st);
-void launch_invert_blocks(int n_blocks, int n, double* D, int* perm, int* singular,
+// Diagonal blocks: runs of consecutive panels of one curve (every panel of a
+// curve when they fit), row-major, one after another in D.  Device arrays.
+struct BlocksView {
+    int n_blocks, max_panels;  // blocks; most panels in one block
+    const int* panel_blk;      // [n_panels] block of each panel
+    const int* node0;          // [n_blocks] first node of the block
+    const int* n;              // [n_blocks] nodes of the block (<= 512)
+    const long long* doff;     // [n_blocks] first element of the block in D
+};
+void launch_curve_blocks(const NodesView& nodes, int g, int s, const ChordsView& segs,
+                         const double* ell, const double* kappa, const double* Pi,
+                         const BlocksView& bv, double* D, hipStream_t st);
+void launch_invert_blocks(const BlocksView& bv, double* D, int* perm, int* singular,
                           hipStream_t st);
 // y[ch] = blockdiag(Dinv) x[ch] for the three channels
-void launch_block_apply(int N, int n, const double* Dinv, const double* x, double* y,
-                        hipStream_t st);
+void launch_block_apply(int N, int g, const BlocksView& bv, const double* Dinv, const double* x,
+                        double* y, hipStream_t st);
+// [3][N] vectors: out = flag[i] ? a : b (in place allowed)
+void launch_select(int N, const unsigned char* flag, const double* a, const double* b,
+                   double* out, hipStream_t st);
 
 }  // namespace dc

@@ -237,6 +237,14 @@ k_mask_merge(int N, const int* __restrict__ flag, const double* __restrict__ x,
     out1[i] = f ? x[i] : y[i];
 }
 
+__global__ void __launch_bounds__(kNT)
+k_select(int N, const unsigned char* __restrict__ flag, const double* a, const double* b,
+         double* out) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= 3 * N) return;
+    out[i] = flag[i % N] ? a[i] : b[i];
+}
+
 inline unsigned blocks(long long n) { return (unsigned)((n + kNT - 1) / kNT); }
 
 }  // namespace
@@ -312,6 +320,13 @@ void launch_mask_merge(int N, const int* flag, const double* x, const double* y,
     if (N <= 0) return;
     hipLaunchKernelGGL(k_mask_merge, dim3(blocks(3LL * N)), dim3(kNT), 0, st, N, flag, x, y,
                        out0, out1);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_select(int N, const unsigned char* flag, const double* a, const double* b,
+                   double* out, hipStream_t st) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_select, dim3(blocks(3LL * N)), dim3(kNT), 0, st, N, flag, a, b, out);
     DC_HIP(hipGetLastError());
 }
 

@@ -16,17 +16,20 @@ constexpr int kNT = 256;
 
 // One thread per (node i, panel p' of the node's curve): 16 entries of row i.
 __global__ void __launch_bounds__(kNT)
-k_curve_blocks(int N, int P, int g, int s, const double* __restrict__ nx,
+k_curve_blocks(int N, int g, int s, const double* __restrict__ nx,
                const double* __restrict__ ny, const int* __restrict__ self_seg,
                const double* __restrict__ tstar, ChordsView segs,
                const double* __restrict__ ell, const double* __restrict__ kappa,
-               const double* __restrict__ Pi, double* __restrict__ D) {
+               const double* __restrict__ Pi, BlocksView bv, double* __restrict__ D) {
     const long long t = (long long)blockIdx.x * kNT + threadIdx.x;
-    const int n = P * g;
-    if (t >= (long long)N * P) return;
-    const int i = (int)(t / P), pp = (int)(t - (long long)i * P);
-    const int c = i / n, iloc = i - c * n;
-    const int panel = c * P + pp;
+    const int mp = bv.max_panels;
+    if (t >= (long long)N * mp) return;
+    const int i = (int)(t / mp), pp = (int)(t - (long long)i * mp);
+    const int b = bv.panel_blk[i / g];
+    const int node0 = bv.node0[b], n = bv.n[b];
+    if (pp >= n / g) return;
+    const int iloc = i - node0;
+    const int panel = node0 / g + pp;
     const double x = nx[i], y = ny[i];
     const int self = self_seg[i];
     double acc[64];
@@ -45,21 +48,19 @@ k_curve_blocks(int N, int P, int g, int s, const double* __restrict__ nx,
         const double* pr = Pi + (size_t)jj * g;
         for (int m = 0; m < g; ++m) acc[m] += G * pr[m];
     }
-    double* row = D + (size_t)c * n * n + (size_t)iloc * n + (size_t)pp * g;
+    double* row = D + bv.doff[b] + (size_t)iloc * n + (size_t)pp * g;
     for (int m = 0; m < g; ++m) row[m] = acc[m];
 }
 
-// In-place Gauss-Jordan inversion with partial (row) pivoting, one
-// workgroup per block; the row interchanges are undone as column swaps at
-// the end.  A singular block leaves the flag set and its inverse undefined.
 __global__ void __launch_bounds__(kNT)
-k_gauss_jordan(int n, double* __restrict__ D, int* __restrict__ perm_all,
+k_gauss_jordan(BlocksView bv, double* __restrict__ D, int* __restrict__ perm_all,
                int* __restrict__ singular) {
     __shared__ double sval[kNT];
     __shared__ int sidx[kNT];
     __shared__ double rowk[512], colk[512];
-    double* a = D + (size_t)blockIdx.x * n * n;
-    int* perm = perm_all + (size_t)blockIdx.x * n;
+    const int n = bv.n[blockIdx.x];
+    double* a = D + bv.doff[blockIdx.x];
+    int* perm = perm_all + bv.node0[blockIdx.x];
     const int tid = threadIdx.x;
     for (int k = 0; k < n; ++k) {
         // pivot: largest |a[i][k]|, i >= k (first index on ties)
@@ -136,14 +137,16 @@ k_gauss_jordan(int n, double* __restrict__ D, int* __restrict__ perm_all,
 
 // y[ch][i] = sum_j Dinv[c][iloc][j] x[ch][c n + j]
 __global__ void __launch_bounds__(kNT)
-k_block_apply(int N, int n, const double* __restrict__ Dinv, const double* __restrict__ x,
-              double* __restrict__ y) {
+k_block_apply(int N, int g, BlocksView bv, const double* __restrict__ Dinv,
+              const double* __restrict__ x, double* __restrict__ y) {
     const int i = blockIdx.x * kNT + threadIdx.x;
     const int ch = blockIdx.y;
     if (i >= N) return;
-    const int c = i / n, iloc = i - c * n;
-    const double* row = Dinv + (size_t)c * n * n + (size_t)iloc * n;
-    const double* xv = x + (size_t)ch * N + (size_t)c * n;
+    const int b = bv.panel_blk[i / g];
+    const int node0 = bv.node0[b], n = bv.n[b];
+    const int iloc = i - node0;
+    const double* row = Dinv + bv.doff[b] + (size_t)iloc * n;
+    const double* xv = x + (size_t)ch * N + (size_t)node0;
     double acc = 0.0;
     for (int j = 0; j < n; ++j) acc += row[j] * xv[j];
     y[(size_t)ch * N + i] = acc;
@@ -151,28 +154,28 @@ k_block_apply(int N, int n, const double* __restrict__ Dinv, const double* __res
 
 }  // namespace
 
-void launch_curve_blocks(const NodesView& nodes, int P, int g, int s, const ChordsView& segs,
-                         const double* ell, const double* kappa, const double* Pi, double* D,
-                         hipStream_t st) {
+void launch_curve_blocks(const NodesView& nodes, int g, int s, const ChordsView& segs,
+                         const double* ell, const double* kappa, const double* Pi,
+                         const BlocksView& bv, double* D, hipStream_t st) {
     DC_REQUIRE(g <= 64, "block preconditioner supports at most 64 GL nodes per panel");
-    const long long threads = (long long)nodes.N * P;
+    const long long threads = (long long)nodes.N * bv.max_panels;
     hipLaunchKernelGGL(k_curve_blocks, dim3((unsigned)((threads + kNT - 1) / kNT)), dim3(kNT), 0,
-                       st, nodes.N, P, g, s, nodes.x, nodes.y, nodes.self_seg, nodes.tstar,
-                       segs, ell, kappa, Pi, D);
+                       st, nodes.N, g, s, nodes.x, nodes.y, nodes.self_seg, nodes.tstar, segs,
+                       ell, kappa, Pi, bv, D);
     DC_HIP(hipGetLastError());
 }
 
-void launch_invert_blocks(int n_blocks, int n, double* D, int* perm, int* singular,
+void launch_invert_blocks(const BlocksView& bv, double* D, int* perm, int* singular,
                           hipStream_t st) {
-    DC_REQUIRE(n <= 512, "block preconditioner supports at most 512 nodes per curve");
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(n_blocks), dim3(kNT), 0, st, n, D, perm, singular);
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(bv.n_blocks), dim3(kNT), 0, st, bv, D, perm,
+                       singular);
     DC_HIP(hipGetLastError());
 }
 
-void launch_block_apply(int N, int n, const double* Dinv, const double* x, double* y,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_block_apply, dim3((N + kNT - 1) / kNT, 3), dim3(kNT), 0, st, N, n, Dinv,
-                       x, y);
+void launch_block_apply(int N, int g, const BlocksView& bv, const double* Dinv, const double* x,
+                        double* y, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_apply, dim3((N + kNT - 1) / kNT, 3), dim3(kNT), 0, st, N, g, bv,
+                       Dinv, x, y);
     DC_HIP(hipGetLastError());
 }
 

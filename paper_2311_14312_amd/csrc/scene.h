@@ -14,6 +14,12 @@ struct dc_scene_s {
     dc::Geometry geo;
     dc::Tree tree;
     std::vector<double> uplus, uminus;  // [3][N] host
+    // The curves and colour stops the scene was made from (adaptive
+    // refinement re-discretises them); boundary_from_stops is false once
+    // the caller has set boundary values at the nodes.
+    std::vector<double> ctrl, left_rgb, right_rgb;
+    int n_stops = 0;
+    bool boundary_from_stops = false;
 
     // Segments (device).
     dc::DevBuf<double> seg_x0, seg_y0, seg_tx, seg_ty, seg_len, seg_ell, seg_kappa;
@@ -21,6 +27,7 @@ struct dc_scene_s {
     dc::DevBuf<double> node_x, node_y, node_tstar;
     dc::DevBuf<int> node_self;
     dc::DevBuf<double> Pi;
+    dc::DevBuf<int> panel_curve;  // [N / g]
     // Boundary data and densities (device, [3][N]).
     dc::DevBuf<double> d_uplus, d_uminus, d_mu, d_sigma;
     bool solved = false;
@@ -31,9 +38,15 @@ struct dc_scene_s {
     dc::DevBuf<double> seg_w;
     bool seg_w_valid = false;
 
-    // Inverted per-curve diagonal blocks (block-Jacobi preconditioner).
+    // Inverted diagonal blocks (block-Jacobi preconditioner) and their layout.
     dc::DevBuf<double> dinv;
     bool dinv_valid = false;
+    dc::DevBuf<int> blk_panel, blk_node0, blk_n;
+    dc::DevBuf<long long> blk_doff;
+    int blk_count = 0, blk_max_panels = 0;
+    dc::BlocksView blocks() const {
+        return {blk_count, blk_max_panels, blk_panel.p, blk_node0.p, blk_n.p, blk_doff.p};
+    }
 
     // FMM state (tree on device, expansions, scratch).
     std::unique_ptr<dc::FmmState> fmm;

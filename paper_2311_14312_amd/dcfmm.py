@@ -120,6 +120,19 @@ class AaReport(C.Structure):
     _fields_ = [("aa_pixels", C.c_longlong), ("blocks", C.c_int), ("samples", C.c_longlong)]
 
 
+class RefineOpts(C.Structure):
+    _fields_ = [("eps2", C.c_double), ("eps1", C.c_double), ("viewport", C.c_double * 4),
+                ("ratio", C.c_double), ("max_rounds", C.c_int), ("local", C.c_int),
+                ("solve", SolveOpts)]
+
+
+class RefineReport(C.Structure):
+    _fields_ = [("rounds", C.c_int), ("panels_cut", C.c_int), ("n_panels", C.c_int),
+                ("curves_resolved", C.c_int), ("iters", C.c_int), ("converged", C.c_int),
+                ("rel_residual", C.c_double), ("seconds", C.c_double),
+                ("label_seconds", C.c_double), ("solve_seconds", C.c_double)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("eval", EvalOpts), ("out_dtype", C.c_int), ("n_streams", C.c_int),
                 ("max_batch", C.c_int), ("max_batch_pixels", C.c_longlong),
@@ -156,6 +169,13 @@ def _load():
         "dc_default_scene_opts": (None, [C.POINTER(SceneOpts)]),
         "dc_default_eval_opts": (None, [C.POINTER(EvalOpts)]),
         "dc_scene_create": (I, [dp, I, dp, dp, I, C.POINTER(SceneOpts), C.POINTER(P)]),
+        "dc_scene_create_panels": (I, [dp, I, dp, dp, I, C.POINTER(C.c_int), dp, dp, I,
+                                       C.POINTER(SceneOpts), C.POINTER(P)]),
+        "dc_scene_panels": (I, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), dp, dp]),
+        "dc_panel_tails": (I, [P, dp, V]),
+        "dc_default_refine_opts": (None, [C.POINTER(RefineOpts)]),
+        "dc_refine": (I, [P, C.POINTER(RefineOpts), C.POINTER(P), C.POINTER(RefineReport),
+                          C.POINTER(C.c_ubyte), V]),
         "dc_scene_destroy": (None, [P]),
         "dc_scene_get_info": (I, [P, C.POINTER(SceneInfo)]),
         "dc_get_nodes": (I, [P, dp]),
@@ -239,7 +259,9 @@ class Scene:
     """A resident scene: geometry, quadtree and densities on the device."""
 
     def __init__(self, ctrl, left, right, panels=16, gl=16, segs=80, leaf_max=64,
-                 max_depth=40, domain=None):
+                 max_depth=40, domain=None, panel_list=None):
+        """panels equal panels per curve, or panel_list = (curve, lo, hi):
+        panels of any lengths (dc_scene_create_panels)."""
         o = SceneOpts()
         _lib.dc_default_scene_opts(C.byref(o))
         o.panels_per_curve, o.gl_per_panel, o.segs_per_panel = panels, gl, segs
@@ -254,9 +276,66 @@ class Scene:
                 or left.ndim != 3 or left.shape[2] != 3:
             raise ValueError("expected ctrl [n,4,2] and left/right [n,stops,3]")
         h = C.c_void_p()
-        _check(_lib.dc_scene_create(_ptr(self._ctrl), n, _ptr(left), _ptr(right),
-                                    left.shape[1], C.byref(o), C.byref(h)))
+        if panel_list is None:
+            _check(_lib.dc_scene_create(_ptr(self._ctrl), n, _ptr(left), _ptr(right),
+                                        left.shape[1], C.byref(o), C.byref(h)))
+        else:
+            pc = np.ascontiguousarray(panel_list[0], dtype=np.int32)
+            lo, hi = _f64(panel_list[1]), _f64(panel_list[2])
+            if lo.shape != pc.shape or hi.shape != pc.shape or pc.ndim != 1:
+                raise ValueError("panel_list: three arrays [n_panels]")
+            _check(_lib.dc_scene_create_panels(
+                _ptr(self._ctrl), n, _ptr(left), _ptr(right), left.shape[1],
+                pc.ctypes.data_as(C.POINTER(C.c_int)), _ptr(lo), _ptr(hi), len(pc),
+                C.byref(o), C.byref(h)))
         self._h = h
+
+    @classmethod
+    def _wrap(cls, handle):
+        sc = cls.__new__(cls)
+        sc._h = handle
+        return sc
+
+    def panels(self):
+        """The panel list (curve [n], lo [n], hi [n]) of dc_scene_panels."""
+        n = C.c_int()
+        _check(_lib.dc_scene_panels(self._h, C.byref(n), None, None, None))
+        pc = np.empty(n.value, np.int32)
+        lo, hi = np.empty(n.value), np.empty(n.value)
+        _check(_lib.dc_scene_panels(self._h, C.byref(n), pc.ctypes.data_as(C.POINTER(C.c_int)),
+                                    _ptr(lo), _ptr(hi)))
+        return pc, lo, hi
+
+    def panel_tails(self):
+        """dc_panel_tails: the highest Legendre coefficient of every panel."""
+        n = len(self.panels()[0])
+        out = np.empty(n)
+        _check(_lib.dc_panel_tails(self._h, _ptr(out), _stream()))
+        return out
+
+    def refine(self, eps2, eps1=0.0, viewport=None, ratio=0.9, max_rounds=1, local=True,
+               tol=1e-10, max_iter=500, precond="block", raise_on_fail=False, **ev):
+        """dc_refine: returns (refined Scene or None, report dict, re-solved
+        curve flags of the last round [n_curves])."""
+        o = RefineOpts()
+        _lib.dc_default_refine_opts(C.byref(o))
+        o.eps2, o.eps1, o.ratio = float(eps2), float(eps1), float(ratio)
+        if viewport is not None:
+            for k in range(4):
+                o.viewport[k] = float(viewport[k])
+        o.max_rounds, o.local = int(max_rounds), 1 if local else 0
+        o.solve.tol, o.solve.max_iter, o.solve.matvec = tol, max_iter, eval_opts(**ev)
+        o.solve.precond = {"none": 0, "block": 1}[precond]
+        rep = RefineReport()
+        res = np.zeros(self.info()["n_curves"], np.uint8)
+        h = C.c_void_p()
+        allow = () if raise_on_fail else (DC_ERR_NOT_CONVERGED,)
+        rc = _check(_lib.dc_refine(self._h, C.byref(o), C.byref(h), C.byref(rep),
+                                   res.ctypes.data_as(C.POINTER(C.c_ubyte)), _stream()), allow)
+        out = Scene._wrap(h) if h.value else None
+        d = {k: getattr(rep, k) for k, _ in RefineReport._fields_}
+        d["rc"] = rc
+        return out, d, res.astype(bool)
 
     @classmethod
     def from_dict(cls, sc, **kw):

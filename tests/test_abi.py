@@ -62,3 +62,26 @@ def test_invalid_arguments_fail_cleanly_without_gpu():
     with pytest.raises(dcfmm.DcError) as e:
         dcfmm.Scene(flat, np.zeros((1, 2, 3)), np.zeros((1, 2, 3)))
     assert e.value.code == dcfmm.DC_ERR_INVALID
+
+
+def test_panel_lists_are_validated_without_gpu():
+    """dc_scene_create_panels rejects malformed panel lists on the host."""
+    import numpy as np
+    from paper_2311_14312_amd import dcfmm
+    assert ctypes.sizeof(dcfmm.RefineOpts) == 112
+    ctrl = np.zeros((2, 4, 2))
+    ctrl[:, :, 0] = [0, 0.3, 0.6, 1.0]
+    ctrl[1, :, 1] = 0.5
+    stops = np.zeros((2, 2, 3))
+    bad_lists = [
+        ([0, 2], [0.0, 0.0], [1.0, 1.0]),          # curve out of range
+        ([0, 0], [0.0, 0.4], [0.5, 1.0]),          # overlapping panels
+        ([0, 1], [0.5, 0.0], [0.5, 1.0]),          # empty panel
+        ([1, 0], [0.0, 0.0], [1.0, 1.0]),          # curves out of order
+        ([0, 1], [0.0, 0.0], [np.nan, 1.0]),       # NaN
+        ([0, 1], [-0.1, 0.0], [1.0, 1.0]),         # outside [0, 1]
+    ]
+    for pl in bad_lists:
+        with pytest.raises(dcfmm.DcError) as e:
+            dcfmm.Scene(ctrl, stops, stops, gl=4, segs=8, panel_list=pl)
+        assert e.value.code == dcfmm.DC_ERR_INVALID
