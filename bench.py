@@ -408,6 +408,45 @@ def serving_bench(args, torch, dcfmm):
     }
 
 
+def refine_bench(scene, cfg, solve_rep, torch):
+    """Adaptive subdivision (Sec. 7) on the solved 200-curve scene: an 8x
+    zoom around the panel with the largest Legendre tail, one round of
+    Alg. 7 cutting the quarter of the panels in view with the largest tails
+    (eps1 = 4 pixels of a 2048-px render of the zoom), re-solved globally
+    and locally from the same warm start; the analogue of the paper's
+    initial solve / global re-solve / local re-solve timing table."""
+    tails = scene.panel_tails()
+    pc, lo, hi = scene.panels()
+    g = cfg["gl"]
+    nodes = scene.nodes().reshape(-1, g, 2)
+    top = int(np.argmax(tails))
+    cx, cy = nodes[top].mean(axis=0)
+    side = 1.0 / 8.0
+    view = (float(cx), float(cy), side, side)
+    inview = (np.abs(nodes[..., 0] - cx) <= side / 2).any(axis=1) & \
+        (np.abs(nodes[..., 1] - cy) <= side / 2).any(axis=1)
+    eps2 = float(np.quantile(tails[inview], 0.75))
+    eps1 = 4.0 * side / 2048
+    ev = dict(method="fmm", precision="f64", p=cfg["p"])
+    out = {"viewport": view, "eps2": eps2, "eps1": eps1, "panels": int(len(pc)),
+           "panels_in_view": int(inview.sum()),
+           "initial_solve_s": solve_rep["seconds"], "initial_iters": max(solve_rep["iters"])}
+    imgs = {}
+    zoom = (view[0], view[1], side, side, 512, 512)
+    for name, local in (("global", False), ("local", True)):
+        torch.cuda.synchronize()
+        ref_, rep_, res = scene.refine(eps2, eps1=eps1, viewport=view, local=local,
+                                       tol=cfg["gmres_tol"], max_iter=1000, **ev)
+        out[name] = {k: rep_[k] for k in ("seconds", "label_seconds", "solve_seconds",
+                                          "iters", "panels_cut", "curves_resolved",
+                                          "rel_residual", "converged")}
+        imgs[name] = ref_.render(zoom, out_dtype=torch.float64, **ev).cpu().numpy()
+        ref_.close()
+        print("refine", name, out[name], flush=True)
+    out["zoom_field_local_vs_global"] = float(np.abs(imgs["local"] - imgs["global"]).max())
+    return out
+
+
 def serving_oracle_check(dcfmm, scenes, tuned, reqs):
     """The first request of every serving scene, served with the scene's
     options but with synthetic densities (the oracle cannot solve the large
@@ -453,6 +492,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-viewport batch")
     ap.add_argument("--batch-leaves", default="4,8")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
+    ap.add_argument("--no-refine", action="store_true",
+                    help="skip the adaptive subdivision timing")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the 1M-node 4096^2 precision workload")
     ap.add_argument("--precision-leaf", type=int, default=8)
@@ -664,6 +705,8 @@ def main():
             "pairs_per_s": cpu["value"] * cpu["S"],
             "full_frame_s_extrapolated": W * H / cpu["value"]},
     }
+    if not args.no_refine:
+        line["refine"] = refine_bench(scene, cfg, rep, torch)
     for scn, _, _ in scenes.values():
         scn.close()
     if not args.no_batch:

@@ -78,19 +78,38 @@ def test_c3_fp64_solve(gpu_lib):
         s.close()
 
 
+def _grid_errs(img, grid):
+    d = img[np.ix_(grid["rows"], grid["cols"])] - grid["vals"]
+    return float(np.abs(d).max()), float(np.sqrt(np.mean(d * d)))
+
+
 def test_c3_render_fp32_and_fp64(c3):
+    """The sampled pixels, and the rows of the 512 x 512 stride-8 grid
+    (pixel rows and columns 4, 12, ..., 4092) that the stored grid golden
+    holds (tests/golden/make_c3_grid512.py)."""
     import torch
     s, g = c3["s"], c3["g"]
+    path = os.path.join(HERE, "golden", "c3_grid512.npz")
+    grid = np.load(path) if os.path.exists(path) else None
     s.set_densities(scenegen.synthetic_densities(s.N))
     vp = CFG["viewport"]
     img32 = s.render(vp, method="fmm", precision="f32", p=12, tile_px=8).cpu().numpy()
     m32, r32 = _errs(img32, g)
+    g32 = _grid_errs(img32, grid) if grid is not None else None
     del img32
     img64 = s.render(vp, out_dtype=torch.float64, method="fmm", p=28, tile_px=8).cpu().numpy()
     m64, r64 = _errs(img64, g)
+    g64 = _grid_errs(img64, grid) if grid is not None else None
     print(f"C3 render vs oracle: FP32 max {m32:.3e} rms {r32:.3e}; FP64 p=28 max {m64:.3e} "
           f"rms {r64:.3e}", flush=True)
     assert m32 <= 1e-4
     # the FP64 bar (smooth densities: no near-cusp amplification of geometry
     # rounding here, measured 1.2e-11 at p = 28)
     assert m64 <= 1e-10
+    if grid is not None:
+        n = grid["vals"].shape[0] * grid["vals"].shape[1]
+        print(f"C3 stride-8 grid ({grid['vals'].shape[0]} of 512 rows, {n} px): FP32 max "
+              f"{g32[0]:.3e} rms {g32[1]:.3e}; FP64 max {g64[0]:.3e} rms {g64[1]:.3e}",
+              flush=True)
+        assert g32[0] <= 1e-4
+        assert g64[0] <= 1e-10
