@@ -862,8 +862,17 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
     const cpx<double>* loc = Lc + (size_t)own * (p + 1) * 3;
 
     for (int tbase = 0; tbase < n_targets; tbase += NT) {
-        const int tgt = tbase + tid;
-        const bool active = tgt < n_targets;
+        // lane tid: target t = tid % TP of this pass, group grp = tid / TP;
+        // the G groups split the pass's separated boxes and near pieces
+        // (a leaf holds a few nodes: one lane per target would leave most
+        // of the wave idle) and their sums are added across the groups
+        const int n_here = min(NT, n_targets - tbase);
+        int TP = 1;
+        while (TP < n_here) TP <<= 1;
+        const int G = NT / TP;
+        const int t = tid & (TP - 1), grp = tid / TP;
+        const int tgt = tbase + t;
+        const bool active = t < n_here;
         double x = cx, y = cy;
         int out_idx = 0;
         if (active) {
@@ -878,7 +887,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
         double accP[3] = {0, 0, 0};
         double acc64[3] = {0, 0, 0};
         // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
-        if (l >= 2) {
+        if (l >= 2 && grp == 0) {
             const cpx<double> z = {(x - cx) / r, (y - cy) / r};
             for (int ch = 0; ch < 3; ++ch) {
                 cpx<double> s = loc[p * 3 + ch];
@@ -946,7 +955,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             // target-from-outgoing (Eq. t-f-o), scaled:
             //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
             if (active) {
-                for (int u = 0; u < nW; ++u) {
+                for (int u = grp; u < nW; u += G) {
                     const int d = sh.W[u];
                     const int ld = tv.lvl[d];
                     const double rd = half_width(tv, ld);
@@ -992,7 +1001,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                 if (active) {
                     const int m = min(NT, total - pbase);
                     const float near2f = (float)a.near2;
-                    for (int j = 0; j < m; ++j) {
+                    for (int j = grp; j < m; j += G) {
                         const T dx = sh.px[j] - xr, dy = sh.py[j] - yr;
                         if (sizeof(T) == 4) {
                             const float tx = (float)sh.tx[j], ty = (float)sh.ty[j];
@@ -1033,10 +1042,14 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             __syncthreads();
             if (!more) break;
         }
-        if (active) {
-            for (int ch = 0; ch < 3; ++ch) {
-                a.y[(size_t)ch * a.N + out_idx] = (accE[ch] - accP[ch] - acc64[ch]) / kTwoPi;
-            }
+        // the groups' sums, added over the lanes that hold the same target
+        double tot[3];
+        for (int ch = 0; ch < 3; ++ch) {
+            tot[ch] = accE[ch] - accP[ch] - acc64[ch];
+            for (int off = TP; off < NT; off <<= 1) tot[ch] += __shfl_xor(tot[ch], off, NT);
+        }
+        if (active && grp == 0) {
+            for (int ch = 0; ch < 3; ++ch) a.y[(size_t)ch * a.N + out_idx] = tot[ch] / kTwoPi;
         }
         __syncthreads();
     }
