@@ -128,6 +128,9 @@ typedef struct {
     int n_cells, n_leaves, depth;  /* quadtree size */
     double root[3];                /* root box x0, y0, side */
     int solved;                    /* densities present */
+    long long table_pairs;         /* (node, piece) pairs in the solve's
+                                      near-field tables (0: none built) */
+    long long table_bytes;         /* device bytes they hold */
 } dc_scene_info;
 
 /* Fill opts / eval with the library defaults (P=16, g=16, s=80, b=64,
@@ -254,6 +257,21 @@ int dc_panel_tails(dc_scene s, double* tails_host, void* stream);
 int dc_refine(dc_scene s, const dc_refine_opts* o, dc_scene* out,
               dc_refine_report* rep, unsigned char* resolved_host,
               void* stream);
+
+/* Cached near-field tables of the solve (Sec. 6.4, the precomputed
+ * operators reused by every GMRES matvec).  The near field of the FP64
+ * operator depends on the geometry alone: on the first FP64 FMM operator
+ * application (dc_solve_densities, dc_apply_operator, ...) the library
+ * can store each target leaf's near pieces and separated boxes and the
+ * chord integrals of every (node, near piece) pair, so that later
+ * applications read them instead of walking the tree and evaluating the
+ * closed forms (same values; sums in another order).  mode = 1 (the
+ * default): built when they fit 16 GiB and the near field averages at
+ * least 256 pairs per node (large leaf capacities; sparser near fields
+ * evaluate as fast as the tables read); mode = 2: whenever they fit;
+ * mode = 0: never (as the FP32 operator).  Every call drops the tables
+ * built so far.  dc_scene_get_info reports their size.  Synchronous. */
+int dc_set_solve_tables(dc_scene s, int mode);
 
 /* Densities sigma at the nodes, host [3][N].  Synchronous. */
 int dc_get_densities(dc_scene s, double* sigma_host);

@@ -465,6 +465,29 @@ int dc_scene_get_info(dc_scene s, dc_scene_info* info) {
         info->root[1] = s->tree.Y0;
         info->root[2] = s->tree.side;
         info->solved = s->solved ? 1 : 0;
+        info->table_pairs = s->fmm ? s->fmm->tab_ok ? s->fmm->tab_pairs : 0 : 0;
+        info->table_bytes = s->fmm ? s->fmm->tab_ok ? (long long)s->fmm->tab_bytes : 0 : 0;
+    });
+}
+
+int dc_set_solve_tables(dc_scene s, int enable) {
+    return guarded([&] {
+        DC_REQUIRE(s && enable >= 0 && enable <= 2, "bad argument");
+        check_not_served(s);
+        DC_REQUIRE(s->fmm != nullptr, "scene has no FMM state");
+        FmmState& f = *s->fmm;
+        DC_HIP(hipDeviceSynchronize());  // no launch may still read the tables
+        f.tab_mode = enable;
+        f.tab_tried = false;
+        f.tab_ok = false;
+        f.tab_bytes = 0;
+        f.tab_pairs = 0;
+        f.tab_pair_off.release();
+        f.tab_piece_off.release();
+        f.tab_w_off.release();
+        f.tab_piece.release();
+        f.tab_w.release();
+        f.tab_val.release();
     });
 }
 

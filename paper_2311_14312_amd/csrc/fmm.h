@@ -126,6 +126,15 @@ struct FmmState {
     // (see m2l_table in fmm.hip).
     std::map<int, std::unique_ptr<DevBuf<double>>> m2l_tab;
     DevBuf<int> nsetS;
+    // Cached near-field tables of the FP64 solve (SolveTables in fmm.hip),
+    // built on the first FP64 operator application when they fit the budget.
+    int tab_mode = 1;  // 0 off, 1 when they pay (dense near fields), 2 whenever they fit
+    bool tab_tried = false, tab_ok = false;
+    size_t tab_bytes = 0;
+    long long tab_pairs = 0;
+    DevBuf<long long> tab_pair_off;
+    DevBuf<int> tab_piece_off, tab_w_off, tab_piece, tab_w;
+    DevBuf<double> tab_val;
     // Upward pass of the resident densities (render reuses it); gen counts
     // the density changes (a captured render graph records it).
     bool up_valid = false;

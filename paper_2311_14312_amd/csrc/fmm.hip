@@ -830,6 +830,14 @@ struct LeafArgs {
     unsigned char* hv_flag;  // per global leaf block: 0 k_tile, 1 queued, 2 done,
                              // 3 k_tile and 4 queued, with the lists kept in `lists`
     int* lists;              // kListInts per global leaf block (8-px tiles)
+    // cached near-field tables of the solve (SolveTables), by target leaf
+    int* tab_count;                // count pass: [leaf][2] near pieces, separated boxes
+    const long long* tab_pair_off; // [leaf] first (node, piece) pair
+    const int* tab_piece_off;      // [leaf + 1] first near piece
+    const int* tab_w_off;          // [leaf + 1] first separated box
+    int* tab_piece;                // near pieces, traversal order
+    int* tab_w;                    // separated boxes, traversal order
+    double* tab_val;               // [pair][2] (int ln, theta) of the chord integrals
 };
 
 template <typename T, int NT>
@@ -844,10 +852,17 @@ struct LeafShared {
 // Solve leaf pass (Alg. 8 at the source leaves): targets are the
 // collocation nodes of each leaf holding nodes; y[3][N] receives the
 // representation at the nodes (before the self-segment correction).
-template <typename T, int NT>
+// Modes: kLeafEval evaluates; kLeafCount (FP64) counts each leaf's near
+// pieces and separated boxes; kLeafFill (FP64) writes the leaf's lists and
+// the chord integrals of each (node, near piece) pair into the tables that
+// k_leaf_tab reads instead (Sec. 6.4's precomputed operators).
+enum { kLeafEval = 0, kLeafCount = 1, kLeafFill = 2 };
+
+template <typename T, int NT, int Mode = kLeafEval>
 __global__ void __launch_bounds__(NT)
 k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset) {
+    static_assert(Mode == kLeafEval || sizeof(T) == 8, "tables hold FP64 values");
     __shared__ LeafShared<T, NT> sh;
     const int tid = threadIdx.x;
     const int own = a.target_leaves[blockIdx.x];
@@ -886,8 +901,10 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
         // near-field sums are kept in FP64 (an FP64 add issues at the FP32 rate)
         double accP[3] = {0, 0, 0};
         double acc64[3] = {0, 0, 0};
+        // table positions of this pass's rounds (count and fill modes)
+        int runP = 0, runW = 0;
         // target-from-incoming (Eq. t-f-i): Re sum_k ((x-c)/r)^k Lt_k
-        if (l >= 2 && grp == 0) {
+        if (Mode == kLeafEval && l >= 2 && grp == 0) {
             const cpx<double> z = {(x - cx) / r, (y - cy) / r};
             for (int ch = 0; ch < 3; ++ch) {
                 cpx<double> s = loc[p * 3 + ch];
@@ -952,9 +969,14 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                 atomicAdd(a.stats + kStatM2P, na * nW);
                 atomicAdd(a.stats + kStatP2P, na * (unsigned long long)sh.Upre[nU]);
             }
+            if constexpr (Mode == kLeafFill) {
+                if (tbase == 0)
+                    for (int u = tid; u < nW; u += NT)
+                        a.tab_w[a.tab_w_off[blockIdx.x] + runW + u] = sh.W[u];
+            }
             // target-from-outgoing (Eq. t-f-o), scaled:
             //   Re[-log(x - c) Mt_0 + sum_{k>=1} (1/k) (r/(x-c))^k Mt_k]
-            if (active) {
+            if (Mode == kLeafEval && active) {
                 for (int u = grp; u < nW; u += G) {
                     const int d = sh.W[u];
                     const int ld = tv.lvl[d];
@@ -979,7 +1001,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             }
             // target-from-source (App. D) over the pieces of the near leaves
             const int total = sh.Upre[nU];
-            for (int pbase = 0; pbase < total; pbase += NT) {
+            for (int pbase = 0; pbase < total && Mode != kLeafCount; pbase += NT) {
                 __syncthreads();
                 const int g = pbase + tid;
                 if (g < total) {
@@ -996,8 +1018,25 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                     sh.len[tid] = (T)pv.len[e];
                     for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
                     sh.pid[tid] = sizeof(T) == 4 && pv.heavy[e] ? -1 - e : e;
+                    if (Mode == kLeafFill && tbase == 0)
+                        a.tab_piece[a.tab_piece_off[blockIdx.x] + runP + g] = e;
                 }
                 __syncthreads();
+                if constexpr (Mode == kLeafFill) {
+                    // the same closed form as the FP64 evaluation below
+                    const int m = min(NT, total - pbase);
+                    if (active)
+                        for (int j = grp; j < m; j += G) {
+                            const T dx = sh.px[j] - xr, dy = sh.py[j] - yr;
+                            T il, th;
+                            chord_log_theta<T>(dx, dy, sh.tx[j], sh.ty[j], sh.len[j], il, th);
+                            const size_t at = (size_t)a.tab_pair_off[blockIdx.x] +
+                                              (size_t)(runP + pbase + j) * n_targets + tgt;
+                            a.tab_val[2 * at] = il;
+                            a.tab_val[2 * at + 1] = th;
+                        }
+                    continue;
+                }
                 if (active) {
                     const int m = min(NT, total - pbase);
                     const float near2f = (float)a.near2;
@@ -1039,9 +1078,18 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                     }
                 }
             }
+            if constexpr (Mode == kLeafCount) {
+                if (tbase == 0 && tid == 0) {
+                    a.tab_count[2 * blockIdx.x] += total;
+                    a.tab_count[2 * blockIdx.x + 1] += nW;
+                }
+            }
+            runP += total;
+            runW += nW;
             __syncthreads();
             if (!more) break;
         }
+        if constexpr (Mode != kLeafEval) continue;
         // the groups' sums, added over the lanes that hold the same target
         double tot[3];
         for (int ch = 0; ch < 3; ++ch) {
@@ -1052,6 +1100,90 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
             for (int ch = 0; ch < 3; ++ch) a.y[(size_t)ch * a.N + out_idx] = tot[ch] / kTwoPi;
         }
         __syncthreads();
+    }
+}
+
+// Solve leaf pass from the cached tables (SolveTables): the leaf's
+// separated boxes and near pieces as stored by k_leaf's fill pass, and the
+// chord integrals of each (node, near piece) pair, so no traversal and no
+// closed form is evaluated; the lanes are grouped as in k_leaf.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_leaf_tab(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ M,
+           const cpx<double>* __restrict__ Lc) {
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int own = a.target_leaves[b];
+    const long long ti = tv.ix[own], tj = tv.iy[own];
+    const int base_pos = tv.nbeg[own];
+    const int n_targets = tv.nend[own] - base_pos;
+    const int l = tv.lvl[own];
+    const double r = half_width(tv, l);
+    double cx, cy;
+    center_of(tv, l, ti, tj, cx, cy);
+    const cpx<double>* loc = Lc + (size_t)own * (p + 1) * 3;
+    const int poff = a.tab_piece_off[b], np = a.tab_piece_off[b + 1] - poff;
+    const int woff = a.tab_w_off[b], nw = a.tab_w_off[b + 1] - woff;
+    const double* val = a.tab_val + 2 * (size_t)a.tab_pair_off[b];
+    for (int tbase = 0; tbase < n_targets; tbase += NT) {
+        const int n_here = min(NT, n_targets - tbase);
+        int TP = 1;
+        while (TP < n_here) TP <<= 1;
+        const int G = NT / TP;
+        const int t = tid & (TP - 1), grp = tid / TP;
+        const int tgt = tbase + t;
+        const bool active = t < n_here;
+        double x = cx, y = cy;
+        int out_idx = 0;
+        if (active) {
+            const int node = tv.node_perm[base_pos + tgt];
+            x = a.node_x[node];
+            y = a.node_y[node];
+            out_idx = node;
+        }
+        double acc[3] = {0, 0, 0};
+        if (active && l >= 2 && grp == 0) {
+            const cpx<double> z = {(x - cx) / r, (y - cy) / r};
+            for (int ch = 0; ch < 3; ++ch) {
+                cpx<double> s = loc[p * 3 + ch];
+                for (int kk = p - 1; kk >= 0; --kk) s = cadd(cmul(s, z), loc[kk * 3 + ch]);
+                acc[ch] += s.re;
+            }
+        }
+        if (active) {
+            for (int u = grp; u < nw; u += G) {
+                const int d = a.tab_w[woff + u];
+                const int ld = tv.lvl[d];
+                const double rd = half_width(tv, ld);
+                double dcx, dcy;
+                center_of(tv, ld, tv.ix[d], tv.iy[d], dcx, dcy);
+                const cpx<double> rel = {(x - dcx) / rd, (y - dcy) / rd};
+                const cpx<double> z = cinv(rel);
+                const cpx<double> lg = clog(rel);
+                const double lr = log(rd);
+                const cpx<double>* src = M + (size_t)d * (p + 1) * 3;
+                for (int ch = 0; ch < 3; ++ch) {
+                    cpx<double> s = cscale(src[p * 3 + ch], recip<double>(p));
+                    for (int kk = p - 1; kk >= 1; --kk)
+                        s = cadd(cmul(s, z), cscale(src[kk * 3 + ch], recip<double>(kk)));
+                    s = cmul(s, z);
+                    const cpx<double> m0 = src[ch];
+                    acc[ch] += s.re - ((lr + lg.re) * m0.re - lg.im * m0.im);
+                }
+            }
+            for (int j = grp; j < np; j += G) {
+                const int e = a.tab_piece[poff + j];
+                const size_t at = 2 * ((size_t)j * n_targets + tgt);
+                const double il = val[at], th = val[at + 1];
+                for (int ch = 0; ch < 3; ++ch)
+                    acc[ch] -= il * pv.w64[(size_t)ch * pv.n + e] +
+                               th * pv.w64[(size_t)(3 + ch) * pv.n + e];
+            }
+        }
+        for (int ch = 0; ch < 3; ++ch)
+            for (int off = TP; off < NT; off <<= 1) acc[ch] += __shfl_xor(acc[ch], off, NT);
+        if (active && grp == 0)
+            for (int ch = 0; ch < 3; ++ch) a.y[(size_t)ch * a.N + out_idx] = acc[ch] / kTwoPi;
     }
 }
 
@@ -2138,6 +2270,84 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
     }
 }
 
+// SolveTables: the near field of the solve depends on the geometry alone,
+// so the FP64 operator stores, once per scene, each target leaf's near
+// pieces and separated boxes and the chord integrals (ln, theta) of each
+// (node, near piece) pair (Sec. 6.4: the precomputed operators of every
+// GMRES matvec); k_leaf_tab then reads them instead of walking the tree and
+// evaluating the closed forms.  Built when the tables fit kSolveTableBytes
+// and, unless forced, when the near field averages at least
+// kTablePairsPerNode pairs per node: a sparse near field evaluates about as
+// fast as the tables read (measured on the 200-curve workload: 58 pairs per
+// node at leaf 4, solve 0.53 s without and 0.58 s with the build; 890 at
+// leaf 64, 1.56 s without and 1.37 s with).
+constexpr size_t kSolveTableBytes = 16ull << 30;
+constexpr long long kTablePairsPerNode = 256;
+
+void build_solve_tables(dc_scene_s& s, FmmState& f, LeafArgs a, int p,
+                        const cpx<double>* M, const cpx<double>* L, hipStream_t st) {
+    f.tab_tried = true;
+    const int nl = f.n_target_leaves;
+    if (nl <= 0) return;
+    const TreeView tv = tree_view(f);
+    const PieceView pv = piece_view(f);
+    DevBuf<int> count;
+    count.upload(std::vector<int>(2 * (size_t)nl, 0));
+    a.tab_count = count.p;
+    hipLaunchKernelGGL((k_leaf<double, kWave, kLeafCount>), dim3(nl), dim3(kWave), 0, st, tv, pv,
+                       a, p, M, L, f.nsetS.p);
+    DC_HIP(hipGetLastError());
+    std::vector<int> cnt(2 * (size_t)nl), nb(nl);
+    DC_HIP(hipMemcpyAsync(cnt.data(), count.p, cnt.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          st));
+    std::vector<int> tl(nl);
+    DC_HIP(hipMemcpyAsync(tl.data(), f.target_leaves.p, nl * sizeof(int), hipMemcpyDeviceToHost,
+                          st));
+    std::vector<int> nbeg(f.n_cells), nend(f.n_cells);
+    DC_HIP(hipMemcpyAsync(nbeg.data(), f.nbeg.p, nbeg.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          st));
+    DC_HIP(hipMemcpyAsync(nend.data(), f.nend.p, nend.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          st));
+    DC_HIP(hipStreamSynchronize(st));
+    std::vector<long long> pair_off(nl);
+    std::vector<int> piece_off(nl + 1), w_off(nl + 1);
+    long long pairs = 0, pieces = 0, ws = 0;
+    for (int b = 0; b < nl; ++b) {
+        pair_off[b] = pairs;
+        piece_off[b] = (int)pieces;
+        w_off[b] = (int)ws;
+        pairs += (long long)cnt[2 * b] * (nend[tl[b]] - nbeg[tl[b]]);
+        pieces += cnt[2 * b];
+        ws += cnt[2 * b + 1];
+        if (pieces >= (1LL << 31) || ws >= (1LL << 31)) return;  // indices would overflow
+    }
+    piece_off[nl] = (int)pieces;
+    w_off[nl] = (int)ws;
+    const size_t bytes = (size_t)pairs * 16 + (size_t)(pieces + ws) * 4 + (size_t)nl * 16;
+    if (bytes > kSolveTableBytes) return;
+    if (f.tab_mode == 1 && pairs < kTablePairsPerNode * (long long)s.geo.N) return;
+    f.tab_pair_off.upload(pair_off);
+    f.tab_piece_off.upload(piece_off);
+    f.tab_w_off.upload(w_off);
+    f.tab_piece.alloc(std::max<long long>(1, pieces));
+    f.tab_w.alloc(std::max<long long>(1, ws));
+    f.tab_val.alloc(2 * (size_t)std::max<long long>(1, pairs));
+    a.tab_count = nullptr;
+    a.tab_pair_off = f.tab_pair_off.p;
+    a.tab_piece_off = f.tab_piece_off.p;
+    a.tab_w_off = f.tab_w_off.p;
+    a.tab_piece = f.tab_piece.p;
+    a.tab_w = f.tab_w.p;
+    a.tab_val = f.tab_val.p;
+    hipLaunchKernelGGL((k_leaf<double, kWave, kLeafFill>), dim3(nl), dim3(kWave), 0, st, tv, pv,
+                       a, p, M, L, f.nsetS.p);
+    DC_HIP(hipGetLastError());
+    DC_HIP(hipStreamSynchronize(st));
+    f.tab_ok = true;
+    f.tab_bytes = bytes;
+    f.tab_pairs = pairs;
+}
+
 template <typename T>
 void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, double* y,
                    const dc_eval_opts& o, hipStream_t st) {
@@ -2171,7 +2381,19 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
     a.y = y;
     a.N = s.geo.N;
     a.near2 = o.near_fp64 * o.near_fp64;
-    if (f.n_target_leaves > 0) {
+    if (sizeof(T) == 8 && f.tab_mode != 0 && !f.tab_tried)
+        build_solve_tables(s, f, a, p, as_cpx(M), as_cpx(L), st);
+    if (f.n_target_leaves > 0 && sizeof(T) == 8 && f.tab_mode != 0 && f.tab_ok) {
+        a.tab_pair_off = f.tab_pair_off.p;
+        a.tab_piece_off = f.tab_piece_off.p;
+        a.tab_w_off = f.tab_w_off.p;
+        a.tab_piece = f.tab_piece.p;
+        a.tab_w = f.tab_w.p;
+        a.tab_val = f.tab_val.p;
+        hipLaunchKernelGGL((k_leaf_tab<kWave>), dim3(f.n_target_leaves), dim3(kWave), 0, st, tv,
+                           pv, a, p, as_cpx(M), as_cpx(L));
+        DC_HIP(hipGetLastError());
+    } else if (f.n_target_leaves > 0) {
         hipLaunchKernelGGL((k_leaf<T, kWave>), dim3(f.n_target_leaves), dim3(kWave), 0, st, tv, pv,
                            a, p, as_cpx(M), as_cpx(L), f.nsetS.p);
         DC_HIP(hipGetLastError());

@@ -52,7 +52,8 @@ class SolveReport(C.Structure):
 class SceneInfo(C.Structure):
     _fields_ = [("n_curves", C.c_int), ("N", C.c_int), ("S", C.c_int),
                 ("n_pieces", C.c_int), ("n_cells", C.c_int), ("n_leaves", C.c_int),
-                ("depth", C.c_int), ("root", C.c_double * 3), ("solved", C.c_int)]
+                ("depth", C.c_int), ("root", C.c_double * 3), ("solved", C.c_int),
+                ("table_pairs", C.c_longlong), ("table_bytes", C.c_longlong)]
 
 
 class WorkCounts(C.Structure):
@@ -176,6 +177,7 @@ def _load():
         "dc_default_refine_opts": (None, [C.POINTER(RefineOpts)]),
         "dc_refine": (I, [P, C.POINTER(RefineOpts), C.POINTER(P), C.POINTER(RefineReport),
                           C.POINTER(C.c_ubyte), V]),
+        "dc_set_solve_tables": (I, [P, I]),
         "dc_scene_destroy": (None, [P]),
         "dc_scene_get_info": (I, [P, C.POINTER(SceneInfo)]),
         "dc_get_nodes": (I, [P, dp]),
@@ -305,6 +307,10 @@ class Scene:
         _check(_lib.dc_scene_panels(self._h, C.byref(n), pc.ctypes.data_as(C.POINTER(C.c_int)),
                                     _ptr(lo), _ptr(hi)))
         return pc, lo, hi
+
+    def set_solve_tables(self, mode="auto"):
+        """dc_set_solve_tables: "auto" (default), "always" or "off"."""
+        _check(_lib.dc_set_solve_tables(self._h, {"off": 0, "auto": 1, "always": 2}[mode]))
 
     def panel_tails(self):
         """dc_panel_tails: the highest Legendre coefficient of every panel."""
