@@ -1369,8 +1369,15 @@ k_near_all(TreeView tv, const VpLevel* __restrict__ lev, int n_ent, int total,
 // Own incoming terms of every non-root target box (one wave each): C[b] =
 // M2L + P2L from its parent's near set; quiet[b] = 1 (and C[b] unwritten)
 // when that near set holds no pieces.
+// Waves per SIMD the kernel is compiled for (its register budget): in
+// FP32, 5 (96 VGPRs, with a few spills) measured 17 us faster than 4 (115
+// VGPRs) on the 2048^2 render, and 6 (80 VGPRs) slower; in FP64 4 (127
+// VGPRs): with 5 the spills cost more than the extra waves win.
+template <typename T>
+constexpr int kContribWaves = sizeof(T) == 4 ? 5 : 4;
+
 template <typename T, bool Count>
-__global__ void __launch_bounds__(kWave, 4)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kContribWaves<T>)))
 k_down_contrib(TreeView tv, PieceView pv, int p, const cpx<double>* __restrict__ M,
                cpx<double>* __restrict__ C, int* __restrict__ nset,
                const cpx<double>* __restrict__ Ttab, const VpLevel* __restrict__ lev, int n_ent,
@@ -1470,10 +1477,11 @@ __device__ __noinline__ Rgb pair_fp64(const double* __restrict__ x0, const doubl
 // queued by k_tile_scan and evaluated by k_tile_big (on a second stream,
 // concurrently with k_tile), whose blocks split one tile's near field over
 // kBigSplit<T> waves.
-// Launch-bound occupancy argument of the one-wave tile kernel (register
-// budget; measured best).
+// Waves per SIMD the one-wave tile kernel is compiled for (its register
+// budget, measured best): 4 (FP32 116 VGPRs; FP64 128).  5 in FP32 (96
+// VGPRs, 18 spilled) measured a slower leaf pass (0.352 against 0.344 ms).
 template <typename T>
-constexpr int kTileWaves = sizeof(T) == 4 ? 8 : 4;
+constexpr int kTileWaves = 4;
 template <typename T>
 constexpr int kHeavyPieces = sizeof(T) == 4 ? 128 : 32;
 template <typename T>
@@ -1877,7 +1885,8 @@ __device__ void tile_body(TileShared<T, NT>& sh, const TreeView& tv, const Piece
 
 // Hardware dispatch places block b on XCD b % 8 (see xcd_block).
 template <typename T, int NT, int PX, int S, bool Count>
-__global__ void __launch_bounds__(NT, NT == kWave ? kTileWaves<T> : 4)
+__global__ void __launch_bounds__(NT)
+    __attribute__((amdgpu_waves_per_eu(NT == kWave ? kTileWaves<T> : 4)))
 k_tile(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restrict__ Ms,
        const cpx<double>* __restrict__ Lc, const int* __restrict__ nset,
        const int2* __restrict__ owner) {
