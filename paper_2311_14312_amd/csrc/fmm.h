@@ -126,6 +126,10 @@ struct FmmState {
     // (see m2l_table in fmm.hip).
     std::map<int, std::unique_ptr<DevBuf<double>>> m2l_tab;
     DevBuf<int> nsetS;
+    // The solve's split downward pass: own incoming terms and quiet flags
+    // of every cell.
+    DevBuf<double> C64;
+    DevBuf<unsigned char> quietS;
     // Cached near-field tables of the FP64 solve (SolveTables in fmm.hip),
     // built on the first FP64 operator application when they fit the budget.
     int tab_mode = 1;  // 0 off, 1 when they pay (dense near fields), 2 whenever they fit

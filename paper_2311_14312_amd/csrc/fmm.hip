@@ -1441,6 +1441,89 @@ k_down_l2l(DownLevel dl, int p, const cpx<double>* __restrict__ C, cpx<double>* 
     for (int ch = 0; ch < 3; ++ch) out[ch] = {(double)acc[ch].re, (double)acc[ch].im};
 }
 
+// The solve's downward pass split the same way, over the source cells
+// (the targets are the cells themselves): near sets of every cell at once,
+// every cell's own incoming terms at once, then one light L2L launch per
+// level.  The solve's cells are never quiet in practice (a cell's parent's
+// near set holds the cell itself); a quiet one would get its parent's
+// translated expansion alone.
+
+// Near set of cell c (levels >= 1), position s: as k_near_all.
+__global__ void __launch_bounds__(256)
+k_near_cells(TreeView tv, int first_cell, int n, int* __restrict__ nset) {
+    const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= 9LL * n) return;
+    const int c = first_cell + (int)(gi / 9), s = (int)(gi % 9);
+    const int l = tv.lvl[c];
+    const long long px = tv.ix[c] + (s % 3) - 1, py = tv.iy[c] + (s / 3) - 1;
+    const long long lim = 1LL << l;
+    int b = -1;
+    if (px >= 0 && py >= 0 && px < lim && py < lim) {
+        b = 0;
+        for (int d = 0; d < l; ++d) {
+            const int ch = tv.child[b];
+            if (ch < 0) break;  // a coarser leaf covers the cell
+            const int sh = l - d - 1;
+            const int q = (int)((px >> sh) & 1) + 2 * (int)((py >> sh) & 1);
+            if (!((tv.cmask[b] >> q) & 1)) {
+                b = -1;  // that child holds no pieces
+                break;
+            }
+            b = ch + q;
+        }
+        if (b >= 0 && tv.npc[b] == 0) b = -1;
+    }
+    nset[(size_t)c * 9 + s] = b;
+}
+
+// Own incoming terms C[c] (M2L + P2L from the parent's near set) of every
+// cell at levels >= 1, one wave each; quiet[c] = 1 (C[c] unwritten) when
+// that near set holds no pieces.
+template <typename T>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kContribWaves<T>)))
+k_down_contrib_cells(TreeView tv, PieceView pv, int p, const cpx<double>* __restrict__ M,
+                     cpx<double>* __restrict__ C, int* __restrict__ nset,
+                     const cpx<double>* __restrict__ Ttab, int first_cell,
+                     unsigned char* __restrict__ quiet) {
+    __shared__ DownShared<T, 1> sh;
+    const int lane = threadIdx.x;
+    const int c = first_cell + xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const bool q = down_body<T, false, 1, true>(sh, tv, pv, tv.lvl[c], tv.ix[c], tv.iy[c], c,
+                                                tv.parent[c], p, M, C, nset, Ttab, nullptr,
+                                                nullptr, lane);
+    if (lane == 0) quiet[c] = q ? 1 : 0;
+}
+
+// One level of the solve's L2L (one wave per cell, lane k = coefficient
+// k): L[c] = C[c] + L2L(L[parent]) in FP64 (Eq. i-f-i, scaled).
+__global__ void __launch_bounds__(kWave)
+k_l2l_cells(TreeView tv, int first_cell, int p, const cpx<double>* __restrict__ C,
+            cpx<double>* __restrict__ L, const unsigned char* __restrict__ quiet) {
+    __shared__ cpx<double> pl[3 * (DC_P_MAX + 1)];
+    const int c = first_cell + blockIdx.x;
+    const int par = tv.parent[c];
+    const int lane = threadIdx.x, P1 = p + 1;
+    for (int i = lane; i < 3 * P1; i += kWave) pl[i] = L[(size_t)par * 3 * P1 + i];
+    __syncthreads();
+    const int k = lane;
+    if (k > p) return;
+    cpx<double> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    if (!quiet[c])
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = C[((size_t)c * P1 + k) * 3 + ch];
+    const cpx<double> z0 = {(tv.ix[c] & 1) ? 0.5 : -0.5, (tv.iy[c] & 1) ? 0.5 : -0.5};
+    cpx<double> pw = {1, 0};
+    double binom = 1;
+    const double sc = ldexp(1.0, -k);
+    for (int m = k; m <= p; ++m) {
+        const cpx<double> f = cscale(pw, binom * sc);
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, pl[m * 3 + ch]));
+        binom = binom * (double)(m + 1) * recip<double>(m + 1 - k);
+        pw = cmul(pw, z0);
+    }
+    cpx<double>* out = L + ((size_t)c * P1 + k) * 3;
+    for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+}
+
 struct Rgb {
     double v[3];
 };
@@ -2372,16 +2455,26 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
     const cpx<double>* Ttab = m2l_table_dev(f, p);
     hipLaunchKernelGGL(k_init_root<double>, dim3(1), dim3(kWave), 0, st, p, as_cpx(L), f.nsetS.p);
     DC_HIP(hipGetLastError());
-    for (int l = 1; l <= f.depth; ++l) {
-        DownLevel dl{};
-        dl.solve = 1;
-        dl.l = l;
-        dl.first = f.level_start[l];
-        const int cnt = f.level_start[l + 1] - dl.first;
-        if (cnt <= 0) continue;
-        hipLaunchKernelGGL((k_down<double, false>), dim3(cnt), dim3(kWave), 0, st, tv, pv, dl, p,
-                           as_cpx(M), as_cpx(L), f.nsetS.p, Ttab, (int2*)nullptr);
+    // split downward pass over the cells of levels >= 1 (see k_near_cells)
+    const int c1 = f.depth >= 1 ? f.level_start[1] : f.n_cells;
+    const int nc = f.n_cells - c1;
+    if (nc > 0) {
+        f.C64.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
+        f.quietS.alloc(f.n_cells);
+        hipLaunchKernelGGL(k_near_cells, dim3((unsigned)((9LL * nc + 255) / 256)), dim3(256), 0, st,
+                           tv, c1, nc, f.nsetS.p);
         DC_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_down_contrib_cells<double>), dim3(nc), dim3(kWave), 0, st, tv, pv, p,
+                           as_cpx(M), as_cpx(f.C64), f.nsetS.p, Ttab, c1, f.quietS.p);
+        DC_HIP(hipGetLastError());
+        for (int l = 1; l <= f.depth; ++l) {
+            const int first = f.level_start[l];
+            const int cnt = f.level_start[l + 1] - first;
+            if (cnt <= 0) continue;
+            hipLaunchKernelGGL(k_l2l_cells, dim3(cnt), dim3(kWave), 0, st, tv, first, p,
+                               as_cpx(f.C64), as_cpx(L), f.quietS.p);
+            DC_HIP(hipGetLastError());
+        }
     }
     LeafArgs a{};
     a.target_leaves = f.target_leaves.p;

@@ -68,7 +68,8 @@ void launch_mask_merge(int N, const int* flag, const double* x, const double* y,
 
 // ------------------------------------------------- block-Jacobi preconditioner
 // Diagonal blocks: runs of consecutive panels of one curve (every panel of a
-// curve when they fit), row-major, one after another in D.  Device arrays.
+// curve when they fit), one after another in D: row-major as assembled,
+// transposed in place once inverted (launch_invert_blocks).  Device arrays.
 struct BlocksView {
     int n_blocks, max_panels;  // blocks; most panels in one block
     const int* panel_blk;      // [n_panels] block of each panel

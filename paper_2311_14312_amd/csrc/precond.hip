@@ -136,20 +136,55 @@ k_gauss_jordan(BlocksView bv, double* __restrict__ D, int* __restrict__ perm_all
 }
 
 // y[ch][i] = sum_j Dinv[c][iloc][j] x[ch][c n + j]
+// Each inverted block transposed in place (one block per workgroup), so
+// that k_block_apply's threads, one per row, read consecutive addresses.
 __global__ void __launch_bounds__(kNT)
-k_block_apply(int N, int g, BlocksView bv, const double* __restrict__ Dinv,
+k_transpose_blocks(BlocksView bv, double* __restrict__ D) {
+    const int n = bv.n[blockIdx.x];
+    double* a = D + bv.doff[blockIdx.x];
+    for (long long q = threadIdx.x; q < (long long)n * n; q += kNT) {
+        const int i = (int)(q / n), j = (int)(q - (long long)i * n);
+        if (i < j) {
+            const double t = a[(size_t)i * n + j];
+            a[(size_t)i * n + j] = a[(size_t)j * n + i];
+            a[(size_t)j * n + i] = t;
+        }
+    }
+}
+
+// y[ch] = blockdiag(Dinv) x[ch] for the three channels: a workgroup takes
+// 64 rows, its four waves a quarter of each row's block each, and the
+// quarters are added through LDS.  DinvT holds each block transposed
+// (column j of the block's inverse at DinvT + doff + j n), so a wave's
+// lanes, one per row, read consecutive addresses.
+constexpr int kApplyRows = 64, kApplySplit = kNT / kApplyRows;
+
+__global__ void __launch_bounds__(kNT)
+k_block_apply(int N, int g, BlocksView bv, const double* __restrict__ DinvT,
               const double* __restrict__ x, double* __restrict__ y) {
-    const int i = blockIdx.x * kNT + threadIdx.x;
-    const int ch = blockIdx.y;
-    if (i >= N) return;
-    const int b = bv.panel_blk[i / g];
-    const int node0 = bv.node0[b], n = bv.n[b];
-    const int iloc = i - node0;
-    const double* row = Dinv + bv.doff[b] + (size_t)iloc * n;
-    const double* xv = x + (size_t)ch * N + (size_t)node0;
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) acc += row[j] * xv[j];
-    y[(size_t)ch * N + i] = acc;
+    __shared__ double part[3][kApplySplit][kApplyRows];
+    const int r = threadIdx.x % kApplyRows, c = threadIdx.x / kApplyRows;
+    const int i = blockIdx.x * kApplyRows + r;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i < N) {
+        const int b = bv.panel_blk[i / g];
+        const int node0 = bv.node0[b], n = bv.n[b];
+        const double* col = DinvT + bv.doff[b] + (i - node0);
+        const double* x0 = x + (size_t)node0;
+        const int j0 = (c * n) / kApplySplit, j1 = ((c + 1) * n) / kApplySplit;
+        for (int j = j0; j < j1; ++j) {
+            const double d = col[(size_t)j * n];
+            for (int ch = 0; ch < 3; ++ch) acc[ch] += d * x0[(size_t)ch * N + j];
+        }
+    }
+    for (int ch = 0; ch < 3; ++ch) part[ch][c][r] = acc[ch];
+    __syncthreads();
+    if (c == 0 && i < N)
+        for (int ch = 0; ch < 3; ++ch) {
+            double v = part[ch][0][r];
+            for (int q = 1; q < kApplySplit; ++q) v += part[ch][q][r];
+            y[(size_t)ch * N + i] = v;
+        }
 }
 
 }  // namespace
@@ -170,12 +205,14 @@ void launch_invert_blocks(const BlocksView& bv, double* D, int* perm, int* singu
     hipLaunchKernelGGL(k_gauss_jordan, dim3(bv.n_blocks), dim3(kNT), 0, st, bv, D, perm,
                        singular);
     DC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_transpose_blocks, dim3(bv.n_blocks), dim3(kNT), 0, st, bv, D);
+    DC_HIP(hipGetLastError());
 }
 
 void launch_block_apply(int N, int g, const BlocksView& bv, const double* Dinv, const double* x,
                         double* y, hipStream_t st) {
-    hipLaunchKernelGGL(k_block_apply, dim3((N + kNT - 1) / kNT, 3), dim3(kNT), 0, st, N, g, bv,
-                       Dinv, x, y);
+    hipLaunchKernelGGL(k_block_apply, dim3((N + kApplyRows - 1) / kApplyRows), dim3(kNT), 0, st,
+                       N, g, bv, Dinv, x, y);
     DC_HIP(hipGetLastError());
 }
 
