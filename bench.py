@@ -486,6 +486,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--p64", type=int, default=0,
                     help="expansion order of the FP64 path (0: dc_autotune to 1e-10)")
+    ap.add_argument("--p32", type=int, default=0,
+                    help="fixed FP32 order (skips the autotuner; first tile size)")
     ap.add_argument("--tiles", default="8,16")
     ap.add_argument("--leaves", default="4,8,16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
@@ -581,13 +583,22 @@ def main():
     for leaf in leaves:
         scn, rep, t_create = make_scene(leaf)
         scenes[leaf] = (scn, rep, t_create)
-        tr = scn.autotune([vp], target_err=5e-5, precision="f32", p_min=8, p_max=24,
-                          p_step=2, tiles=tiles, samples=2048, timing_reps=5)
-        ev = tr["eval"]
-        ms, _ = timed(scn, ev, 5, 2, torch.float32)
-        tune.append({"leaf": leaf, "tile": ev["tile_px"], "p": ev["p"], "ms": ms,
-                     "tuner_err": tr["err"], "tuner_samples": tr["n_samples"],
-                     "per_tile": {"tiles": tr["tiles"], "p": tr["tile_p"], "ms": tr["tile_ms"]}})
+        if args.p32 > 0:
+            # a fixed order and the first tile size (profiling runs: only the
+            # timed configuration's kernels are launched)
+            ev = dict(method="fmm", precision="f32", p=args.p32, tile_px=tiles[0])
+            ms, _ = timed(scn, ev, 5, 2, torch.float32)
+            tune.append({"leaf": leaf, "tile": tiles[0], "p": args.p32, "ms": ms,
+                         "tuner_err": None, "fixed": True})
+        else:
+            tr = scn.autotune([vp], target_err=5e-5, precision="f32", p_min=8, p_max=24,
+                              p_step=2, tiles=tiles, samples=2048, timing_reps=5)
+            ev = tr["eval"]
+            ms, _ = timed(scn, ev, 5, 2, torch.float32)
+            tune.append({"leaf": leaf, "tile": ev["tile_px"], "p": ev["p"], "ms": ms,
+                         "tuner_err": tr["err"], "tuner_samples": tr["n_samples"],
+                         "per_tile": {"tiles": tr["tiles"], "p": tr["tile_p"],
+                                      "ms": tr["tile_ms"]}})
         print("autotune", tune[-1], flush=True)
         if best is None or ms < best["ms"]:
             best = dict(tune[-1])
@@ -598,10 +609,14 @@ def main():
     p32, tile, leaf = best["p"], best["tile"], best["leaf"]
     # the FP64 comparator's order: dc_autotune against the same direct sum
     # with the FP64 bar (1e-10) as target
-    tr64 = scene.autotune([vp], target_err=1e-10, precision="f64", p_min=20, p_max=40,
-                          p_step=4, tiles=(tile,), samples=1024, timing_reps=1)
-    p64 = tr64["eval"]["p"] if args.p64 <= 0 else args.p64
-    print(f"FP64 order {p64} (tuner error {tr64['err']:.2e})", flush=True)
+    if args.p64 > 0:
+        tr64 = {"err": None}
+        p64 = args.p64
+    else:
+        tr64 = scene.autotune([vp], target_err=1e-10, precision="f64", p_min=20, p_max=40,
+                              p_step=4, tiles=(tile,), samples=1024, timing_reps=1)
+        p64 = tr64["eval"]["p"]
+    print(f"FP64 order {p64} (tuner error {tr64['err']})", flush=True)
 
     ev32 = dict(method="fmm", precision="f32", p=p32, tile_px=tile)
     ev64 = dict(method="fmm", precision="f64", p=p64, tile_px=tile)
