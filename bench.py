@@ -34,10 +34,11 @@ PEAK_FP64 = 78.6e12
 FLOP_P2P = 117.0
 
 
-def measured_traffic(kernel, config):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when it covers another kernel or configuration, or the
-    kernel source has changed since the counters were taken."""
+def measured_traffic(kernel, config, key="hbm_bytes_per_launch"):
+    """A per-launch figure of `kernel` (HBM bytes, or VALU wave instructions)
+    from the committed rocprofv3 counter summary, or None when it covers
+    another kernel or configuration, or the kernel source has changed since
+    the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_tile_c2_2048_traffic.txt")
     src = os.path.join(ROOT, "paper_2311_14312_amd", "csrc", "fmm.hip")
@@ -50,9 +51,23 @@ def measured_traffic(kernel, config):
             kv[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if kv.get("kernel") != kernel or kv.get("config") != config or \
-            kv.get("source_sha256") != sha:
+            kv.get("source_sha256") != sha or key not in kv:
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    return float(kv[key])
+
+
+def valu_issue(kernel, config, kernel_ms):
+    """The pass's VALU wave instructions (SQ_INSTS_VALU, committed counter
+    summary) per second against the issue peak, 256 CUs x 4 SIMDs x
+    2.4 GHz / 4 cycles per wave64 instruction: how close the ALU-bound pass
+    runs to instruction issue, independent of the flop weights."""
+    n = measured_traffic(kernel, config, "valu_wave_instructions_per_launch")
+    if n is None:
+        return None
+    peak = 256 * 4 * 2.4e9 / 4
+    rate = n / (kernel_ms * 1e-3)
+    return {"wave_instructions": n, "achieved_per_s": rate, "peak_per_s": peak,
+            "frac": rate / peak}
 
 
 def flops_l2p(p):
@@ -703,7 +718,9 @@ def main():
                      "traffic_unit": "bytes/launch",
                      "kernel": kernel_name,
                      "kernel_ms": leaf_ms,
-                     "flop_eq_per_launch": fl},
+                     "flop_eq_per_launch": fl,
+                     "valu_issue": valu_issue(kernel_name, f"leaf {leaf}, tile {tile}, p {p32}",
+                                              leaf_ms)},
         "phases_ms": {k: v / max(1, tm["calls"]) for k, v in tm.items() if k.endswith("_ms")},
         "work": counts,
         "solve": {"seconds": rep["seconds"], "iters": rep["iters"], "precond": "block",
