@@ -1211,9 +1211,19 @@ struct TileShared {
     T py[NT], tx[NT], ty[NT], len[NT];
     T w[6][NT];
     int pid[NT];
+    unsigned char far[NT];  // FP32: the piece is well separated from the whole tile
     int U[kUCap], Upre[kUCap + 1], W[kWCap], Q[kQCap];
     int nU, nW, nQ, heavy;
 };
+
+// A piece whose chord lies at least kGaussSep chord lengths from every
+// point of a tile's box is integrated at the tile's pixels by the two-point
+// Gauss-Legendre rule (FP32 path): for r >= kGaussSep la the rule's error
+// is below la (la/r)^4 / 720 for the single layer and 3e-2 (la/r)^5 for the
+// double layer, far under FP32 rounding of the closed form's terms.
+constexpr float kGaussSep = 10.0f;
+constexpr float kGaussA = 0.21132486540518713f;  // (1 - 1/sqrt(3)) / 2
+constexpr float kGaussB = 0.78867513459481287f;  // (1 + 1/sqrt(3)) / 2
 
 // Per-wave LDS buffers of 3 (p + 1) expansion coefficients (L2P and M2P),
 // in the dynamic shared memory of the tile kernels (tile_coef_bytes).
@@ -1723,6 +1733,8 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
     constexpr int G = NT / S;
     const int gid = tid / G, gt = tid - gid * G;
     const T* wts = weights<T>(pv);
+    // half width of the tile's box (pixel centres lie inside it)
+    const float rtile = (float)half_width(tv, l);
     if (kl.on) {
         // the lists of the only round, as k_tile_scan's tile_round left them
         const int nU = kl.nU, nW = kl.nW;
@@ -1806,7 +1818,19 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                 sh.ty[tid] = (T)pv.ty[e];
                 sh.len[tid] = (T)pv.len[e];
                 for (int c6 = 0; c6 < 6; ++c6) sh.w[c6][tid] = wts[(size_t)c6 * pv.n + e];
-                sh.pid[tid] = sizeof(T) == 4 && pv.heavy[e] ? -1 - e : e;
+                const bool hv = sizeof(T) == 4 && pv.heavy[e];
+                sh.pid[tid] = hv ? -1 - e : e;
+                if constexpr (sizeof(T) == 4) {
+                    // distance from the chord's midpoint to the tile's box,
+                    // less half the chord, against kGaussSep chord lengths
+                    const float la = (float)sh.len[tid];
+                    const float mx = (float)sh.px[tid] + 0.5f * la * (float)sh.tx[tid];
+                    const float my = (float)sh.py[tid] + 0.5f * la * (float)sh.ty[tid];
+                    const float ex = fmaxf(fabsf(mx) - rtile, 0.f);
+                    const float ey = fmaxf(fabsf(my) - rtile, 0.f);
+                    const float sep = (kGaussSep + 0.5f) * la;
+                    sh.far[tid] = !hv && ex * ex + ey * ey >= sep * sep ? 1 : 0;
+                }
             }
             __syncthreads();
             const int m = min(NT, total - pbase);
@@ -1816,6 +1840,26 @@ __device__ void tile_near(TileShared<T, NT>& sh, const TreeView& tv, const Piece
                 const T px0 = sh.px[j], py0 = sh.py[j];
                 const T tx = sh.tx[j], ty = sh.ty[j], la = sh.len[j];
                 const int pid = sh.pid[j];
+                if (sizeof(T) == 4 && sh.far[j]) {
+                    // two-point Gauss-Legendre on the chord (a well-separated
+                    // piece: uniform over the wave, no near-singular pairs)
+                    const float fla = (float)la;
+                    float w6[6];
+                    for (int c6 = 0; c6 < 6; ++c6) w6[c6] = (float)sh.w[c6][j];
+                    for (int q = 0; q < PX; ++q) {
+                        const float dx = (float)(px0 - tt.xr[q]), dy = (float)(py0 - tt.yr[q]);
+                        const float xi1 = dx * (float)tx + dy * (float)ty;
+                        const float h = dy * (float)tx - dx * (float)ty;
+                        const float xa = xi1 + kGaussA * fla, xb = xi1 + kGaussB * fla;
+                        const float ra = xa * xa + h * h, rb = xb * xb + h * h;
+                        const float il = 0.25f * fla * fast_ln(ra * rb);
+                        const float th = 0.5f * fla * h *
+                                         (__builtin_amdgcn_rcpf(ra) + __builtin_amdgcn_rcpf(rb));
+                        for (int ch = 0; ch < 3; ++ch)
+                            acc[q][ch] -= (double)(il * w6[ch] + th * w6[3 + ch]);
+                    }
+                    continue;
+                }
                 if (sizeof(T) == 8) {
                     for (int q = 0; q < PX; ++q) {
                         T il, th;
