@@ -1403,35 +1403,43 @@ k_down_contrib(TreeView tv, PieceView pv, int p, const cpx<double>* __restrict__
     if (lane == 0) quiet[b] = q ? 1 : 0;
 }
 
-// One level of the split pass (one wave per box, lane k = coefficient k):
-// L[b] = C[b] + L2L(L[parent]) (Eq. i-f-i, scaled; the same recurrence as
-// down_body's) with owner[b] = (b, l); a quiet box records its parent's
-// owner instead (the nearest ancestor that is not quiet).
+// One level of the split pass (G = 64 / (p + 1) boxes per wave, lane k of
+// a group = coefficient k): L[b] = C[b] + L2L(L[parent]) (Eq. i-f-i,
+// scaled; the same recurrence as down_body's) with owner[b] = (b, l); a
+// quiet box records its parent's owner instead (the nearest ancestor that
+// is not quiet).
 template <typename T>
 __global__ void __launch_bounds__(kWave)
-k_down_l2l(DownLevel dl, int p, const cpx<double>* __restrict__ C, cpx<double>* __restrict__ L,
-           const unsigned char* __restrict__ quiet, int2* __restrict__ owner) {
-    __shared__ cpx<T> pl[3 * (DC_P_MAX + 1)];
-    const VpLevel& e = find_entry(dl.vl, dl.nvl, (int)blockIdx.x);
-    const int bb = (int)blockIdx.x - e.first_block;
-    const long long ti = e.i0 + bb % e.wl, tj = e.j0 + bb / e.wl;
-    const int own = e.off + bb;
-    const int par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
-    const int lane = threadIdx.x;
-    const int2 po = owner[par];
-    if (po.x != par || quiet[own]) {
-        if (lane == 0) owner[own] = po;
-        return;
+k_down_l2l(DownLevel dl, int n_boxes, int p, const cpx<double>* __restrict__ C,
+           cpx<double>* __restrict__ L, const unsigned char* __restrict__ quiet,
+           int2* __restrict__ owner) {
+    __shared__ cpx<T> pl[3 * kWave];  // the groups' parent expansions
+    const int lane = threadIdx.x, P1 = p + 1;
+    const int G = kWave / P1;
+    const int g = lane / P1, k = lane - g * P1;
+    const int bi = (int)blockIdx.x * G + g;
+    long long ti = 0, tj = 0;
+    int own = 0, par = 0;
+    bool work = false;
+    if (g < G && bi < n_boxes) {
+        const VpLevel& e = find_entry(dl.vl, dl.nvl, bi);
+        const int bb = bi - e.first_block;
+        ti = e.i0 + bb % e.wl;
+        tj = e.j0 + bb / e.wl;
+        own = e.off + bb;
+        par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
+        const int2 po = owner[par];
+        work = po.x == par && !quiet[own];
+        if (k == 0) owner[own] = work ? make_int2(own, dl.l) : po;
     }
-    if (lane == 0) owner[own] = make_int2(own, dl.l);
-    const int P1 = p + 1;
-    for (int i = lane; i < 3 * P1; i += kWave) {
-        const cpx<double> v = L[(size_t)par * 3 * P1 + i];
-        pl[i] = to_c<T>(v.re, v.im);
-    }
+    cpx<T>* src = pl + g * 3 * P1;
+    if (work)
+        for (int i = k; i < 3 * P1; i += P1) {
+            const cpx<double> v = L[(size_t)par * 3 * P1 + i];
+            src[i] = to_c<T>(v.re, v.im);
+        }
     __syncthreads();
-    const int k = lane;
-    if (k > p) return;
+    if (!work) return;
     cpx<T> acc[3];
     for (int ch = 0; ch < 3; ++ch) {
         const cpx<double> c = C[((size_t)own * P1 + k) * 3 + ch];
@@ -1443,7 +1451,7 @@ k_down_l2l(DownLevel dl, int p, const cpx<double>* __restrict__ C, cpx<double>* 
     const T sc = (T)ldexp(1.0, -k);
     for (int m = k; m <= p; ++m) {
         const cpx<T> f = cscale(pw, binom * sc);
-        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, pl[m * 3 + ch]));
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
         binom = binom * (T)(m + 1) * recip<T>(m + 1 - k);
         pw = cmul(pw, z0);
     }
@@ -2705,8 +2713,10 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
                 dl.l = l;
                 dl.vl = d_lev + pl.lev_begin[l];
                 dl.nvl = pl.lev_begin[l + 1] - pl.lev_begin[l];
-                hipLaunchKernelGGL((k_down_l2l<T>), dim3(pl.lev_blocks[l]), dim3(kWave), 0, st, dl,
-                                   p, C, TL, quiet, owner);
+                const int G = kWave / (p + 1);
+                hipLaunchKernelGGL((k_down_l2l<T>), dim3((pl.lev_blocks[l] + G - 1) / G),
+                                   dim3(kWave), 0, st, dl, pl.lev_blocks[l], p, C, TL, quiet,
+                                   owner);
                 DC_HIP(hipGetLastError());
             }
         }
