@@ -1512,19 +1512,25 @@ k_down_contrib_cells(TreeView tv, PieceView pv, int p, const cpx<double>* __rest
     if (lane == 0) quiet[c] = q ? 1 : 0;
 }
 
-// One level of the solve's L2L (one wave per cell, lane k = coefficient
-// k): L[c] = C[c] + L2L(L[parent]) in FP64 (Eq. i-f-i, scaled).
+// One level of the solve's L2L (G = 64 / (p + 1) cells per wave, lane k
+// of a group = coefficient k): L[c] = C[c] + L2L(L[parent]) in FP64
+// (Eq. i-f-i, scaled).
 __global__ void __launch_bounds__(kWave)
-k_l2l_cells(TreeView tv, int first_cell, int p, const cpx<double>* __restrict__ C,
+k_l2l_cells(TreeView tv, int first_cell, int n_cells, int p, const cpx<double>* __restrict__ C,
             cpx<double>* __restrict__ L, const unsigned char* __restrict__ quiet) {
-    __shared__ cpx<double> pl[3 * (DC_P_MAX + 1)];
-    const int c = first_cell + blockIdx.x;
-    const int par = tv.parent[c];
+    __shared__ cpx<double> pl[3 * kWave];  // the groups' parent expansions
     const int lane = threadIdx.x, P1 = p + 1;
-    for (int i = lane; i < 3 * P1; i += kWave) pl[i] = L[(size_t)par * 3 * P1 + i];
+    const int G = kWave / P1;
+    const int g = lane / P1, k = lane - g * P1;
+    const int ci = (int)blockIdx.x * G + g;
+    const bool work = g < G && ci < n_cells;
+    const int c = first_cell + (work ? ci : 0);
+    const int par = tv.parent[c];
+    cpx<double>* src = pl + g * 3 * P1;
+    if (work)
+        for (int i = k; i < 3 * P1; i += P1) src[i] = L[(size_t)par * 3 * P1 + i];
     __syncthreads();
-    const int k = lane;
-    if (k > p) return;
+    if (!work) return;
     cpx<double> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (!quiet[c])
         for (int ch = 0; ch < 3; ++ch) acc[ch] = C[((size_t)c * P1 + k) * 3 + ch];
@@ -1534,7 +1540,7 @@ k_l2l_cells(TreeView tv, int first_cell, int p, const cpx<double>* __restrict__ 
     const double sc = ldexp(1.0, -k);
     for (int m = k; m <= p; ++m) {
         const cpx<double> f = cscale(pw, binom * sc);
-        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, pl[m * 3 + ch]));
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
         binom = binom * (double)(m + 1) * recip<double>(m + 1 - k);
         pw = cmul(pw, z0);
     }
@@ -2523,8 +2529,9 @@ void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double
             const int first = f.level_start[l];
             const int cnt = f.level_start[l + 1] - first;
             if (cnt <= 0) continue;
-            hipLaunchKernelGGL(k_l2l_cells, dim3(cnt), dim3(kWave), 0, st, tv, first, p,
-                               as_cpx(f.C64), as_cpx(L), f.quietS.p);
+            const int G = kWave / (p + 1);
+            hipLaunchKernelGGL(k_l2l_cells, dim3((cnt + G - 1) / G), dim3(kWave), 0, st, tv, first,
+                               cnt, p, as_cpx(f.C64), as_cpx(L), f.quietS.p);
             DC_HIP(hipGetLastError());
         }
     }
