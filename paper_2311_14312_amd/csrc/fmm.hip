@@ -258,30 +258,45 @@ k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
 
 // Outgoing-from-outgoing (Eq. o-f-o) in scaled form, child quadrant q:
 //   Mt'_k = sum_{l<=k} C(k,l) z0^{k-l} 2^{-l} Mt_l,  z0 = (c_child - c)/r'.
+// G = 64 / (p + 1) cells per wave, lane k of a group = coefficient k; the
+// group's four children's expansions are staged in LDS by one round of
+// independent loads.
 template <typename T>
 __global__ void __launch_bounds__(kWave)
-k_m2m(TreeView tv, int first, int p, cpx<T>* __restrict__ M) {
-    const int c = first + blockIdx.x;
-    if (tv.child[c] < 0) return;
-    const int k = threadIdx.x;
-    if (k > p) return;
+k_m2m(TreeView tv, int first, int n, int p, cpx<T>* __restrict__ M) {
+    __shared__ cpx<T> cm[4 * 3 * kWave];
+    const int lane = threadIdx.x, P1 = p + 1, span = 3 * P1;
+    const int G = kWave / P1;
+    const int g = lane / P1, k = lane - g * P1;
+    const int ci = (int)blockIdx.x * G + g;
+    const bool valid = g < G && ci < n;
+    const int c = first + (valid ? ci : 0);
+    const int c0 = valid ? tv.child[c] : -1;
+    const bool work = c0 >= 0;
+    cpx<T>* src = cm + g * 4 * span;
+    if (work)
+        for (int i = k; i < 4 * span; i += P1) {
+            const int q = i / span;
+            src[i] = M[(size_t)(c0 + q) * span + (i - q * span)];
+        }
+    __syncthreads();
+    if (!work) return;
     cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int q = 0; q < 4; ++q) {
-        const int cc = tv.child[c] + q;
-        if (tv.npc[cc] == 0) continue;
+        if (tv.npc[c0 + q] == 0) continue;
         const cpx<T> z0 = {(T)((q & 1) ? 0.5 : -0.5), (T)((q >> 1) ? 0.5 : -0.5)};
-        const cpx<T>* src = M + (size_t)cc * (p + 1) * 3;
+        const cpx<T>* cs = src + q * span;
         cpx<T> pw = {1, 0};
         T binom = 1, sc = (T)ldexp(1.0, -k);
         for (int l = k; l >= 0; --l) {
             const cpx<T> f = cscale(pw, binom * sc);
-            for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[l * 3 + ch]));
+            for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, cs[l * 3 + ch]));
             binom = binom * (T)l * recip<T>(k - l + 1);
             sc *= (T)2;
             pw = cmul(pw, z0);
         }
     }
-    cpx<T>* out = M + ((size_t)c * (p + 1) + k) * 3;
+    cpx<T>* out = M + ((size_t)c * P1 + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
 }
 
@@ -2405,8 +2420,9 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
     for (int l = f.depth - 1; l >= 0; --l) {
         const int first = f.level_start[l], cnt = f.level_start[l + 1] - first;
         if (cnt <= 0) continue;
-        hipLaunchKernelGGL(k_m2m<double>, dim3(cnt), dim3(kWave), 0, st, tv, first, p,
-                           as_cpx(f.M64));
+        const int G = kWave / (p + 1);
+        hipLaunchKernelGGL(k_m2m<double>, dim3((cnt + G - 1) / G), dim3(kWave), 0, st, tv, first,
+                           cnt, p, as_cpx(f.M64));
         DC_HIP(hipGetLastError());
     }
     f.Ms64.alloc(nm);
