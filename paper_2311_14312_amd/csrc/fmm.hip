@@ -397,6 +397,9 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
                           const cpx<double>* __restrict__ M, cpx<double>* __restrict__ L,
                           int* __restrict__ nset, const cpx<double>* __restrict__ Ttab,
                           int2* __restrict__ owner, unsigned long long* stats, int lane) {
+    // the split pass stages one interaction-list entry per group and round
+    // (several entries per round are used, and tested, by k_down only)
+    static_assert(!Split || E == 1, "split pass: E = 1");
     // Render: the children of a quiet box are quiet (below); they record the
     // owner and leave without using the parent's near set.
     const int2 po = (!Split && owner != nullptr) ? owner[par] : make_int2(par, 0);
