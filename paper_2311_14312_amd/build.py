@@ -24,7 +24,7 @@ COMMON = [
     # packed FP32 instructions stay off: some of their forms have produced
     # silent wrong results on this hardware generation
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-Wall", "-Wshadow", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
 

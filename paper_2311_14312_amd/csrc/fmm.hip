@@ -952,7 +952,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                 while (sh.nS > 0 && nU < kUCap && nW + 4 <= kWCap) {
                     const int c = sh.stack[--sh.nS];
                     const int c0 = tv.child[c], cm = tv.cmask[c], lc = tv.lvl[c];
-                    const long long cx = tv.ix[c], cy = tv.iy[c];
+                    const long long bx = tv.ix[c], by = tv.iy[c];
                     if (c0 < 0) {
                         sh.Upre[nU] = 0;
                         sh.U[nU++] = c;
@@ -961,7 +961,7 @@ k_leaf(TreeView tv, PieceView pv, LeafArgs a, int p, const cpx<double>* __restri
                     for (int q = 0; q < 4; ++q) {
                         const int d = c0 + q;
                         if (!((cm >> q) & 1)) continue;
-                        if (touches_at(lc + 1, 2 * cx + (q & 1), 2 * cy + (q >> 1), l, ti, tj)) {
+                        if (touches_at(lc + 1, 2 * bx + (q & 1), 2 * by + (q >> 1), l, ti, tj)) {
                             if (sh.nS < kSCap) sh.stack[sh.nS++] = d;
                         } else {
                             sh.W[nW++] = d;
@@ -2423,9 +2423,9 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
     for (int l = f.depth - 1; l >= 0; --l) {
         const int first = f.level_start[l], cnt = f.level_start[l + 1] - first;
         if (cnt <= 0) continue;
-        const int G = kWave / (p + 1);
-        hipLaunchKernelGGL(k_m2m<double>, dim3((cnt + G - 1) / G), dim3(kWave), 0, st, tv, first,
-                           cnt, p, as_cpx(f.M64));
+        const int groups = kWave / (p + 1);
+        hipLaunchKernelGGL(k_m2m<double>, dim3((cnt + groups - 1) / groups), dim3(kWave), 0, st,
+                           tv, first, cnt, p, as_cpx(f.M64));
         DC_HIP(hipGetLastError());
     }
     f.Ms64.alloc(nm);
