@@ -421,6 +421,7 @@ typedef struct {
     unsigned long long l2p_targets;     /* targets evaluated from an incoming expansion */
     unsigned long long m2l_pairs;       /* (target box, source box) translations */
     unsigned long long p2l_pairs;       /* (target box, piece) incoming-from-source */
+    unsigned long long p2l_fp64_pairs;  /* of those, evaluated in FP64 */
     unsigned long long l2l_boxes;       /* parent-to-child incoming translations */
     unsigned long long leaf_boxes;      /* target leaves evaluated */
     unsigned long long pieces;          /* clipped chord pieces of the scene */

@@ -47,8 +47,8 @@ constexpr int kUCap = 128;   // near leaves per round
 constexpr int kWCap = 256;   // smaller-separated boxes per round
 constexpr int kSCap = 256;   // traversal stack (>= 9 + 4 * max depth)
 // work counters (dc_work_counts order)
-enum { kStatP2P = 0, kStatP2P64, kStatM2P, kStatL2P, kStatM2L, kStatP2L, kStatL2L, kStatLeaf,
-       kNStat };
+enum { kStatP2P = 0, kStatP2P64, kStatM2P, kStatL2P, kStatM2L, kStatP2L, kStatP2L64, kStatL2L,
+       kStatLeaf, kNStat };
 
 // 1/n for n < 128 (entry 0 unused): the coefficient recurrences of the
 // translation operators multiply by these instead of dividing (an FP64
@@ -776,6 +776,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         }
     if (Count && lane == 0) {
         atomicAdd(stats + kStatP2L, (unsigned long long)total);
+        if (!p2l32) atomicAdd(stats + kStatP2L64, (unsigned long long)total);
         atomicAdd(stats + kStatL2L, 1ULL);
     }
     // reduce the groups' shares into group 0
@@ -2972,6 +2973,7 @@ void fmm_render_counts(dc_scene_s& s, const dc_viewport& vp, const dc_eval_opts&
     counts->l2p_targets = h[kStatL2P];
     counts->m2l_pairs = h[kStatM2L];
     counts->p2l_pairs = h[kStatP2L];
+    counts->p2l_fp64_pairs = h[kStatP2L64];
     counts->l2l_boxes = h[kStatL2L];
     counts->leaf_boxes = h[kStatLeaf];
     counts->pieces = (unsigned long long)f.n_pieces;

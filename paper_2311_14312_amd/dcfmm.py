@@ -60,7 +60,7 @@ class WorkCounts(C.Structure):
     _fields_ = [("p2p_pairs", C.c_ulonglong), ("p2p_fp64_pairs", C.c_ulonglong),
                 ("m2p_pairs", C.c_ulonglong), ("l2p_targets", C.c_ulonglong),
                 ("m2l_pairs", C.c_ulonglong), ("p2l_pairs", C.c_ulonglong),
-                ("l2l_boxes", C.c_ulonglong), ("leaf_boxes", C.c_ulonglong),
+                ("p2l_fp64_pairs", C.c_ulonglong), ("l2l_boxes", C.c_ulonglong), ("leaf_boxes", C.c_ulonglong),
                 ("pieces", C.c_ulonglong), ("source_cells", C.c_ulonglong),
                 ("levels", C.c_int), ("p", C.c_int)]
 

@@ -60,6 +60,34 @@ def test_c3_operator_rows(c3):
         assert eF <= (1e-8 if p == 20 else 1e-10)
 
 
+@pytest.mark.parametrize("leaf", [32, 64])
+def test_c3_fp32_incoming_from_source_routing(gpu_lib, leaf):
+    """The FP32 path's choice of FP32 or FP64 for each box's incoming-from-
+    source terms (by the largest |charge| x length of one piece) on the
+    clustered scene with larger leaves, where a separated leaf holds more
+    pieces: the FP32 bar still holds, and the work counts show how many of
+    those terms are taken in FP64."""
+    g = np.load(os.path.join(HERE, "golden", "c3_golden.npz"))
+    sc = scenegen.clustered_scene(seed=CFG["seed"], panels=CFG["panels"], gl=CFG["gl"],
+                                  segs=CFG["segs"])
+    s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=CFG["panels"],
+                      gl=CFG["gl"], segs=CFG["segs"], leaf_max=leaf)
+    try:
+        s.set_densities(scenegen.synthetic_densities(s.N))
+        vp = CFG["viewport"]
+        ev = dict(method="fmm", precision="f32", p=12, tile_px=8)
+        m32, r32 = _errs(s.render(vp, **ev).cpu().numpy(), g)
+        c = s.render_counts(vp, **ev)
+        frac = c["p2l_fp64_pairs"] / max(1, c["p2l_pairs"])
+        print(f"C3 leaf {leaf}: FP32 max {m32:.3e} rms {r32:.3e}; incoming-from-source pairs "
+              f"{c['p2l_pairs']:,}, in FP64 {c['p2l_fp64_pairs']:,} ({100 * frac:.1f}%)",
+              flush=True)
+        assert c["p2l_fp64_pairs"] <= c["p2l_pairs"]
+        assert m32 <= 1e-4
+    finally:
+        s.close()
+
+
 @pytest.mark.timeout(600)
 def test_c3_fp64_solve(gpu_lib):
     """FP64 FMM-GMRES (p = 20, block preconditioner) on all 1,034,240 nodes."""

@@ -140,6 +140,12 @@ def test_render_counts_are_consistent(scene, ref):
     # every pixel is evaluated from an incoming expansion exactly once
     assert c["l2p_targets"] == 256 * 256
     assert c["p2p_pairs"] > 0 and c["m2l_pairs"] > 0
+    assert c["p2l_fp64_pairs"] <= c["p2l_pairs"]
+    c64 = scene.render_counts(VP, method="fmm", p=16, precision="f64")
+    # the FP64 path takes every incoming-from-source term in FP64; the tree
+    # walk is the same
+    assert c64["p2l_fp64_pairs"] == c64["p2l_pairs"] == c["p2l_pairs"]
+    assert c64["m2l_pairs"] == c["m2l_pairs"]
 
 
 def test_block_preconditioner_same_solution(gpu_lib, ref):
