@@ -516,9 +516,15 @@ int dc_server_fetch(dc_server sv, long long ticket, void* dst, int dst_is_device
             status = r.status;
         }
         hipError_t e = hipSuccess;
-        if (status == DC_OK)
+        if (status == DC_OK) {
             e = hipMemcpy(dst, sv->arena_base + off, bytes,
                           dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+            // A device-to-device hipMemcpy can return before the copy has
+            // run.  The region goes back to the arena below, and the next
+            // batch (on a stream that does not wait for this one) may write
+            // it at once: the copy must be finished first.
+            if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        }
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             if (off != SIZE_MAX) sv->arena.release(off, bytes);

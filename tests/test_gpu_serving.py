@@ -154,6 +154,39 @@ def test_admission_by_footprint(gpu_lib, scenes):
         srv.close()
 
 
+def test_fetched_images_survive_the_next_batch(gpu_lib, scenes):
+    """Large images through a small arena: a fetched image's region is
+    handed to the next batch as soon as fetch returns, so the copy out of
+    it must have finished by then.  Every image fetched into device memory
+    while later batches run equals a plain dc_render of its viewport."""
+    import torch
+    ss = scenes["scenes"]
+    srv = gpu_lib.Server(**EV, n_streams=4, max_batch=2, hbm_budget=160 << 20)
+    try:
+        for s in ss:
+            srv.add_scene(s)
+        vps = [(0.5, 0.5, 1.0, 1.0, 1024, 1024), (0.45, 0.55, 0.5, 0.5, 1024, 1024),
+               (0.6, 0.4, 0.25, 0.25, 1024, 1024)]
+        reqs = [(ss[k % 3], vps[(k // 3) % 3]) for k in range(24)]
+        tickets = [srv.submit(s, vp) for s, vp in reqs]
+        imgs = []
+        for t in tickets:
+            info = srv.wait(t, timeout=120)
+            assert info is not None and info["status"] == 0
+            imgs.append(srv.fetch(t))
+        st = srv.stats()
+        print("server stats", st, flush=True)
+        assert st["admission_waits"] >= 1
+        refs = {}
+        for (s, vp), img in zip(reqs, imgs):
+            key = (id(s), vp)
+            if key not in refs:
+                refs[key] = s.render(vp, method="fmm", **EV)
+            assert torch.equal(img, refs[key]), vp
+    finally:
+        srv.close()
+
+
 def test_registered_scene_is_read_only(gpu_lib, scenes):
     s = scenes["scenes"][1]
     srv = gpu_lib.Server(**EV, n_streams=1)
