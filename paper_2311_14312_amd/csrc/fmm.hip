@@ -478,8 +478,7 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
     // translation of a truncated expansion is exact, so evaluating the
     // ancestor's expansion at a pixel gives the same value).
     if (Split || owner != nullptr) {
-        bool quiet = true;
-        for (int s = 0; s < 9; ++s) quiet = quiet && (sh.PN[s] < 0 || sh.PN2[s] == 0);
+        const bool quiet = __ballot(lane < 9 && sh.PN[lane] >= 0 && sh.PN2[lane] != 0) == 0;
         if (quiet) {
             if (!Split && lane == 0) owner[own] = po;
             return true;
@@ -1343,6 +1342,17 @@ __device__ inline int xcd_block(int b, int nb) {
 // boxes (k_down_l2l).  Coarse levels, whose few boxes each run a long chain
 // of dependent loads, then overlap with the finer ones in one launch.
 
+// Cell and parent of global box b, which lies in level-table entry at.
+__device__ inline const VpLevel& box_at(const VpLevel* __restrict__ lev, int at, int b,
+                                        long long& ti, long long& tj, int& par) {
+    const VpLevel& e = lev[at];
+    const int rel = b - e.off;
+    ti = e.i0 + rel % e.wl;
+    tj = e.j0 + rel / e.wl;
+    par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
+    return e;
+}
+
 // Level-table entry, cell and parent of global box b (entries sorted by off).
 __device__ inline const VpLevel& box_entry(const VpLevel* __restrict__ lev, int n_ent, int b,
                                            long long& ti, long long& tj, int& par) {
@@ -1351,13 +1361,12 @@ __device__ inline const VpLevel& box_entry(const VpLevel* __restrict__ lev, int 
         const int mid = (lo + hi + 1) >> 1;
         if (lev[mid].off <= b) lo = mid; else hi = mid - 1;
     }
-    const VpLevel& e = lev[lo];
-    const int rel = b - e.off;
-    ti = e.i0 + rel % e.wl;
-    tj = e.j0 + rel / e.wl;
-    par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
-    return e;
+    return box_at(lev, lo, b, ti, tj, par);
 }
+
+// Level-table entries whose first-box offsets k_near_all stages in LDS (a
+// longer table is searched in memory).
+constexpr int kNearOffs = 1024;
 
 // Near set of box b, cell s (one thread each): the deepest source box at a
 // level <= l covering the cell, found by descending the source tree from
@@ -1367,12 +1376,27 @@ __device__ inline const VpLevel& box_entry(const VpLevel* __restrict__ lev, int 
 __global__ void __launch_bounds__(256)
 k_near_all(TreeView tv, const VpLevel* __restrict__ lev, int n_ent, int total,
            int* __restrict__ nset) {
+    __shared__ int offs[kNearOffs];
+    const bool staged = n_ent <= kNearOffs;
+    if (staged)
+        for (int i = threadIdx.x; i < n_ent; i += blockDim.x) offs[i] = lev[i].off;
+    __syncthreads();
     const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= 9LL * total) return;
     const int b = (int)(gi / 9), s = (int)(gi - 9LL * b);
     long long ti, tj;
     int par;
-    const VpLevel& e = box_entry(lev, n_ent, b, ti, tj, par);
+    int at = 0;
+    if (staged) {
+        int lo = 0, hi = n_ent - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= b) lo = mid; else hi = mid - 1;
+        }
+        at = lo;
+    }
+    const VpLevel& e = staged ? box_at(lev, at, b, ti, tj, par)
+                              : box_entry(lev, n_ent, b, ti, tj, par);
     const int l = e.level;
     const long long px = ti + (s % 3) - 1, py = tj + (s / 3) - 1;
     const long long lim = 1LL << l;
@@ -1422,6 +1446,9 @@ k_down_contrib(TreeView tv, PieceView pv, int p, const cpx<double>* __restrict__
     if (lane == 0) quiet[b] = q ? 1 : 0;
 }
 
+// Boxes of a level up to which k_down_l2l loads ahead of its flags.
+constexpr int kL2LAhead = 8192;
+
 // One level of the split pass (G = 64 / (p + 1) boxes per wave, lane k of
 // a group = coefficient k): L[b] = C[b] + L2L(L[parent]) (Eq. i-f-i,
 // scaled; the same recurrence as down_body's) with owner[b] = (b, l); a
@@ -1440,30 +1467,47 @@ k_down_l2l(DownLevel dl, int n_boxes, int p, const cpx<double>* __restrict__ C,
     long long ti = 0, tj = 0;
     int own = 0, par = 0;
     bool work = false;
-    if (g < G && bi < n_boxes) {
+    const bool box = g < G && bi < n_boxes;
+    if (box) {
         const VpLevel& e = find_entry(dl.vl, dl.nvl, bi);
         const int bb = bi - e.first_block;
         ti = e.i0 + bb % e.wl;
         tj = e.j0 + bb / e.wl;
         own = e.off + bb;
         par = e.poff + (int)((ti >> 1) - e.pi0) + (int)((tj >> 1) - e.pj0) * e.pwl;
-        const int2 po = owner[par];
-        work = po.x == par && !quiet[own];
+    }
+    // On levels with few boxes, whose launches are one chain of dependent
+    // loads, every load of a box is issued at once: the parent's owner, the
+    // quiet flag, the box's own terms and the parent's expansion (the last
+    // two lie inside C and L whatever the flags say, and are used only when
+    // the box works: its parent's L and its own C are then written).  On
+    // the larger levels, where most boxes are quiet, the terms are loaded
+    // only for working boxes.
+    const bool ahead = n_boxes <= kL2LAhead;
+    int2 po = make_int2(0, 0);
+    unsigned char qb = 1;
+    cpx<double> cv[3], lv[3];
+    if (box) {
+        po = owner[par];
+        qb = quiet[own];
+        if (ahead) {
+            for (int ch = 0; ch < 3; ++ch) cv[ch] = C[((size_t)own * P1 + k) * 3 + ch];
+            for (int t = 0; t < 3; ++t) lv[t] = L[(size_t)par * 3 * P1 + k + t * P1];
+        }
+        work = po.x == par && !qb;
         if (k == 0) owner[own] = work ? make_int2(own, dl.l) : po;
+        if (work && !ahead) {
+            for (int ch = 0; ch < 3; ++ch) cv[ch] = C[((size_t)own * P1 + k) * 3 + ch];
+            for (int t = 0; t < 3; ++t) lv[t] = L[(size_t)par * 3 * P1 + k + t * P1];
+        }
     }
     cpx<T>* src = pl + g * 3 * P1;
     if (work)
-        for (int i = k; i < 3 * P1; i += P1) {
-            const cpx<double> v = L[(size_t)par * 3 * P1 + i];
-            src[i] = to_c<T>(v.re, v.im);
-        }
+        for (int t = 0; t < 3; ++t) src[k + t * P1] = to_c<T>(lv[t].re, lv[t].im);
     __syncthreads();
     if (!work) return;
     cpx<T> acc[3];
-    for (int ch = 0; ch < 3; ++ch) {
-        const cpx<double> c = C[((size_t)own * P1 + k) * 3 + ch];
-        acc[ch] = to_c<T>(c.re, c.im);
-    }
+    for (int ch = 0; ch < 3; ++ch) acc[ch] = to_c<T>(cv[ch].re, cv[ch].im);
     const cpx<T> z0 = {(T)((ti & 1) ? 0.5 : -0.5), (T)((tj & 1) ? 0.5 : -0.5)};
     cpx<T> pw = {1, 0};
     T binom = 1;
