@@ -141,17 +141,21 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     const int N = s->geo.N;
     const size_t n3 = 3 * (size_t)N;
     const int m = std::max(1, std::min(o.max_iter, N));
-    DevBuf<double> b, x, w, tmp, V, dev_h, dev_small;
+    DevBuf<double> b, x, w, tmp, V, dev_h, dots_part;
     b.alloc(n3);
     x.alloc(n3);
     w.alloc(n3);
     tmp.alloc(n3);
     V.alloc((size_t)(m + 1) * n3);
     const int kcap = m + 1;
-    dev_h.alloc((size_t)2 * 3 * kcap);
-    dev_small.alloc(3 * (size_t)kcap + 8);
+    // h1 [3][kcap], h2 [3][kcap] and the norms of w [3], one after another:
+    // one copy to the host per Arnoldi step
+    dev_h.alloc((size_t)6 * kcap + 8);
+    dots_part.alloc((size_t)3 * kcap * block_dots_split(N));
     double* h1 = dev_h.p;
     double* h2 = dev_h.p + 3 * kcap;
+    double* hn = dev_h.p + 6 * kcap;
+    PinnedHost<double> host(6 * (size_t)kcap + 8);
     const bool pre = o.precond == DC_PRECOND_BLOCK && mixed == nullptr;
     DevBuf<double> z;
     if (pre) {
@@ -196,13 +200,11 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     apply_A(x.p, tmp.p);
     launch_axpby((int)n3, 1.0, b.p, -1.0, tmp.p, w.p, st);
 
-    std::vector<double> host(6 * (size_t)kcap + 8);
     auto norms = [&](const double* vec, double out[3]) {
-        launch_block_dots(vec, 1, vec, N, dev_small.p, st);
-        DC_HIP(hipMemcpyAsync(host.data(), dev_small.p, 3 * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
+        launch_block_dots(vec, 1, vec, N, hn, dots_part.p, st);
+        DC_HIP(hipMemcpyAsync(host.p, hn, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
         DC_HIP(hipStreamSynchronize(st));
-        for (int c = 0; c < 3; ++c) out[c] = std::sqrt(std::max(host[c], 0.0));
+        for (int c = 0; c < 3; ++c) out[c] = std::sqrt(std::max(host.p[c], 0.0));
     };
     double bnorm[3], beta[3];
     norms(b.p, bnorm);
@@ -222,8 +224,7 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         active[c] = rep.rel_residual[c] > o.tol && beta[c] > 0;
         alpha[c] = beta[c] > 0 ? 1.0 / beta[c] : 0.0;
     }
-    DC_HIP(hipMemcpyAsync(dev_small.p, alpha, 3 * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_scale3(w.p, dev_small.p, V.p, N, st);
+    launch_scale3(w.p, alpha, V.p, N, st);
 
     for (int k = 0; k < m && (active[0] || active[1] || active[2]); ++k) {
         double* vk = V.p + (size_t)k * n3;
@@ -235,16 +236,14 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
             apply_A(vk, w.p);
         }
         // classical Gram-Schmidt, twice (CGS2), against V[0..k]
-        launch_block_dots(V.p, k + 1, w.p, N, h1, st);
+        launch_block_dots(V.p, k + 1, w.p, N, h1, dots_part.p, st);
         launch_block_update(V.p, k + 1, h1, k + 1, w.p, N, st);
-        launch_block_dots(V.p, k + 1, w.p, N, h2, st);
+        launch_block_dots(V.p, k + 1, w.p, N, h2, dots_part.p, st);
         launch_block_update(V.p, k + 1, h2, k + 1, w.p, N, st);
-        launch_block_dots(w.p, 1, w.p, N, dev_small.p, st);
-        DC_HIP(hipMemcpyAsync(host.data(), h1, 3 * (size_t)(k + 1) * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        DC_HIP(hipMemcpyAsync(host.data() + 3 * (size_t)kcap, h2,
-                              3 * (size_t)(k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-        DC_HIP(hipMemcpyAsync(host.data() + 6 * (size_t)kcap, dev_small.p, 3 * sizeof(double),
+        launch_block_dots(w.p, 1, w.p, N, hn, dots_part.p, st);
+        // h1 and h2 (3 (k + 1) values each, at the starts of their slots)
+        // and the norms, in one copy to pinned memory
+        DC_HIP(hipMemcpyAsync(host.p, dev_h.p, (6 * (size_t)kcap + 3) * sizeof(double),
                               hipMemcpyDeviceToHost, st));
         DC_HIP(hipStreamSynchronize(st));
         for (int c = 0; c < 3; ++c) {
@@ -252,8 +251,9 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
             if (!active[c]) continue;
             double* col = &R[c][(size_t)k * kcap];
             for (int j = 0; j <= k; ++j)
-                col[j] = host[(size_t)c * (k + 1) + j] + host[3 * (size_t)kcap + (size_t)c * (k + 1) + j];
-            const double hk1 = std::sqrt(std::max(host[6 * (size_t)kcap + c], 0.0));
+                col[j] = host.p[(size_t)c * (k + 1) + j] +
+                         host.p[3 * (size_t)kcap + (size_t)c * (k + 1) + j];
+            const double hk1 = std::sqrt(std::max(host.p[6 * (size_t)kcap + c], 0.0));
             for (int j = 0; j < k; ++j) {
                 const double a = cs[c][j] * col[j] + sn[c][j] * col[j + 1];
                 col[j + 1] = -sn[c][j] * col[j] + cs[c][j] * col[j + 1];
@@ -271,8 +271,7 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
             if (rep.rel_residual[c] <= o.tol || hk1 == 0.0) active[c] = false;
             alpha[c] = (active[c] && hk1 > 0) ? 1.0 / hk1 : 0.0;
         }
-        DC_HIP(hipMemcpyAsync(dev_small.p, alpha, 3 * sizeof(double), hipMemcpyHostToDevice, st));
-        launch_scale3(w.p, dev_small.p, V.p + (size_t)(k + 1) * n3, N, st);
+        launch_scale3(w.p, alpha, V.p + (size_t)(k + 1) * n3, N, st);
     }
     // Back substitution R y = g per channel; x += V y.
     std::vector<double> y(3 * (size_t)kcap, 0.0);

@@ -85,6 +85,22 @@ struct DevBuf {
     }
 };
 
+// Owning pinned host buffer (hipHostMalloc / hipHostFree): copies from the
+// device into it need no staging through a bounce buffer.
+template <typename T>
+struct PinnedHost {
+    T* p = nullptr;
+    explicit PinnedHost(size_t count) {
+        DC_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), count * sizeof(T),
+                             hipHostMallocDefault));
+    }
+    PinnedHost(const PinnedHost&) = delete;
+    PinnedHost& operator=(const PinnedHost&) = delete;
+    ~PinnedHost() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // ---------------------------------------------------------------- complex

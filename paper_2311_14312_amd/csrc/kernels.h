@@ -43,15 +43,17 @@ void launch_direct_targets(const TargetGrid* grid, const double* pts, int n_pts,
                            void* out, hipStream_t st);
 
 // ------------------------------------------------------------ GMRES helpers
-// dots[c][j] = <V[j][c], w[c]> for j < k (V is [k][3][N]).
+// dots[c][j] = <V[j][c], w[c]> for j < k (V is [k][3][N]); part holds
+// 3 k block_dots_split(N) partial sums.
+int block_dots_split(int N);
 void launch_block_dots(const double* V, int k, const double* w, int N, double* dots,
-                       hipStream_t st);
+                       double* part, hipStream_t st);
 // w[c] -= sum_j V[j][c] * h[c][j]; h given on the device [3][kcap] with
 // stride kcap.
 void launch_block_update(const double* V, int k, const double* h, int kcap, double* w,
                          int N, hipStream_t st);
-// y[c] = alpha[c] * x[c]
-void launch_scale3(const double* x, const double* alpha, double* y, int N, hipStream_t st);
+// y[c] = alpha[c] * x[c] (alpha on the host)
+void launch_scale3(const double* x, const double alpha[3], double* y, int N, hipStream_t st);
 // x[c] += sum_j V[j][c] * y[c][j]  (y host-provided on device, stride kcap)
 void launch_combine(const double* V, int k, const double* y, int kcap, double* x, int N,
                     hipStream_t st);

@@ -159,17 +159,34 @@ __device__ inline double block_sum(double v, double* red) {
     return red[0];
 }
 
+// Rows summed by one block of k_block_dots.
+constexpr int kDotRows = 8192;
+
+// dots[c k + j] = <V_j^c, w^c> in two steps: block (j, c, s) sums the rows
+// [s R, (s + 1) R) into part[(c k + j) S + s] (S = gridDim.z), and
+// k_dots_finish adds each dot's S partial sums in order, so the result does
+// not depend on the order in which blocks run.
 __global__ void __launch_bounds__(kNT)
 k_block_dots(const double* __restrict__ V, const double* __restrict__ w, int N,
-             double* __restrict__ dots, int k) {
+             double* __restrict__ part, int k) {
     __shared__ double red[kNT];
-    const int j = blockIdx.x, c = blockIdx.y;
+    const int j = blockIdx.x, c = blockIdx.y, sb = blockIdx.z;
     const double* v = V + ((size_t)j * 3 + c) * N;
     const double* ww = w + (size_t)c * N;
+    const int hi = min(N, (sb + 1) * kDotRows);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < N; i += kNT) acc += v[i] * ww[i];
+    for (int i = sb * kDotRows + threadIdx.x; i < hi; i += kNT) acc += v[i] * ww[i];
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) dots[(size_t)c * k + j] = s;
+    if (threadIdx.x == 0) part[((size_t)c * k + j) * gridDim.z + sb] = s;
+}
+
+__global__ void __launch_bounds__(kNT)
+k_dots_finish(const double* __restrict__ part, int n, int S, double* __restrict__ dots) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int t = 0; t < S; ++t) s += part[(size_t)i * S + t];
+    dots[i] = s;
 }
 
 __global__ void __launch_bounds__(kNT)
@@ -183,12 +200,16 @@ k_block_update(const double* __restrict__ V, int k, const double* __restrict__ h
     w[(size_t)c * N + i] = acc;
 }
 
+// Per-channel factors, passed by value (no copy to the device).
+struct Scale3 {
+    double a[3];
+};
+
 __global__ void __launch_bounds__(kNT)
-k_scale3(const double* __restrict__ x, const double* __restrict__ alpha,
-         double* __restrict__ y, int N) {
+k_scale3(const double* __restrict__ x, Scale3 alpha, double* __restrict__ y, int N) {
     const int i = blockIdx.x * kNT + threadIdx.x;
     const int c = blockIdx.y;
-    if (i < N) y[(size_t)c * N + i] = alpha[c] * x[(size_t)c * N + i];
+    if (i < N) y[(size_t)c * N + i] = alpha.a[c] * x[(size_t)c * N + i];
 }
 
 __global__ void __launch_bounds__(kNT)
@@ -277,9 +298,15 @@ void launch_direct_targets(const TargetGrid* grid, const double* pts, int n_pts,
     DC_HIP(hipGetLastError());
 }
 
+int block_dots_split(int N) { return std::max(1, (N + kDotRows - 1) / kDotRows); }
+
 void launch_block_dots(const double* V, int k, const double* w, int N, double* dots,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_block_dots, dim3(k, 3), dim3(kNT), 0, st, V, w, N, dots, k);
+                       double* part, hipStream_t st) {
+    const int S = block_dots_split(N);
+    hipLaunchKernelGGL(k_block_dots, dim3(k, 3, S), dim3(kNT), 0, st, V, w, N, part, k);
+    DC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_dots_finish, dim3(blocks(3LL * k)), dim3(kNT), 0, st, part, 3 * k, S,
+                       dots);
     DC_HIP(hipGetLastError());
 }
 
@@ -290,8 +317,9 @@ void launch_block_update(const double* V, int k, const double* h, int kcap, doub
     DC_HIP(hipGetLastError());
 }
 
-void launch_scale3(const double* x, const double* alpha, double* y, int N, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale3, dim3(blocks(N), 3), dim3(kNT), 0, st, x, alpha, y, N);
+void launch_scale3(const double* x, const double alpha[3], double* y, int N, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale3, dim3(blocks(N), 3), dim3(kNT), 0, st, x,
+                       Scale3{{alpha[0], alpha[1], alpha[2]}}, y, N);
     DC_HIP(hipGetLastError());
 }
 
