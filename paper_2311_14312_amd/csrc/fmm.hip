@@ -224,13 +224,16 @@ __device__ inline void chord_fast_nz(float xi1, float h, float xi2, float la, fl
 // A, B = piece end points relative to the box centre in units of r,
 // wbar = conjugate unit tangent, qs = kappa sigma_bar, qm = kappa mu_bar
 // (the left normal nu = i w makes nu wbar = i).
+// G = 64 / (p + 1) groups of p + 1 lanes: group g takes the leaf's pieces
+// g, g + G, ...; group 0 adds the others' sums in group order.
 template <typename T>
 __global__ void __launch_bounds__(kWave)
 k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
+    __shared__ cpx<T> red[kWave][3];
     const int c = blockIdx.x;
     if (tv.child[c] >= 0) return;
-    const int k = threadIdx.x;
-    if (k > p) return;
+    const int P1 = p + 1, G = kWave / P1;
+    const int g = threadIdx.x / P1, k = threadIdx.x - g * P1;
     const int l = tv.lvl[c];
     const double r = half_width(tv, l);
     double cx, cy;
@@ -239,7 +242,8 @@ k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
     const T* w = weights<T>(pv);
     cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     const T rk = (T)(r / (k + 1));
-    for (int e = tv.pbeg[c]; e < tv.pend[c]; ++e) {
+    const int e1 = g < G ? tv.pend[c] : 0;
+    for (int e = tv.pbeg[c] + g; e < e1; e += G) {
         const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
         const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
         const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
@@ -252,7 +256,13 @@ k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
             acc[ch] = cadd(acc[ch], cadd(cscale(ds, qs), cscale(dm, qm)));
         }
     }
-    cpx<T>* out = M + ((size_t)c * (p + 1) + k) * 3;
+    if (g < G)
+        for (int ch = 0; ch < 3; ++ch) red[threadIdx.x][ch] = acc[ch];
+    __syncthreads();
+    if (g != 0) return;
+    for (int g2 = 1; g2 < G; ++g2)
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], red[g2 * P1 + k][ch]);
+    cpx<T>* out = M + ((size_t)c * P1 + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
 }
 
@@ -271,27 +281,32 @@ k_m2m(TreeView tv, int first, int n, int p, cpx<T>* __restrict__ M) {
     const int ci = (int)blockIdx.x * G + g;
     const bool valid = g < G && ci < n;
     const int c = first + (valid ? ci : 0);
+    // the children and the mask of those holding pieces, in one round
     const int c0 = valid ? tv.child[c] : -1;
+    const int held = valid ? tv.cmask[c] : 0;
     const bool work = c0 >= 0;
     cpx<T>* src = cm + g * 4 * span;
     if (work)
         for (int i = k; i < 4 * span; i += P1) {
             const int q = i / span;
-            src[i] = M[(size_t)(c0 + q) * span + (i - q * span)];
+            if ((held >> q) & 1) src[i] = M[(size_t)(c0 + q) * span + (i - q * span)];
         }
     __syncthreads();
     if (!work) return;
     cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
     for (int q = 0; q < 4; ++q) {
-        if (tv.npc[c0 + q] == 0) continue;
+        if (!((held >> q) & 1)) continue;
         const cpx<T> z0 = {(T)((q & 1) ? 0.5 : -0.5), (T)((q >> 1) ? 0.5 : -0.5)};
         const cpx<T>* cs = src + q * span;
         cpx<T> pw = {1, 0};
         T binom = 1, sc = (T)ldexp(1.0, -k);
-        for (int l = k; l >= 0; --l) {
+        // the loop counter j = k - l is the same in every lane, so the
+        // reciprocals are read at one address per wave
+        for (int j = 0; j <= k; ++j) {
+            const int l = k - j;
             const cpx<T> f = cscale(pw, binom * sc);
             for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, cs[l * 3 + ch]));
-            binom = binom * (T)l * recip<T>(k - l + 1);
+            binom = binom * (T)l * recip<T>(j + 1);
             sc *= (T)2;
             pw = cmul(pw, z0);
         }
@@ -504,10 +519,11 @@ __device__ bool down_body(DownShared<T, E>& sh, const TreeView& tv, const PieceV
         cpx<T> pw = {1, 0};
         T binom = 1;
         const T sc = (T)ldexp(1.0, -k);
-        for (int m = k; m <= p; ++m) {
+        for (int j = 0; j <= p - k; ++j) {  // j = m - k: the same in every lane
+            const int m = k + j;
             const cpx<T> f = cscale(pw, binom * sc);
             for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
-            binom = binom * (T)(m + 1) * recip<T>(m + 1 - k);
+            binom = binom * (T)(m + 1) * recip<T>(j + 1);
             pw = cmul(pw, z0);
         }
     }
@@ -1512,10 +1528,11 @@ k_down_l2l(DownLevel dl, int n_boxes, int p, const cpx<double>* __restrict__ C,
     cpx<T> pw = {1, 0};
     T binom = 1;
     const T sc = (T)ldexp(1.0, -k);
-    for (int m = k; m <= p; ++m) {
+    for (int j = 0; j <= p - k; ++j) {  // j = m - k: the same in every lane
+        const int m = k + j;
         const cpx<T> f = cscale(pw, binom * sc);
         for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
-        binom = binom * (T)(m + 1) * recip<T>(m + 1 - k);
+        binom = binom * (T)(m + 1) * recip<T>(j + 1);
         pw = cmul(pw, z0);
     }
     cpx<double>* out = L + ((size_t)own * P1 + k) * 3;
@@ -1588,23 +1605,31 @@ k_l2l_cells(TreeView tv, int first_cell, int n_cells, int p, const cpx<double>* 
     const int ci = (int)blockIdx.x * G + g;
     const bool work = g < G && ci < n_cells;
     const int c = first_cell + (work ? ci : 0);
+    // everything but the parent's expansion in one round of loads (the own
+    // terms lie inside C whether or not the cell is quiet, and are used only
+    // when it is not: then they are written)
     const int par = tv.parent[c];
+    const bool qc = quiet[c] != 0;
+    const long long cix = tv.ix[c], ciy = tv.iy[c];
+    cpx<double> own[3];
+    for (int ch = 0; ch < 3; ++ch) own[ch] = C[((size_t)c * P1 + k) * 3 + ch];
     cpx<double>* src = pl + g * 3 * P1;
     if (work)
         for (int i = k; i < 3 * P1; i += P1) src[i] = L[(size_t)par * 3 * P1 + i];
     __syncthreads();
     if (!work) return;
     cpx<double> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
-    if (!quiet[c])
-        for (int ch = 0; ch < 3; ++ch) acc[ch] = C[((size_t)c * P1 + k) * 3 + ch];
-    const cpx<double> z0 = {(tv.ix[c] & 1) ? 0.5 : -0.5, (tv.iy[c] & 1) ? 0.5 : -0.5};
+    if (!qc)
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = own[ch];
+    const cpx<double> z0 = {(cix & 1) ? 0.5 : -0.5, (ciy & 1) ? 0.5 : -0.5};
     cpx<double> pw = {1, 0};
     double binom = 1;
     const double sc = ldexp(1.0, -k);
-    for (int m = k; m <= p; ++m) {
+    for (int j = 0; j <= p - k; ++j) {  // j = m - k: the same in every lane
+        const int m = k + j;
         const cpx<double> f = cscale(pw, binom * sc);
         for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, src[m * 3 + ch]));
-        binom = binom * (double)(m + 1) * recip<double>(m + 1 - k);
+        binom = binom * (double)(m + 1) * recip<double>(j + 1);
         pw = cmul(pw, z0);
     }
     cpx<double>* out = L + ((size_t)c * P1 + k) * 3;

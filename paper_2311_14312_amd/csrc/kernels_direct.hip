@@ -189,15 +189,32 @@ k_dots_finish(const double* __restrict__ part, int n, int S, double* __restrict_
     dots[i] = s;
 }
 
+// w[c] -= sum_j V_j^c h[c][j]: a workgroup takes kUpdRows rows, its
+// kUpdSplit waves a quarter of the vectors each (more loads in flight than
+// one thread per row over all vectors), and the quarters are added in order
+// through LDS.
+constexpr int kUpdRows = 64, kUpdSplit = kNT / kUpdRows;
+
 __global__ void __launch_bounds__(kNT)
 k_block_update(const double* __restrict__ V, int k, const double* __restrict__ h, int kcap,
                double* __restrict__ w, int N) {
-    const int i = blockIdx.x * kNT + threadIdx.x;
+    __shared__ double part[kUpdSplit][kUpdRows];
+    const int r = threadIdx.x % kUpdRows, q = threadIdx.x / kUpdRows;
+    const int i = blockIdx.x * kUpdRows + r;
     const int c = blockIdx.y;
-    if (i >= N) return;
-    double acc = w[(size_t)c * N + i];
-    for (int j = 0; j < k; ++j) acc -= V[((size_t)j * 3 + c) * N + i] * h[(size_t)c * kcap + j];
-    w[(size_t)c * N + i] = acc;
+    double acc = 0.0;
+    if (i < N) {
+        const int j1 = ((q + 1) * k) / kUpdSplit;
+        for (int j = (q * k) / kUpdSplit; j < j1; ++j)
+            acc += V[((size_t)j * 3 + c) * N + i] * h[(size_t)c * kcap + j];
+    }
+    part[q][r] = acc;
+    __syncthreads();
+    if (q == 0 && i < N) {
+        double sum = part[0][r];
+        for (int t = 1; t < kUpdSplit; ++t) sum += part[t][r];
+        w[(size_t)c * N + i] -= sum;
+    }
 }
 
 // Per-channel factors, passed by value (no copy to the device).
@@ -312,8 +329,8 @@ void launch_block_dots(const double* V, int k, const double* w, int N, double* d
 
 void launch_block_update(const double* V, int k, const double* h, int kcap, double* w, int N,
                          hipStream_t st) {
-    hipLaunchKernelGGL(k_block_update, dim3(blocks(N), 3), dim3(kNT), 0, st, V, k, h, kcap, w,
-                       N);
+    hipLaunchKernelGGL(k_block_update, dim3((N + kUpdRows - 1) / kUpdRows, 3), dim3(kNT), 0, st,
+                       V, k, h, kcap, w, N);
     DC_HIP(hipGetLastError());
 }
 
