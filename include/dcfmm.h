@@ -269,8 +269,12 @@ int dc_refine(dc_scene s, const dc_refine_opts* o, dc_scene* out,
  * default): built when they fit 16 GiB and the near field averages at
  * least 256 pairs per node (large leaf capacities; sparser near fields
  * evaluate as fast as the tables read); mode = 2: whenever they fit;
- * mode = 0: never (as the FP32 operator).  Every call drops the tables
- * built so far.  dc_scene_get_info reports their size.  Synchronous. */
+ * mode = 0: never (as the FP32 operator).  Mode 2 also keeps, for every
+ * operator application (FP64 or FP32), the density-free factors of each
+ * piece's outgoing expansion (n_pieces x (p + 1) x 32 bytes, at most
+ * 8 GiB) and reads them instead of recomputing them: the same values.
+ * Every call drops the tables built so far.  dc_scene_get_info reports the
+ * near-field tables' size.  Synchronous. */
 int dc_set_solve_tables(dc_scene s, int mode);
 
 /* Densities sigma at the nodes, host [3][N].  Synchronous. */

@@ -487,6 +487,8 @@ int dc_set_solve_tables(dc_scene s, int enable) {
         f.tab_piece.release();
         f.tab_w.release();
         f.tab_val.release();
+        f.p2m_tab.release();
+        f.p2m_tab_p = -1;
     });
 }
 

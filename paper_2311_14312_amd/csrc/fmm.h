@@ -139,6 +139,10 @@ struct FmmState {
     DevBuf<long long> tab_pair_off;
     DevBuf<int> tab_piece_off, tab_w_off, tab_piece, tab_w;
     DevBuf<double> tab_val;
+    // Cached P2M factors of order p2m_tab_p (k_p2m in fmm.hip), under the
+    // same switch.
+    DevBuf<double> p2m_tab;
+    int p2m_tab_p = -1;
     // Upward pass of the resident densities (render reuses it); gen counts
     // the density changes (a captured render graph records it).
     bool up_valid = false;

@@ -226,9 +226,30 @@ __device__ inline void chord_fast_nz(float xi1, float h, float xi2, float la, fl
 // (the left normal nu = i w makes nu wbar = i).
 // G = 64 / (p + 1) groups of p + 1 lanes: group g takes the leaf's pieces
 // g, g + G, ...; group 0 adds the others' sums in group order.
+//
+// The factors of qs and qm depend on the geometry alone.  Repeated
+// applications of the operator (GMRES) store them once per piece and order
+// (the P2M part of the paper's precomputed per-segment operators, Sec. 6.4)
+// and read them instead of raising the end points to the k-th power: the
+// same values, summed in the same order.  Mode: kP2MEval computes them,
+// kP2MFill only writes them to tab [piece][k][ds, dm], kP2MRead reads them.
+enum { kP2MEval = 0, kP2MFill = 1, kP2MRead = 2 };
+
 template <typename T>
+__device__ inline void p2m_factors(const PieceView& pv, int e, double cx, double cy, double inv_r,
+                                   T rk, int k, cpx<T>& ds, cpx<T>& dm) {
+    const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
+    const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
+    const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
+    const cpx<T> Ak = cpow(A, k), Bk = cpow(B, k);
+    ds = cmul(cscale(csub(cmul(Bk, B), cmul(Ak, A)), rk), wbar);
+    const cpx<T> dk = csub(Bk, Ak);
+    dm = {-dk.im, dk.re};
+}
+
+template <typename T, int Mode = kP2MEval>
 __global__ void __launch_bounds__(kWave)
-k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
+k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M, cpx<T>* __restrict__ tab) {
     __shared__ cpx<T> red[kWave][3];
     const int c = blockIdx.x;
     if (tv.child[c] >= 0) return;
@@ -244,18 +265,24 @@ k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M) {
     const T rk = (T)(r / (k + 1));
     const int e1 = g < G ? tv.pend[c] : 0;
     for (int e = tv.pbeg[c] + g; e < e1; e += G) {
-        const cpx<T> A = to_c<T>((pv.x0[e] - cx) * inv_r, (pv.y0[e] - cy) * inv_r);
-        const cpx<T> B = to_c<T>((pv.x1[e] - cx) * inv_r, (pv.y1[e] - cy) * inv_r);
-        const cpx<T> wbar = {(T)pv.tx[e], (T)(-pv.ty[e])};
-        const cpx<T> Ak = cpow(A, k), Bk = cpow(B, k);
-        const cpx<T> ds = cmul(cscale(csub(cmul(Bk, B), cmul(Ak, A)), rk), wbar);
-        const cpx<T> dk = csub(Bk, Ak);
-        const cpx<T> dm = {-dk.im, dk.re};
+        cpx<T> ds, dm;
+        if constexpr (Mode == kP2MRead) {
+            ds = tab[((size_t)e * P1 + k) * 2];
+            dm = tab[((size_t)e * P1 + k) * 2 + 1];
+        } else {
+            p2m_factors<T>(pv, e, cx, cy, inv_r, rk, k, ds, dm);
+        }
+        if constexpr (Mode == kP2MFill) {
+            tab[((size_t)e * P1 + k) * 2] = ds;
+            tab[((size_t)e * P1 + k) * 2 + 1] = dm;
+            continue;
+        }
         for (int ch = 0; ch < 3; ++ch) {
             const T qs = w[(size_t)ch * pv.n + e], qm = w[(size_t)(3 + ch) * pv.n + e];
             acc[ch] = cadd(acc[ch], cadd(cscale(ds, qs), cscale(dm, qm)));
         }
     }
+    if constexpr (Mode == kP2MFill) return;
     if (g < G)
         for (int ch = 0; ch < 3; ++ch) red[threadIdx.x][ch] = acc[ch];
     __syncthreads();
@@ -2473,8 +2500,30 @@ const cpx<double>* m2l_table_dev(FmmState& f, int p) {
 // that can cancel by orders of magnitude near cusps.  The FP32 mode keeps
 // FP32 for the near-field closed forms, whose logarithms and arctangent are
 // where FP64 costs many more instructions.
+// Bytes of the cached P2M factors that upward builds for repeated
+// operator applications (at most).
+constexpr size_t kP2MTableBytes = 8ull << 30;
+
+// The cached P2M factors of order p (built on first use under table mode
+// 2; false when they are off or do not fit).  Not built by default: on the
+// 200-curve solve (p = 20) reading them took P2M from 70 to 62 us per
+// application, for 188 MB; the kernel waits on its leaves' loads either way.
+bool p2m_table(FmmState& f, int p, hipStream_t st) {
+    if (f.tab_mode != 2 || f.n_pieces == 0) return false;
+    if (f.p2m_tab_p == p) return true;
+    const size_t n = (size_t)f.n_pieces * (p + 1) * 2;
+    if (n * sizeof(cpx<double>) > kP2MTableBytes) return false;
+    f.p2m_tab.alloc(2 * n);
+    hipLaunchKernelGGL((k_p2m<double, kP2MFill>), dim3(f.n_cells), dim3(kWave), 0, st,
+                       tree_view(f), piece_view(f), p, (cpx<double>*)nullptr,
+                       as_cpx(f.p2m_tab));
+    DC_HIP(hipGetLastError());
+    f.p2m_tab_p = p;
+    return true;
+}
+
 void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, int p,
-            bool want32, hipStream_t st) {
+            bool want32, hipStream_t st, bool repeated) {
     const Geometry& G = s.geo;
     f.w64.alloc((size_t)6 * f.n_pieces);
     if (want32) {
@@ -2487,8 +2536,12 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
     f.M64.alloc(nm);
     const TreeView tv = tree_view(f);
     const PieceView pv = piece_view(f);
-    hipLaunchKernelGGL(k_p2m<double>, dim3(f.n_cells), dim3(kWave), 0, st, tv, pv, p,
-                       as_cpx(f.M64));
+    if (repeated && p2m_table(f, p, st))
+        hipLaunchKernelGGL((k_p2m<double, kP2MRead>), dim3(f.n_cells), dim3(kWave), 0, st, tv, pv,
+                           p, as_cpx(f.M64), as_cpx(f.p2m_tab));
+    else
+        hipLaunchKernelGGL((k_p2m<double, kP2MEval>), dim3(f.n_cells), dim3(kWave), 0, st, tv, pv,
+                           p, as_cpx(f.M64), (cpx<double>*)nullptr);
     DC_HIP(hipGetLastError());
     for (int l = f.depth - 1; l >= 0; --l) {
         const int first = f.level_start[l], cnt = f.level_start[l + 1] - first;
@@ -2591,7 +2644,7 @@ template <typename T>
 void apply_nodes_t(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, double* y,
                    const dc_eval_opts& o, hipStream_t st) {
     const int p = o.p;
-    upward(s, f, sigma, mu, p, sizeof(T) == 4, st);
+    upward(s, f, sigma, mu, p, sizeof(T) == 4, st, true);
     f.up_valid = false;  // the cache now holds these densities, not the scene's
     DevBuf<double>& L = f.L64;
     L.alloc((size_t)f.n_cells * (p + 1) * 3 * 2);
@@ -2748,7 +2801,7 @@ void launch_render_t(dc_scene_s& s, FmmState& f, const RenderPlan& pl, const dc_
     int2* owner = reinterpret_cast<int2*>(scratch + pl.owner_at);
     if (timed) DC_HIP(hipEventRecord(f.ev[0], st));
     if (!f.up_valid || f.up_p != p || f.up_prec != (int)sizeof(T)) {
-        upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st);
+        upward(s, f, s.d_sigma.p, s.d_mu.p, p, sizeof(T) == 4, st, false);
         ++f.up_epoch;
         f.up_valid = true;
         f.up_p = p;
@@ -3235,7 +3288,7 @@ void fmm_prepare(dc_scene_s& s, const dc_eval_opts& o, hipStream_t st) {
     (void)m2l_table_dev(f, o.p);
     const int prec = o.precision == DC_PREC_F32 ? 4 : 8;
     if (!f.up_valid || f.up_p != o.p || f.up_prec != prec) {
-        upward(s, f, s.d_sigma.p, s.d_mu.p, o.p, prec == 4, st);
+        upward(s, f, s.d_sigma.p, s.d_mu.p, o.p, prec == 4, st, false);
         ++f.up_epoch;
         f.up_valid = true;
         f.up_p = o.p;
