@@ -295,49 +295,56 @@ k_p2m(TreeView tv, PieceView pv, int p, cpx<T>* __restrict__ M, cpx<T>* __restri
 
 // Outgoing-from-outgoing (Eq. o-f-o) in scaled form, child quadrant q:
 //   Mt'_k = sum_{l<=k} C(k,l) z0^{k-l} 2^{-l} Mt_l,  z0 = (c_child - c)/r'.
-// G = 64 / (p + 1) cells per wave, lane k of a group = coefficient k; the
-// group's four children's expansions are staged in LDS by one round of
-// independent loads.
+// One cell per wave: its four children's expansions are staged in LDS by
+// one round of independent loads; G = min(4, 64 / (p + 1)) groups of p + 1
+// lanes (lane k = coefficient k) translate children g, g + G, ..., so a
+// lane's chain of dependent multiply-adds covers one or two children
+// instead of four, and group 0 adds the groups' sums in group order.
 template <typename T>
 __global__ void __launch_bounds__(kWave)
 k_m2m(TreeView tv, int first, int n, int p, cpx<T>* __restrict__ M) {
     __shared__ cpx<T> cm[4 * 3 * kWave];
     const int lane = threadIdx.x, P1 = p + 1, span = 3 * P1;
-    const int G = kWave / P1;
+    const int G = min(4, kWave / P1);
     const int g = lane / P1, k = lane - g * P1;
-    const int ci = (int)blockIdx.x * G + g;
-    const bool valid = g < G && ci < n;
-    const int c = first + (valid ? ci : 0);
+    const int c = first + (int)blockIdx.x;
     // the children and the mask of those holding pieces, in one round
-    const int c0 = valid ? tv.child[c] : -1;
-    const int held = valid ? tv.cmask[c] : 0;
-    const bool work = c0 >= 0;
-    cpx<T>* src = cm + g * 4 * span;
-    if (work)
-        for (int i = k; i < 4 * span; i += P1) {
-            const int q = i / span;
-            if ((held >> q) & 1) src[i] = M[(size_t)(c0 + q) * span + (i - q * span)];
-        }
-    __syncthreads();
-    if (!work) return;
-    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
-    for (int q = 0; q < 4; ++q) {
-        if (!((held >> q) & 1)) continue;
-        const cpx<T> z0 = {(T)((q & 1) ? 0.5 : -0.5), (T)((q >> 1) ? 0.5 : -0.5)};
-        const cpx<T>* cs = src + q * span;
-        cpx<T> pw = {1, 0};
-        T binom = 1, sc = (T)ldexp(1.0, -k);
-        // the loop counter j = k - l is the same in every lane, so the
-        // reciprocals are read at one address per wave
-        for (int j = 0; j <= k; ++j) {
-            const int l = k - j;
-            const cpx<T> f = cscale(pw, binom * sc);
-            for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, cs[l * 3 + ch]));
-            binom = binom * (T)l * recip<T>(j + 1);
-            sc *= (T)2;
-            pw = cmul(pw, z0);
-        }
+    const int c0 = tv.child[c];
+    const int held = tv.cmask[c];
+    if (c0 < 0 || (int)blockIdx.x >= n) return;
+    for (int i = lane; i < 4 * span; i += kWave) {
+        const int q = i / span;
+        if ((held >> q) & 1) cm[i] = M[(size_t)(c0 + q) * span + (i - q * span)];
     }
+    __syncthreads();
+    cpx<T> acc[3] = {{0, 0}, {0, 0}, {0, 0}};
+    if (g < G)
+        for (int q = g; q < 4; q += G) {
+            if (!((held >> q) & 1)) continue;
+            const cpx<T> z0 = {(T)((q & 1) ? 0.5 : -0.5), (T)((q >> 1) ? 0.5 : -0.5)};
+            const cpx<T>* cs = cm + q * span;
+            cpx<T> pw = {1, 0};
+            T binom = 1, sc = (T)ldexp(1.0, -k);
+            // the loop counter j = k - l is the same in every lane, so the
+            // reciprocals are read at one address per wave
+            for (int j = 0; j <= k; ++j) {
+                const int l = k - j;
+                const cpx<T> f = cscale(pw, binom * sc);
+                for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cmul(f, cs[l * 3 + ch]));
+                binom = binom * (T)l * recip<T>(j + 1);
+                sc *= (T)2;
+                pw = cmul(pw, z0);
+            }
+        }
+    // the groups' sums, through the staging area once every group is done
+    // reading it
+    __syncthreads();
+    if (g > 0 && g < G)
+        for (int ch = 0; ch < 3; ++ch) cm[(g - 1) * span + k * 3 + ch] = acc[ch];
+    __syncthreads();
+    if (g != 0) return;
+    for (int g2 = 1; g2 < G; ++g2)
+        for (int ch = 0; ch < 3; ++ch) acc[ch] = cadd(acc[ch], cm[(g2 - 1) * span + k * 3 + ch]);
     cpx<T>* out = M + ((size_t)c * P1 + k) * 3;
     for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
 }
@@ -2546,9 +2553,8 @@ void upward(dc_scene_s& s, FmmState& f, const double* sigma, const double* mu, i
     for (int l = f.depth - 1; l >= 0; --l) {
         const int first = f.level_start[l], cnt = f.level_start[l + 1] - first;
         if (cnt <= 0) continue;
-        const int groups = kWave / (p + 1);
-        hipLaunchKernelGGL(k_m2m<double>, dim3((cnt + groups - 1) / groups), dim3(kWave), 0, st,
-                           tv, first, cnt, p, as_cpx(f.M64));
+        hipLaunchKernelGGL(k_m2m<double>, dim3(cnt), dim3(kWave), 0, st, tv, first, cnt, p,
+                           as_cpx(f.M64));
         DC_HIP(hipGetLastError());
     }
     f.Ms64.alloc(nm);
