@@ -52,28 +52,34 @@ k_curve_blocks(int N, int g, int s, const double* __restrict__ nx,
     for (int m = 0; m < g; ++m) row[m] = acc[m];
 }
 
-__global__ void __launch_bounds__(kNT)
+// Gauss-Jordan with partial pivoting, one block of at most 512 rows per
+// workgroup of kGJ threads: kGJRows rows at a time, kGJCols consecutive
+// columns per row (a wave reads 512 contiguous bytes of one row).
+constexpr int kGJ = 512, kGJCols = 64, kGJRows = kGJ / kGJCols;
+
+__global__ void __launch_bounds__(kGJ)
 k_gauss_jordan(BlocksView bv, double* __restrict__ D, int* __restrict__ perm_all,
                int* __restrict__ singular) {
-    __shared__ double sval[kNT];
-    __shared__ int sidx[kNT];
+    __shared__ double sval[kGJ];
+    __shared__ int sidx[kGJ];
     __shared__ double rowk[512], colk[512];
     const int n = bv.n[blockIdx.x];
     double* a = D + bv.doff[blockIdx.x];
     int* perm = perm_all + bv.node0[blockIdx.x];
     const int tid = threadIdx.x;
+    const int ty = tid / kGJCols, tx = tid - ty * kGJCols;
     for (int k = 0; k < n; ++k) {
         // pivot: largest |a[i][k]|, i >= k (first index on ties)
         double best = -1.0;
         int bi = k;
-        for (int i = k + tid; i < n; i += kNT) {
+        for (int i = k + tid; i < n; i += kGJ) {
             const double v = fabs(a[(size_t)i * n + k]);
             if (v > best) { best = v; bi = i; }
         }
         sval[tid] = best;
         sidx[tid] = bi;
         __syncthreads();
-        for (int st = kNT / 2; st > 0; st >>= 1) {
+        for (int st = kGJ / 2; st > 0; st >>= 1) {
             if (tid < st) {
                 const double o = sval[tid + st];
                 const int oi = sidx[tid + st];
@@ -95,10 +101,10 @@ k_gauss_jordan(BlocksView bv, double* __restrict__ D, int* __restrict__ perm_all
         const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
         // column k of the other rows, read before anyone changes it (after the
         // swap row pr holds the old row k)
-        for (int i = tid; i < n; i += kNT)
+        for (int i = tid; i < n; i += kGJ)
             colk[i] = (i == pr) ? a[(size_t)k * n + k] : a[(size_t)i * n + k];
         __syncthreads();
-        for (int j = tid; j < n; j += kNT) {
+        for (int j = tid; j < n; j += kGJ) {
             double vk = a[(size_t)k * n + j], vp = a[(size_t)pr * n + j];
             if (pr != k) {
                 a[(size_t)pr * n + j] = vk;
@@ -110,15 +116,17 @@ k_gauss_jordan(BlocksView bv, double* __restrict__ D, int* __restrict__ perm_all
         }
         __syncthreads();
         // eliminate column k from every other row (a[i][k] := 0 first)
-        for (long long q = tid; q < (long long)n * n; q += kNT) {
-            const int i = (int)(q / n), j = (int)(q - (long long)i * n);
+        for (int i = ty; i < n; i += kGJRows) {
             if (i == k) continue;
             const double f = colk[i];
             if (f == 0.0) continue;
-            if (j == k)
-                a[(size_t)i * n + j] = -f * rowk[k];
-            else
-                a[(size_t)i * n + j] -= f * rowk[j];
+            double* ai = a + (size_t)i * n;
+            for (int j = tx; j < n; j += kGJCols) {
+                if (j == k)
+                    ai[j] = -f * rowk[k];
+                else
+                    ai[j] -= f * rowk[j];
+            }
         }
         __syncthreads();
     }
@@ -126,7 +134,7 @@ k_gauss_jordan(BlocksView bv, double* __restrict__ D, int* __restrict__ perm_all
     for (int k = n - 1; k >= 0; --k) {
         const int pr = perm[k];
         if (pr == k) continue;
-        for (int i = tid; i < n; i += kNT) {
+        for (int i = tid; i < n; i += kGJ) {
             const double t = a[(size_t)i * n + k];
             a[(size_t)i * n + k] = a[(size_t)i * n + pr];
             a[(size_t)i * n + pr] = t;
@@ -202,7 +210,7 @@ void launch_curve_blocks(const NodesView& nodes, int g, int s, const ChordsView&
 
 void launch_invert_blocks(const BlocksView& bv, double* D, int* perm, int* singular,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(bv.n_blocks), dim3(kNT), 0, st, bv, D, perm,
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(bv.n_blocks), dim3(kGJ), 0, st, bv, D, perm,
                        singular);
     DC_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_transpose_blocks, dim3(bv.n_blocks), dim3(kNT), 0, st, bv, D);
