@@ -136,6 +136,20 @@ void ensure_block_inverse(dc_scene s, hipStream_t st) {
 // identity and their right-hand side the fixed values: the Krylov vectors
 // stay zero there, so GMRES runs on (G_H)_rr with b_r - (G_H)_rc sigma_c.
 // A given initial guess replaces x0 = 1 (the warm start of Sec. 7.1.1).
+// The two events of the Arnoldi steps' copies to the host (see gmres_solve).
+struct StepEvents {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    StepEvents() {
+        for (auto& x : e) DC_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    }
+    StepEvents(const StepEvents&) = delete;
+    StepEvents& operator=(const StepEvents&) = delete;
+    ~StepEvents() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStream_t st,
                 const MixedBC* mixed, const LocalSolve* local) {
     const int N = s->geo.N;
@@ -155,7 +169,11 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     double* h1 = dev_h.p;
     double* h2 = dev_h.p + 3 * kcap;
     double* hn = dev_h.p + 6 * kcap;
-    PinnedHost<double> host(6 * (size_t)kcap + 8);
+    // two host slots: the host reads one step's values while the next
+    // step's copy lands in the other
+    const size_t slot = 6 * (size_t)kcap + 8;
+    PinnedHost<double> host(2 * slot);
+    StepEvents ev;
     const bool pre = o.precond == DC_PRECOND_BLOCK && mixed == nullptr;
     DevBuf<double> z;
     if (pre) {
@@ -226,7 +244,13 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
     }
     launch_scale3(w.p, alpha, V.p, N, st);
 
-    for (int k = 0; k < m && (active[0] || active[1] || active[2]); ++k) {
+    // Arnoldi step k: w = A M^-1 V_k orthogonalised against V_0..V_k, its
+    // Hessenberg column and norm copied to host slot k % 2 (event k % 2),
+    // and V_{k+1} = w / ||w|| per channel, scaled on the device.  Steps are
+    // queued one ahead of the host: step k + 1 runs while the host applies
+    // step k's Givens rotations.  A channel that has converged keeps being
+    // extended; its later columns are not used.
+    auto enqueue_step = [&](int k) {
         double* vk = V.p + (size_t)k * n3;
         if (pre) {
             launch_block_apply(N, s->geo.g, s->blocks(), s->dinv.p, vk, z.p, st);
@@ -243,17 +267,23 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
         launch_block_dots(w.p, 1, w.p, N, hn, dots_part.p, st);
         // h1 and h2 (3 (k + 1) values each, at the starts of their slots)
         // and the norms, in one copy to pinned memory
-        DC_HIP(hipMemcpyAsync(host.p, dev_h.p, (6 * (size_t)kcap + 3) * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        DC_HIP(hipStreamSynchronize(st));
+        DC_HIP(hipMemcpyAsync(host.p + (k % 2) * slot, dev_h.p,
+                              (6 * (size_t)kcap + 3) * sizeof(double), hipMemcpyDeviceToHost,
+                              st));
+        DC_HIP(hipEventRecord(ev.e[k % 2], st));
+        launch_scale3_by_norm(w.p, hn, V.p + (size_t)(k + 1) * n3, N, st);
+    };
+    if (active[0] || active[1] || active[2]) enqueue_step(0);
+    for (int k = 0; k < m && (active[0] || active[1] || active[2]); ++k) {
+        if (k + 1 < m) enqueue_step(k + 1);
+        DC_HIP(hipEventSynchronize(ev.e[k % 2]));
+        const double* hs = host.p + (k % 2) * slot;
         for (int c = 0; c < 3; ++c) {
-            alpha[c] = 0.0;
             if (!active[c]) continue;
             double* col = &R[c][(size_t)k * kcap];
             for (int j = 0; j <= k; ++j)
-                col[j] = host.p[(size_t)c * (k + 1) + j] +
-                         host.p[3 * (size_t)kcap + (size_t)c * (k + 1) + j];
-            const double hk1 = std::sqrt(std::max(host.p[6 * (size_t)kcap + c], 0.0));
+                col[j] = hs[(size_t)c * (k + 1) + j] + hs[3 * (size_t)kcap + (size_t)c * (k + 1) + j];
+            const double hk1 = std::sqrt(std::max(hs[6 * (size_t)kcap + c], 0.0));
             for (int j = 0; j < k; ++j) {
                 const double a = cs[c][j] * col[j] + sn[c][j] * col[j + 1];
                 col[j + 1] = -sn[c][j] * col[j] + cs[c][j] * col[j + 1];
@@ -269,9 +299,7 @@ int gmres_solve(dc_scene s, const dc_solve_opts& o, dc_solve_report& rep, hipStr
             const double bn = bnorm[c] > 0 ? bnorm[c] : 1.0;
             rep.rel_residual[c] = std::fabs(gv[c][k + 1]) / bn;
             if (rep.rel_residual[c] <= o.tol || hk1 == 0.0) active[c] = false;
-            alpha[c] = (active[c] && hk1 > 0) ? 1.0 / hk1 : 0.0;
         }
-        launch_scale3(w.p, alpha, V.p + (size_t)(k + 1) * n3, N, st);
     }
     // Back substitution R y = g per channel; x += V y.
     std::vector<double> y(3 * (size_t)kcap, 0.0);

@@ -54,6 +54,9 @@ void launch_block_update(const double* V, int k, const double* h, int kcap, doub
                          int N, hipStream_t st);
 // y[c] = alpha[c] * x[c] (alpha on the host)
 void launch_scale3(const double* x, const double alpha[3], double* y, int N, hipStream_t st);
+// y[c] = x[c] / sqrt(n2[c]), 0 where n2[c] <= 0 (n2 [3] on the device)
+void launch_scale3_by_norm(const double* x, const double* n2, double* y, int N,
+                           hipStream_t st);
 // x[c] += sum_j V[j][c] * y[c][j]  (y host-provided on device, stride kcap)
 void launch_combine(const double* V, int k, const double* y, int kcap, double* x, int N,
                     hipStream_t st);

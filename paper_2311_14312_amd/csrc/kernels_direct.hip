@@ -229,6 +229,19 @@ k_scale3(const double* __restrict__ x, Scale3 alpha, double* __restrict__ y, int
     if (i < N) y[(size_t)c * N + i] = alpha.a[c] * x[(size_t)c * N + i];
 }
 
+// y[c] = x[c] / sqrt(n2[c]) (0 where n2[c] <= 0), the squared norms n2 on
+// the device.
+__global__ void __launch_bounds__(kNT)
+k_scale3_norm(const double* __restrict__ x, const double* __restrict__ n2,
+              double* __restrict__ y, int N) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= N) return;
+    const double v = n2[c];
+    const double a = v > 0.0 ? 1.0 / sqrt(v) : 0.0;
+    y[(size_t)c * N + i] = a * x[(size_t)c * N + i];
+}
+
 __global__ void __launch_bounds__(kNT)
 k_combine(const double* __restrict__ V, int k, const double* __restrict__ y, int kcap,
           double* __restrict__ x, int N) {
@@ -337,6 +350,12 @@ void launch_block_update(const double* V, int k, const double* h, int kcap, doub
 void launch_scale3(const double* x, const double alpha[3], double* y, int N, hipStream_t st) {
     hipLaunchKernelGGL(k_scale3, dim3(blocks(N), 3), dim3(kNT), 0, st, x,
                        Scale3{{alpha[0], alpha[1], alpha[2]}}, y, N);
+    DC_HIP(hipGetLastError());
+}
+
+void launch_scale3_by_norm(const double* x, const double* n2, double* y, int N,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_scale3_norm, dim3(blocks(N), 3), dim3(kNT), 0, st, x, n2, y, N);
     DC_HIP(hipGetLastError());
 }
 
