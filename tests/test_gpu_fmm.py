@@ -165,3 +165,32 @@ def test_block_preconditioner_same_solution(gpu_lib, ref):
     assert np.abs(s1 - ref["sigma"]).max() <= 1e-8 * scale
     assert np.abs(s0 - s1).max() <= 1e-8 * scale
     s.close()
+
+
+@pytest.mark.parametrize("precond", ["none", "block"])
+def test_gmres_step_limits(gpu_lib, ref, precond):
+    """GMRES capped at 1, 2, 3 and 8 Arnoldi steps (each step is queued
+    before the host has read the previous one): every channel stops at the
+    cap, unconverged, and the residual shrinks with the cap; the GMRES
+    estimate agrees with the recomputed residual.  A tolerance the initial
+    guess already meets takes no step."""
+    sc = ref["sc"]
+    s = gpu_lib.Scene(sc["ctrl"], sc["left"], sc["right"], panels=CFG["panels"],
+                      gl=CFG["gl"], segs=CFG["segs"], leaf_max=16)
+    try:
+        ev = dict(method="fmm", p=40, precond=precond)
+        prev = None
+        for m in (1, 2, 3, 8):
+            r = s.solve(tol=1e-14, max_iter=m, **ev)
+            print(f"{precond} max_iter {m}: iters {r['iters']}, estimate {r['rel_residual']}, "
+                  f"recomputed {r['true_rel_residual']}", flush=True)
+            assert not r["converged"] and r["iters"] == [m, m, m]
+            est, true = np.array(r["rel_residual"]), np.array(r["true_rel_residual"])
+            assert np.all(np.abs(est - true) <= 1e-6 + 1e-6 * true)
+            if prev is not None:
+                assert np.all(true <= prev * (1 + 1e-12))
+            prev = true
+        r = s.solve(tol=1e3, max_iter=50, **ev)
+        assert r["converged"] and r["iters"] == [0, 0, 0]
+    finally:
+        s.close()
